@@ -1,0 +1,330 @@
+#!/usr/bin/env python3
+"""Benchmark of the gfx950 word sort: one JSON line on stdout.
+
+A step is one whole sort (length histogram, bucket scatter and packing,
+odd-even chunk sort, every merge level) of the workload, with inputs already
+in HBM, through the graph-captured plan (the batched form).  Default
+workload: 64M words, 1M-word Zipf(1.1) vocabulary, lengths 1-24 (the
+largest single-GPU configuration).  Beside it the line carries the
+per-bucket-launch form on the same input, the roofline of the dominant
+kernel (HIP-event timed on its stream) and the CPU oracle's rate.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload c4|c3|c2|c1]
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "Mwords/s sorted + achieved HBM GB/s, batched vs per-bucket launch, bit-exact"
+HBM_PEAK_GBS = 8000.0
+WORKLOADS = {
+    "c1": (1, "35k words, 5k-word Zipf(1.0) vocabulary, lengths 1-16"),
+    "c2": (2, "250k words, 20k-word Zipf(1.0) vocabulary, lengths 1-20, odd-even chunks of 1024"),
+    "c3": (3, "4096 documents of 100-50k words (log-uniform), 50k-word Zipf(1.1) vocabulary, lengths 1-20"),
+    "c4": (4, "64M words, 1M-word Zipf(1.1) vocabulary, lengths 1-24"),
+}
+CSRC = [os.path.join(ROOT, "paper_1411_5283_amd", "csrc", f)
+        for f in ("sw_device.hpp", "sw_kernels.hpp", "sw_runtime.hip")]
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "hbm_traffic.json")
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def kernel_source_hash() -> str:
+    h = hashlib.sha256()
+    for p in CSRC:
+        with open(p, "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+# ------------------------------------------------------------------ byte model
+def element_bytes(cls: int) -> int:
+    """HBM bytes of one key element of a class: packed u64, or lanes + u32 index."""
+    return {0: 8, 1: 12, 2: 20, 3: 36}[cls]
+
+
+def class_of_len(L: int) -> int:
+    return 0 if L <= 4 else (1 if L <= 8 else (2 if L <= 16 else 3))
+
+
+def levels_for(n: int, T: int) -> int:
+    m, r = 0, T
+    while r < n:
+        r <<= 1
+        m += 1
+    return m
+
+
+def algorithmic_bytes(seg_sizes, tiles):
+    """Bytes each kernel family must move, per step, for the given segments.
+
+    seg_sizes: list of (length L, words n).  tiles[c] = (chunk-sort tile T).
+    chunk sort: read the element, write it back (or 4-byte index if the
+    segment is finished); merge level l < m: read + write the element, the
+    last level writes the 4-byte index instead.  Scatter: 4 B offset + L
+    chars in, one element out.  Histogram: 4 B offset per word."""
+    fam = {}
+
+    def add(k, v):
+        fam[k] = fam.get(k, 0) + v
+
+    for L, n in seg_sizes:
+        if n == 0:
+            continue
+        c = class_of_len(L)
+        e = element_bytes(c)
+        m = levels_for(n, tiles[c])
+        add("hist", 4 * n)
+        add("scatter_pack", (4 + L + e) * n)
+        add("sort_tiles_c%d" % c, (e + (e if m else 4)) * n)
+        for l in range(m):
+            add("merge_c%d" % c, (e + (e if l < m - 1 else 4)) * n)
+    return fam
+
+
+# ------------------------------------------------------------------ helpers
+def light_check(wl, perm: np.ndarray, boff: np.ndarray, n_docs: int) -> dict:
+    """Invariants of the result that hold at any size (no oracle): a
+    permutation per document, bucket sizes equal the length histogram, and the
+    key order on a sample of neighbouring pairs."""
+    offs = wl.offsets.astype(np.int64)
+    lens = offs[1:] - offs[:-1]
+    docs = wl.doc_offsets.astype(np.int64) if wl.doc_offsets is not None else np.array([0, wl.n])
+    boff = boff.reshape(n_docs, 34).astype(np.int64)
+    rng = np.random.default_rng(0)
+    ok = True
+    for d in range(n_docs) if n_docs <= 64 else rng.choice(n_docs, 64, replace=False):
+        lo, hi = int(docs[d]), int(docs[d + 1])
+        p = perm[lo:hi].astype(np.int64)
+        ok &= bool(p.size == 0 or (p.max() < hi - lo and np.all(np.bincount(p, minlength=hi - lo) == 1)))
+        h = np.bincount(lens[lo:hi], minlength=33)[:33]
+        ok &= bool(np.array_equal(np.diff(boff[d]), h) and boff[d][0] == 0)
+        if hi - lo > 1:
+            k = rng.integers(0, hi - lo - 1, size=min(200_000, hi - lo - 1))
+            a, b = p[k] + lo, p[k + 1] + lo
+            la, lb = lens[a], lens[b]
+            good = la < lb
+            same = la == lb
+            # compare bytes of equal-length neighbours one by one (sample only)
+            for j in range(int(lens.max(initial=0))):
+                ca = np.where(la > j, wl.chars[np.minimum(offs[a] + j, len(wl.chars) - 1)], 0)
+                cb = np.where(lb > j, wl.chars[np.minimum(offs[b] + j, len(wl.chars) - 1)], 0)
+                good |= same & (ca < cb)
+                same &= ca == cb
+            good |= same & (a < b)
+            ok &= bool(np.all(good))
+    return {"invariants": "permutation, bucket sizes, key order on sampled neighbours",
+            "ok": bool(ok)}
+
+
+def cpu_baseline(wl, budget_s: float = 12.0) -> dict:
+    """The oracle as it stands, single-threaded, on a bounded prefix sample."""
+    import oracle
+    oracle.build(force=False)
+    n = min(1 << 20, wl.n)
+    while True:
+        offs = np.ascontiguousarray(wl.offsets[:n + 1])
+        t0 = time.perf_counter()
+        oracle.oracle_def(wl.chars, offs)
+        dt = time.perf_counter() - t0
+        if dt * 2.2 > budget_s or n >= wl.n:
+            break
+        n = min(n * 2, wl.n)
+    res = {"value": n / dt / 1e6, "unit": "Mwords/s", "cores": 1, "kind": "oracle",
+           "sample": "oracle_def (qsort by length, bytes, index) on the first %d words of the "
+                     "same workload, one thread, %.2f s" % (n, dt)}
+    # the paper's own method on a paper-sized text (Table 1 analog)
+    from paper_1411_5283_amd import wordgen
+    c1 = wordgen.config(1)
+    t0 = time.perf_counter()
+    oracle.oracle_bubble(c1.chars, c1.offsets)
+    res["oracle_bubble_35k_words_s"] = time.perf_counter() - t0
+    res["paper_table1_dataset1_s"] = 6.639
+    res["paper_hardware"] = "Intel Core i7-3610QM 2.3 GHz (paper, Table 1)"
+    try:
+        with open("/proc/cpuinfo") as f:
+            res["host_cpu"] = next((l.split(":", 1)[1].strip() for l in f if l.startswith("model name")), "?")
+    except OSError:
+        pass
+    res["host_cores_available"] = len(os.sched_getaffinity(0))
+    return res
+
+
+def hbm_traffic(dominant_kernel: str):
+    """HBM bytes per launch of the dominant kernel from the committed
+    rocprofv3 counter summary, if it was taken on the current kernel source."""
+    try:
+        with open(TRAFFIC_FILE) as f:
+            t = json.load(f)
+    except (OSError, ValueError):
+        return None
+    if t.get("source_hash") != kernel_source_hash():
+        return None
+    k = t.get("kernels", {}).get(dominant_kernel)
+    return None if k is None else k.get("bytes_per_launch")
+
+
+# ------------------------------------------------------------------ main
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", default="c4", choices=sorted(WORKLOADS))
+    ap.add_argument("--plain-steps", type=int, default=2)
+    ap.add_argument("--profile-steps", type=int, default=3)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-check", action="store_true")
+    ap.add_argument("--no-plain", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py: this build runs on one GPU only; --gpus %d is not supported "
+              "(see DESIGN.md for how the sort would shard)" % args.gpus, file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import paper_1411_5283_amd as sw
+    from paper_1411_5283_amd import wordgen
+
+    cfg_no, desc = WORKLOADS[args.workload]
+    log("generating workload %s: %s" % (args.workload, desc))
+    t0 = time.perf_counter()
+    wl = wordgen.config(cfg_no)
+    log("generated %d words in %.1f s" % (wl.n, time.perf_counter() - t0))
+    if "chunk" in wl.meta:
+        sw.set_config(chunk=[wl.meta["chunk"]] * 4, variant=[0] * 4)
+    cfg = sw.get_config()
+    tiles = [sw.variant_tiles(c, cfg["variant"][c])[0] for c in range(4)]
+
+    torch.cuda.set_device(0)
+    dev = torch.device("cuda:0")
+    chars, offs, docs = sw.device_words(wl, dev)
+    n, nd = wl.n, wl.n_docs
+    perm = torch.empty(max(n, 1), dtype=torch.int32, device=dev)
+    boff = torch.empty(nd * 34, dtype=torch.int32, device=dev)
+    stream = torch.cuda.current_stream()
+    torch.cuda.synchronize()
+
+    # ---- batched form: graph-captured plan
+    plan = sw.Plan(n, nd, stream=stream)
+    run = lambda: plan.run(chars, offs, docs, nd, n, perm, boff)
+    for _ in range(args.warmup):
+        run()
+    plan.status()
+    torch.cuda.synchronize()
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    t0 = time.perf_counter()
+    ev0.record(stream)
+    for _ in range(args.steps):
+        run()
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    plan.status()
+    ms_step = ev0.elapsed_time(ev1) / args.steps
+    value = n / (ms_step / 1e3) / 1e6
+    log("plan: %.3f ms/step, %.1f Mwords/s (wall %.3f ms/step)" % (ms_step, value, wall * 1e3 / args.steps))
+
+    perm_h = sw.to_u32(perm)[:n]
+    boff_h = sw.to_u32(boff)
+    check = None if args.no_check else light_check(wl, perm_h, boff_h, nd)
+    if check:
+        log("check: %s" % check)
+
+    # ---- per-bucket-launch form on the same input
+    plain = None
+    ws = torch.empty(sw.sort_words_workspace_size(n, nd), dtype=torch.uint8, device=dev)
+    doc_t = docs if docs is not None else torch.tensor(np.array([0, n], np.uint32).view(np.int32), device=dev)
+    if not args.no_plain and args.plain_steps > 0:
+        perm2 = torch.empty_like(perm)
+        sw.sort_words_plain(chars, offs, doc_t, nd, perm2, boff, ws)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.plain_steps):
+            sw.sort_words_plain(chars, offs, doc_t, nd, perm2, boff, ws)
+        torch.cuda.synchronize()
+        pms = (time.perf_counter() - t0) * 1e3 / args.plain_steps
+        same = bool(torch.equal(perm2, perm))
+        plain = {"value": n / (pms / 1e3) / 1e6, "unit": "Mwords/s", "ms_per_step": pms,
+                 "same_result_as_batched": same,
+                 "form": "sort_words_plain: histogram read back, chunk sort and each merge level "
+                         "launched per (document, length) segment"}
+        log("plain: %.3f ms/step, %.1f Mwords/s, same=%s" % (pms, plain["value"], same))
+        del perm2
+
+    # ---- per-kernel timing of the same pass (eager launches, HIP events on this stream)
+    sw.profile_reset()
+    sw.profile_enable(True)
+    for _ in range(args.profile_steps):
+        if docs is None:
+            sw.sort_words_ex(chars, offs, n, perm, boff, ws, stream)
+        else:
+            sw.sort_words_batch(chars, offs, docs, nd, perm, boff, ws, stream)
+    torch.cuda.synchronize()
+    prof = sw.profile_read()
+    sw.profile_enable(False)
+    sw.sort_words_status(ws, stream)
+
+    # algorithmic bytes from the (document, length) segment sizes of the result
+    bo = boff_h[:nd * 34].reshape(nd, 34).astype(np.int64)
+    segs = [(L, int(c)) for row in np.diff(bo, axis=1) for L, c in enumerate(row)]
+    fam_bytes = algorithmic_bytes(segs, tiles)
+    kern = {}
+    for name, (launches, ms) in prof.items():
+        if launches == 0:
+            continue
+        per_step_ms = ms / args.profile_steps
+        b = fam_bytes.get(name)
+        kern[name] = {"launches_per_step": launches // args.profile_steps, "ms_per_step": per_step_ms,
+                      "avg_launch_us": ms / launches * 1e3}
+        if b is not None and per_step_ms > 0:
+            kern[name]["algorithmic_GBs"] = b / (per_step_ms / 1e3) / 1e9
+    dom = max(kern, key=lambda k: kern[k]["ms_per_step"])
+    dom_launches = kern[dom]["launches_per_step"]
+    achieved = kern[dom].get("algorithmic_GBs")
+    tsum = sum(v["ms_per_step"] for v in kern.values())
+    total_bytes = sum(fam_bytes.values())
+    traffic = hbm_traffic(dom)
+    roof = {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": (achieved / HBM_PEAK_GBS) if achieved else None,
+            "traffic": traffic,
+            "algorithmic_bytes_per_launch": (fam_bytes.get(dom, 0) / dom_launches) if dom_launches else None,
+            "avg_launch_us": kern[dom]["avg_launch_us"],
+            "kernels": kern,
+            "whole_pass_algorithmic_GB": total_bytes / 1e9,
+            "whole_pass_GBs_at_plan_time": total_bytes / (ms_step / 1e3) / 1e9,
+            "eager_kernel_sum_ms": tsum}
+
+    cpu = None if args.no_cpu_baseline else cpu_baseline(wl)
+    out = {
+        "metric": METRIC, "value": value, "unit": "Mwords/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": ms_step, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "u64", "data": "synthetic",
+        "config": {"workload": "%s: %s" % (args.workload, desc), "n_words": n, "n_docs": nd,
+                   "form": "graph-captured plan (batched, device-side segment scheduling)",
+                   "chunk": cfg["chunk"], "variant": cfg["variant"], "sort_tile": tiles},
+        "per_bucket_launch": plain,
+        "batched_over_plain": (value / plain["value"]) if plain else None,
+        "check": check,
+        "roofline": roof,
+        "cpu_baseline": cpu,
+        "kernel_source": kernel_source_hash(),
+    }
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,174 @@
+/*
+ * sort_words.h -- C ABI of the MI355X (gfx950) length-bucketed word sort.
+ *
+ * The operation (arXiv:1411.5283, "Parallelize Bubble and Merge Sort
+ * Algorithms Using MPI"):
+ *   - words go into one sub-array per character count, shorter words first,
+ *     each sub-array sized by the number of words of that length (Abstract;
+ *     section 3, "Pre-processing", phase 2);
+ *   - each sub-array is put in alphabetical order by bubble sort (section 2;
+ *     phase 3);
+ *   - in the parallel form a sub-array is cut into chunks, each chunk is
+ *     bubble-sorted on its own and the sorted chunks are merged (section 3.2;
+ *     section 4, "MPI Implementation"; section 5).
+ * On the GPU the chunk sort is odd-even transposition (the data-parallel form
+ * of bubble sort's adjacent compare-exchanges) on chunks held in registers,
+ * followed by merge-path merges, first in LDS and then across HBM.
+ *
+ * Result: the unique order of the word indices by the key
+ *     (length, bytes compared as unsigned, original index).
+ * Ties between equal words keep input order, as bubble sort (which never
+ * exchanges equal items) does.
+ *
+ * Conventions shared by every entry point
+ *   - Word i is chars[offsets[i] .. offsets[i+1]).  `offsets` has n+1 entries,
+ *     must not decrease, and offsets[0] need not be 0.  Total characters must
+ *     be below 2^32.  Any byte value is allowed.
+ *   - Lengths 0..SW_MAX_LEN are accepted.  A longer word is an error
+ *     (SW_ERR_WORD_TOO_LONG); offsets that decrease are SW_ERR_INVALID_ARG,
+ *     which takes precedence.  On any error the outputs are unspecified.
+ *   - out_perm[k] = index of the word at sorted position k (gather form).
+ *   - out_bucket_offsets[L] = number of words shorter than L, for
+ *     L = 0..SW_MAX_LEN+1 (SW_NUM_OFFSETS entries; the last one is n).  The
+ *     words of length L are out_perm[out_bucket_offsets[L] ..
+ *     out_bucket_offsets[L+1]).
+ *   - Pointers named chars/offsets/doc_offsets/out_* are DEVICE pointers.  The
+ *     caller owns every buffer; the library keeps no reference to one after
+ *     the work on the stream has completed.  Inputs and outputs must not
+ *     alias.  Outputs are fully overwritten.
+ *   - `stream` is a hipStream_t passed as void* (NULL = the null stream).
+ *   - Return values are sw_status codes.  sort_words_last_error() gives a
+ *     thread-local message for the last non-OK return of the calling thread.
+ */
+#ifndef SORT_WORDS_H
+#define SORT_WORDS_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define SW_MAX_LEN 32
+#define SW_NUM_OFFSETS (SW_MAX_LEN + 2)
+#define SW_NUM_CLASSES 4   /* key classes: lengths 0-4, 5-8, 9-16, 17-32 */
+
+typedef enum {
+    SW_OK = 0,
+    SW_ERR_INVALID_ARG = -1,   /* null pointer, bad size, offsets that decrease */
+    SW_ERR_WORD_TOO_LONG = -2, /* a word longer than SW_MAX_LEN bytes */
+    SW_ERR_WORKSPACE = -3,     /* workspace too small for the request */
+    SW_ERR_OOM = -4,           /* device allocation failed */
+    SW_ERR_HIP = -5            /* a HIP runtime call failed */
+} sw_status;
+
+/* Simple form.  Sorts n words on the null stream with a library-owned,
+ * cached workspace and returns when the result is ready, including errors the
+ * device detects.  Abstract and section 3 ("Pre-processing", phases 2-3).
+ *   chars     device, the characters (may be NULL when the total is 0)
+ *   offsets   device, n+1 entries
+ *   out_perm  device, n entries; out_bucket_offsets device, SW_NUM_OFFSETS */
+int sort_words(const uint8_t *chars, const uint32_t *offsets, uint32_t n,
+               uint32_t *out_perm, uint32_t *out_bucket_offsets);
+
+/* Bytes of device workspace that sort_words_ex / sort_words_batch /
+ * sort_words_plain need for up to max_words words in up to max_docs
+ * documents.  Returns 0 if the sizes are out of range. */
+size_t sort_words_workspace_size(uint32_t max_words, uint32_t max_docs);
+
+/* Asynchronous form of sort_words: enqueues the whole sort on `stream` and
+ * returns without waiting.  Argument errors found on the host are returned
+ * at once; errors found on the device are read with sort_words_status().
+ * `workspace` (device, caller-owned, at least
+ * sort_words_workspace_size(n, 1) bytes) must not be used by another call
+ * until this one has completed on the stream. */
+int sort_words_ex(const uint8_t *chars, const uint32_t *offsets, uint32_t n,
+                  uint32_t *out_perm, uint32_t *out_bucket_offsets,
+                  void *workspace, size_t workspace_bytes, void *stream);
+
+/* Batched form: n_docs independent documents sorted in one pass; every
+ * (document, length) pair is one segment (section 3.2: each sub-array is
+ * given to its own worker).
+ *   offsets      device, N+1 entries over all documents (N total words)
+ *   doc_offsets  device, n_docs+1 entries into the word list, doc_offsets[0]
+ *                must be 0 and entries must not decrease; document d holds
+ *                words doc_offsets[d] .. doc_offsets[d+1]
+ *   out_perm     device, N entries; positions doc_offsets[d] ..
+ *                doc_offsets[d+1] hold document d's result as
+ *                DOCUMENT-LOCAL word indices
+ *   out_bucket_offsets  device, n_docs * SW_NUM_OFFSETS entries, row d is
+ *                document d's bucket offsets (document-local)
+ * Asynchronous like sort_words_ex.  N is read on the device; N above the
+ * workspace capacity is SW_ERR_WORKSPACE (reported by sort_words_status). */
+int sort_words_batch(const uint8_t *chars, const uint32_t *offsets,
+                     const uint32_t *doc_offsets, uint32_t n_docs,
+                     uint32_t *out_perm, uint32_t *out_bucket_offsets,
+                     void *workspace, size_t workspace_bytes, void *stream);
+
+/* Per-bucket-launch form of sort_words_batch, the comparison baseline for
+ * the batched form: the length histogram is read back to the host, then the
+ * chunk sort and every merge level are launched separately for each
+ * (document, length) segment.  Same arguments and result as
+ * sort_words_batch; SYNCHRONOUS (returns device-detected errors). */
+int sort_words_plain(const uint8_t *chars, const uint32_t *offsets,
+                     const uint32_t *doc_offsets, uint32_t n_docs,
+                     uint32_t *out_perm, uint32_t *out_bucket_offsets,
+                     void *workspace, size_t workspace_bytes, void *stream);
+
+/* Waits for `stream`, then returns the status the device recorded in
+ * `workspace` for the last call enqueued with it (SW_OK or an error). */
+int sort_words_status(const void *workspace, void *stream);
+
+/* Persistent plan for repeated batched sorts (serving, benchmarks): owns its
+ * workspace and a captured HIP graph of the whole pass, so one run is one
+ * small descriptor kernel plus one hipGraphLaunch on the plan's stream.
+ *   sw_plan_create  capacity max_words / max_docs; `stream` as above;
+ *                   *out receives the plan (NULL on error)
+ *   sw_plan_run     same arguments and result as sort_words_batch
+ *                   (doc_offsets may be NULL: one document of n_words words);
+ *                   asynchronous; device errors via sw_plan_status
+ *   sw_plan_status  waits for the plan's stream, returns the device status
+ *   sw_plan_destroy frees the plan (waits for its stream first)
+ * A plan is not thread-safe; distinct plans may be used from distinct
+ * threads. */
+typedef struct sw_plan sw_plan;
+int sw_plan_create(uint32_t max_words, uint32_t max_docs, void *stream, sw_plan **out);
+int sw_plan_run(sw_plan *plan, const uint8_t *chars, const uint32_t *offsets,
+                const uint32_t *doc_offsets, uint32_t n_docs, uint32_t n_words,
+                uint32_t *out_perm, uint32_t *out_bucket_offsets);
+int sw_plan_status(sw_plan *plan);
+void sw_plan_destroy(sw_plan *plan);
+
+/* Tuning knobs, process-wide, read when work is enqueued (and when a plan's
+ * graph is captured).  chunk[c] is the odd-even chunk size of key class c
+ * (section 5: chunk size = array size / processors; here a power of two in
+ * [2, 1024]); variant[c] selects a compiled tile configuration of class c
+ * (0 .. sw_num_variants(c)-1).  Results never depend on these values. */
+typedef struct {
+    uint32_t chunk[SW_NUM_CLASSES];
+    uint32_t variant[SW_NUM_CLASSES];
+} sw_config;
+int sw_get_config(sw_config *out);
+int sw_set_config(const sw_config *cfg);
+/* Number of compiled variants of class c, and the chunk-sort tile (words per
+ * workgroup) and merge tile of a variant. */
+int sw_num_variants(int cls);
+int sw_variant_tiles(int cls, int variant, uint32_t *sort_tile, uint32_t *merge_tile);
+
+/* Kernel timing for measurement: while enabled, every kernel the library
+ * enqueues on the eager path (sort_words*, not plan graphs) is bracketed by
+ * HIP events on its own stream.  sw_profile_read waits for the recorded
+ * work and returns, per kernel family, the launch count and the summed
+ * device time in milliseconds; names are static strings. */
+int sw_profile_enable(int on);
+int sw_profile_reset(void);
+int sw_profile_read(int max_entries, const char **names, uint32_t *launches, double *ms);
+
+const char *sort_words_last_error(void);
+const char *sort_words_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* SORT_WORDS_H */

@@ -1,1 +1,272 @@
-"""MI355X-native length-bucketed word sort (arXiv:1411.5283's method on gfx950)."""
+"""MI355X-native length-bucketed word sort (arXiv:1411.5283's method on gfx950).
+
+Thin ctypes binding over ``libsortwords.so`` (built from ``csrc/`` by
+``build.py``).  Every step of the sort runs in the library's HIP kernels;
+this module only marshals arguments.  Device buffers are torch CUDA tensors
+(torch is used for device memory and streams only).  Word offsets and
+permutations are uint32 on the device and travel as int32 tensors holding
+the same bits.
+
+The C entry points and their semantics are declared in
+``include/sort_words.h``; the functions here carry the same names.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libsortwords.so")
+
+MAX_LEN = 32
+NUM_OFFSETS = MAX_LEN + 2
+NUM_CLASSES = 4
+
+OK, ERR_INVALID_ARG, ERR_WORD_TOO_LONG, ERR_WORKSPACE, ERR_OOM, ERR_HIP = 0, -1, -2, -3, -4, -5
+_STATUS_NAMES = {0: "SW_OK", -1: "SW_ERR_INVALID_ARG", -2: "SW_ERR_WORD_TOO_LONG",
+                 -3: "SW_ERR_WORKSPACE", -4: "SW_ERR_OOM", -5: "SW_ERR_HIP"}
+
+
+class SortWordsError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__("%s (%d): %s" % (_STATUS_NAMES.get(code, "?"), code, msg))
+        self.code = code
+
+
+class sw_config(ctypes.Structure):
+    _fields_ = [("chunk", ctypes.c_uint32 * NUM_CLASSES), ("variant", ctypes.c_uint32 * NUM_CLASSES)]
+
+
+_lib = None
+
+
+def lib() -> ctypes.CDLL:
+    """The HIP library; raises if it has not been built (there is no fallback)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError("libsortwords.so is not built; run __graft_entry__.build() or "
+                           "python -m paper_1411_5283_amd.build")
+    L = ctypes.CDLL(LIB_PATH)
+    vp, u32, i32, sz = ctypes.c_void_p, ctypes.c_uint32, ctypes.c_int, ctypes.c_size_t
+    sig = {
+        "sort_words": ([vp, vp, u32, vp, vp], i32),
+        "sort_words_workspace_size": ([u32, u32], sz),
+        "sort_words_ex": ([vp, vp, u32, vp, vp, vp, sz, vp], i32),
+        "sort_words_batch": ([vp, vp, vp, u32, vp, vp, vp, sz, vp], i32),
+        "sort_words_plain": ([vp, vp, vp, u32, vp, vp, vp, sz, vp], i32),
+        "sort_words_status": ([vp, vp], i32),
+        "sw_plan_create": ([u32, u32, vp, ctypes.POINTER(vp)], i32),
+        "sw_plan_run": ([vp, vp, vp, vp, u32, u32, vp, vp], i32),
+        "sw_plan_status": ([vp], i32),
+        "sw_plan_destroy": ([vp], None),
+        "sw_get_config": ([ctypes.POINTER(sw_config)], i32),
+        "sw_set_config": ([ctypes.POINTER(sw_config)], i32),
+        "sw_num_variants": ([i32], i32),
+        "sw_variant_tiles": ([i32, i32, ctypes.POINTER(u32), ctypes.POINTER(u32)], i32),
+        "sw_profile_enable": ([i32], i32),
+        "sw_profile_reset": ([], i32),
+        "sw_profile_read": ([i32, ctypes.POINTER(ctypes.c_char_p), ctypes.POINTER(u32),
+                             ctypes.POINTER(ctypes.c_double)], i32),
+        "sort_words_last_error": ([], ctypes.c_char_p),
+        "sort_words_version": ([], ctypes.c_char_p),
+    }
+    for name, (args, res) in sig.items():
+        f = getattr(L, name)
+        f.argtypes = args
+        f.restype = res
+    _lib = L
+    return L
+
+
+EXPORTED = ("sort_words", "sort_words_workspace_size", "sort_words_ex", "sort_words_batch",
+            "sort_words_plain", "sort_words_status", "sw_plan_create", "sw_plan_run",
+            "sw_plan_status", "sw_plan_destroy", "sw_get_config", "sw_set_config",
+            "sw_num_variants", "sw_variant_tiles", "sw_profile_enable", "sw_profile_reset",
+            "sw_profile_read", "sort_words_last_error", "sort_words_version")
+
+
+def _check(rc: int) -> int:
+    if rc != OK:
+        raise SortWordsError(rc, lib().sort_words_last_error().decode())
+    return rc
+
+
+def _ptr(t):
+    if t is None:
+        return None
+    p = t.data_ptr()
+    return p or None
+
+
+def _stream(stream):
+    if stream is None:
+        import torch
+        return torch.cuda.current_stream().cuda_stream or None
+    if isinstance(stream, int):
+        return stream or None
+    return stream.cuda_stream or None
+
+
+# ------------------------------------------------------------------ entry points
+def sort_words(chars, offsets, n, out_perm, out_bucket_offsets) -> int:
+    """Synchronous sort on the null stream (library-owned workspace)."""
+    return _check(lib().sort_words(_ptr(chars), _ptr(offsets), int(n), _ptr(out_perm),
+                                   _ptr(out_bucket_offsets)))
+
+
+def sort_words_workspace_size(max_words: int, max_docs: int = 1) -> int:
+    return int(lib().sort_words_workspace_size(int(max_words), int(max_docs)))
+
+
+def sort_words_ex(chars, offsets, n, out_perm, out_bucket_offsets, workspace, stream=None) -> int:
+    return _check(lib().sort_words_ex(_ptr(chars), _ptr(offsets), int(n), _ptr(out_perm),
+                                      _ptr(out_bucket_offsets), _ptr(workspace),
+                                      workspace.numel() * workspace.element_size(), _stream(stream)))
+
+
+def sort_words_batch(chars, offsets, doc_offsets, n_docs, out_perm, out_bucket_offsets, workspace,
+                     stream=None) -> int:
+    return _check(lib().sort_words_batch(_ptr(chars), _ptr(offsets), _ptr(doc_offsets), int(n_docs),
+                                         _ptr(out_perm), _ptr(out_bucket_offsets), _ptr(workspace),
+                                         workspace.numel() * workspace.element_size(),
+                                         _stream(stream)))
+
+
+def sort_words_plain(chars, offsets, doc_offsets, n_docs, out_perm, out_bucket_offsets, workspace,
+                     stream=None) -> int:
+    return _check(lib().sort_words_plain(_ptr(chars), _ptr(offsets), _ptr(doc_offsets), int(n_docs),
+                                         _ptr(out_perm), _ptr(out_bucket_offsets), _ptr(workspace),
+                                         workspace.numel() * workspace.element_size(),
+                                         _stream(stream)))
+
+
+def sort_words_status(workspace, stream=None) -> int:
+    """Device status of the last call enqueued with this workspace (raises on error)."""
+    return _check(lib().sort_words_status(_ptr(workspace), _stream(stream)))
+
+
+def sort_words_status_code(workspace, stream=None) -> int:
+    return int(lib().sort_words_status(_ptr(workspace), _stream(stream)))
+
+
+class Plan:
+    """Graph-captured persistent plan (sw_plan_*)."""
+
+    def __init__(self, max_words: int, max_docs: int = 1, stream=None):
+        h = ctypes.c_void_p()
+        s = None if stream is None else _stream(stream)
+        _check(lib().sw_plan_create(int(max_words), int(max_docs), s, ctypes.byref(h)))
+        self._h = h
+        self.max_words, self.max_docs = int(max_words), int(max_docs)
+
+    def run(self, chars, offsets, doc_offsets, n_docs, n_words, out_perm, out_bucket_offsets) -> int:
+        return _check(lib().sw_plan_run(self._h, _ptr(chars), _ptr(offsets), _ptr(doc_offsets),
+                                        int(n_docs), int(n_words), _ptr(out_perm),
+                                        _ptr(out_bucket_offsets)))
+
+    def status(self) -> int:
+        return _check(lib().sw_plan_status(self._h))
+
+    def status_code(self) -> int:
+        return int(lib().sw_plan_status(self._h))
+
+    def close(self):
+        if self._h:
+            lib().sw_plan_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def get_config() -> dict:
+    c = sw_config()
+    _check(lib().sw_get_config(ctypes.byref(c)))
+    return {"chunk": list(c.chunk), "variant": list(c.variant)}
+
+
+def set_config(chunk=None, variant=None) -> dict:
+    cur = get_config()
+    c = sw_config()
+    for k in range(NUM_CLASSES):
+        c.chunk[k] = int((chunk if chunk is not None else cur["chunk"])[k])
+        c.variant[k] = int((variant if variant is not None else cur["variant"])[k])
+    _check(lib().sw_set_config(ctypes.byref(c)))
+    return get_config()
+
+
+def num_variants(cls: int) -> int:
+    return int(lib().sw_num_variants(int(cls)))
+
+
+def variant_tiles(cls: int, variant: int) -> tuple[int, int]:
+    a, b = ctypes.c_uint32(), ctypes.c_uint32()
+    _check(lib().sw_variant_tiles(int(cls), int(variant), ctypes.byref(a), ctypes.byref(b)))
+    return int(a.value), int(b.value)
+
+
+def profile_enable(on: bool = True):
+    _check(lib().sw_profile_enable(1 if on else 0))
+
+
+def profile_reset():
+    _check(lib().sw_profile_reset())
+
+
+def profile_read() -> dict:
+    """{kernel family: (launches, milliseconds)} since the last reset."""
+    n = 64
+    names = (ctypes.c_char_p * n)()
+    launches = (ctypes.c_uint32 * n)()
+    ms = (ctypes.c_double * n)()
+    k = lib().sw_profile_read(n, names, launches, ms)
+    if k < 0:
+        _check(k)
+    return {names[i].decode(): (int(launches[i]), float(ms[i])) for i in range(k)}
+
+
+def version() -> str:
+    return lib().sort_words_version().decode()
+
+
+# ------------------------------------------------------------------ host helpers
+def device_words(wl, device="cuda"):
+    """Copy a wordgen.WordList to the device: (chars u8, offsets i32[n+1], doc_offsets or None)."""
+    import torch
+    chars = torch.from_numpy(np.ascontiguousarray(wl.chars)).to(device)
+    offsets = torch.from_numpy(np.ascontiguousarray(wl.offsets, dtype=np.uint32).view(np.int32)).to(device)
+    docs = None
+    if wl.doc_offsets is not None:
+        docs = torch.from_numpy(np.ascontiguousarray(wl.doc_offsets, dtype=np.uint32).view(np.int32)).to(device)
+    return chars, offsets, docs
+
+
+def to_u32(t) -> np.ndarray:
+    return t.cpu().numpy().view(np.uint32)
+
+
+def sort_wordlist(wl, device="cuda"):
+    """Sort a host word list on the GPU (single document: sort_words; batch: sort_words_batch).
+
+    Returns numpy (perm uint32[n], bucket_offsets uint32[34] or [n_docs, 34])."""
+    import torch
+    chars, offsets, docs = device_words(wl, device)
+    n = wl.n
+    perm = torch.empty(max(n, 1), dtype=torch.int32, device=device)
+    if docs is None:
+        boff = torch.empty(NUM_OFFSETS, dtype=torch.int32, device=device)
+        sort_words(chars, offsets, n, perm, boff)
+        return to_u32(perm)[:n], to_u32(boff)
+    nd = wl.n_docs
+    boff = torch.empty(max(nd, 1) * NUM_OFFSETS, dtype=torch.int32, device=device)
+    ws = torch.empty(sort_words_workspace_size(n, nd), dtype=torch.uint8, device=device)
+    sort_words_batch(chars, offsets, docs, nd, perm, boff, ws)
+    sort_words_status(ws)
+    return to_u32(perm)[:n], to_u32(boff)[:nd * NUM_OFFSETS].reshape(nd, NUM_OFFSETS)

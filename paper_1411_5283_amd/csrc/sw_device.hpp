@@ -1,0 +1,333 @@
+// sw_device.hpp -- device-side types and helpers of the gfx950 word sort.
+//
+// Key representation.  Words of one length L are compared as L bytes,
+// unsigned, most significant first (the "alphabetic" order of section 3's
+// phase 3, read as byte order).  A word is packed into big-endian 64-bit
+// lanes, zero padded: for two words of the SAME length, comparing the lanes
+// as unsigned integers, most significant lane first, is the same as
+// comparing the bytes.  The original index breaks ties, which is the order
+// bubble sort leaves equal words in, so every key is distinct and the sort
+// has exactly one correct result.
+//
+// Key classes by length (fixed-width rows, the paper's 3-D char array):
+//   class 0: L 0..4    one u64 = (4 key bytes << 32) | index
+//   class 1: L 5..8    one lane + u32 index
+//   class 2: L 9..16   two lanes + u32 index
+//   class 3: L 17..32  four lanes + u32 index
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace sw {
+
+constexpr int kMaxLen = 32;
+constexpr int kNB = kMaxLen + 1;        // buckets L = 0..32
+constexpr int kNOff = kMaxLen + 2;      // bucket offsets per document
+constexpr int kNClass = 4;
+constexpr int kMaxLev = 24;             // merge levels a segment may need
+constexpr uint32_t kWordsPerBlock = 4096;
+constexpr uint32_t kSegsPerBlock = 4096;
+constexpr int kNKeys = kNClass * kMaxLev + 1;   // segment-order keys (+1: empty)
+constexpr int kKeyBits = 7;
+static_assert(kNKeys <= (1 << kKeyBits), "segment key bits");
+
+// device status bits
+enum : uint32_t { ST_INVALID = 1u, ST_TOO_LONG = 2u, ST_WORKSPACE = 4u };
+
+__host__ __device__ inline int class_of_len(uint32_t L) {
+  return L <= 4 ? 0 : (L <= 8 ? 1 : (L <= 16 ? 2 : 3));
+}
+// lanes stored per class (class 0 is packed with the index)
+__host__ __device__ constexpr int lanes_of_class(int c) { return c == 0 ? 0 : (c == 3 ? 4 : c); }
+
+// Merge levels a segment of n items needs when tiles of T items come out of
+// the chunk sort already sorted: runs double each level until one run holds n.
+__host__ __device__ inline uint32_t levels_for(uint32_t n, uint32_t T) {
+  uint32_t m = 0;
+  uint64_t r = T;
+  while (r < n) {
+    r <<= 1;
+    ++m;
+  }
+  return m;
+}
+
+// ---------------------------------------------------------------- run state
+struct RunDesc {
+  const uint8_t* chars;
+  const uint32_t* offsets;
+  const uint32_t* doc_offsets;   // null: one document of n_words words
+  uint32_t* out_perm;
+  uint32_t* out_boff;
+  uint32_t n_words;              // used when doc_offsets is null
+  uint32_t n_docs;
+};
+
+struct Header {
+  RunDesc d;
+  uint32_t status;               // ST_* bits
+  uint32_t abort;                // nonzero: later kernels do nothing
+  uint32_t n_docs;               // documents in this run
+  uint32_t n_words;
+  uint32_t n_blocks;             // word blocks (never spanning documents)
+  uint32_t n_segs;               // n_docs * kNB
+  uint32_t n_segblocks;
+  uint32_t cls_start[kNClass + 1];         // class sublists of the ordered segments
+  uint32_t active[kNClass][kMaxLev];       // segments of a class with more levels than l
+  uint32_t sort_tiles[kNClass];
+};
+
+struct KeyBuf {
+  uint64_t* k[4];
+  uint32_t* idx;
+};
+
+// Workspace view handed to every kernel (by value).
+struct Ws {
+  Header* h;
+  uint32_t* doc_off;    // [Dmax+1]  word offset of each document
+  uint32_t* doc_blk;    // [Dmax+1]  first word block of each document
+  uint32_t* cnt;        // [kNB][Bmax+1]  per-block length counts, then their prefix
+  uint32_t* seg_n;      // [Dmax*kNB]  words of (document, length)
+  uint32_t* seg_base;   // [Dmax*kNB]  first output position of the segment
+  uint32_t* segcnt;     // [kNKeys][SBmax+1]
+  uint32_t* sorted;     // [Smax]      non-empty segments by (class, levels desc)
+  uint32_t* st;         // [Smax+kNClass]  chunk-sort tile prefix per class
+  uint32_t* mt;         // [Smax+kNClass]  merge tile prefix per class
+  KeyBuf a;             // key buffer 0 (scatter output, chunk sort in place)
+  KeyBuf b;             // key buffer 1 (ping-pong for merge levels)
+  uint32_t Nmax, Dmax, Bmax, Smax, SBmax;
+  uint32_t T[kNClass];      // chunk-sort tile (items per workgroup)
+  uint32_t P[kNClass];      // merge tile
+  uint32_t chunk[kNClass];  // odd-even chunk size
+};
+
+// A workgroup's work: from the device-side segment lists, or one segment given
+// directly by the host (the per-bucket-launch form).
+struct TileWork {
+  uint32_t direct;
+  uint32_t base, n, m;
+};
+
+// ---------------------------------------------------------------- wave tools
+__device__ inline uint32_t lanes_below(uint64_t m) {
+  return __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
+}
+
+// Lanes whose BITS-bit key equals this lane's (valid lanes only).
+template <int BITS>
+__device__ inline uint64_t match_mask(uint32_t key, bool valid) {
+  uint64_t m = __ballot(valid);
+#pragma unroll
+  for (int b = 0; b < BITS; ++b) {
+    const bool bit = (key >> b) & 1u;
+    const uint64_t bb = __ballot(bit);
+    m &= bit ? bb : ~bb;
+  }
+  return m;
+}
+
+__device__ inline uint32_t wave_incl_scan(uint32_t v) {
+  const int lane = __lane_id();
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    const uint32_t t = __shfl_up(v, o);
+    if (lane >= o) v += t;
+  }
+  return v;
+}
+
+// Exclusive scan over the workgroup; s_tmp holds NT/64 words.  Ends with a
+// barrier, so s_tmp may be reused at once.
+template <int NT>
+__device__ inline uint32_t block_excl_scan(uint32_t v, uint32_t* s_tmp, uint32_t& total) {
+  constexpr int NW = NT / 64;
+  const int lane = __lane_id();
+  const int wave = threadIdx.x >> 6;
+  const uint32_t incl = wave_incl_scan(v);
+  if (lane == 63) s_tmp[wave] = incl;
+  __syncthreads();
+  if (wave == 0) {
+    uint32_t x = lane < NW ? s_tmp[lane] : 0u;
+    x = wave_incl_scan(x);
+    if (lane < NW) s_tmp[lane] = x;
+  }
+  __syncthreads();
+  const uint32_t before = wave ? s_tmp[wave - 1] : 0u;
+  total = s_tmp[NW - 1];
+  __syncthreads();
+  return before + incl - v;
+}
+
+// Largest k in [0, count) with prefix[k] <= t, for non-decreasing prefix with
+// prefix[0] <= t.  One wave, 64 probes per round.
+__device__ inline uint32_t wave_find(const uint32_t* prefix, uint32_t count, uint32_t t) {
+  const uint32_t lane = __lane_id();
+  uint32_t lo = 0, hi = count;
+  while (hi - lo > 1) {
+    const uint32_t step = (hi - lo + 63) >> 6;
+    const uint32_t pos = lo + lane * step;
+    const bool p = pos < hi && prefix[pos] <= t;
+    const uint32_t c = max((uint32_t)__popcll(__ballot(p)), 1u);   // prefix[lo] <= t holds
+    lo = lo + (c - 1) * step;
+    hi = min(lo + step, hi);
+  }
+  return lo;
+}
+
+// ---------------------------------------------------------------- keys
+template <int NL>
+struct Key {
+  uint64_t k[NL];
+  uint32_t idx;
+};
+template <>
+struct Key<0> {
+  uint64_t k;
+};
+
+template <int NL>
+__device__ inline bool key_less(const Key<NL>& a, const Key<NL>& b) {
+  bool lt = a.idx < b.idx;
+#pragma unroll
+  for (int q = NL - 1; q >= 0; --q) lt = (a.k[q] == b.k[q]) ? lt : (a.k[q] < b.k[q]);
+  return lt;
+}
+template <>
+__device__ inline bool key_less<0>(const Key<0>& a, const Key<0>& b) {
+  return a.k < b.k;
+}
+
+template <int NL>
+__device__ inline Key<NL> key_sentinel() {
+  Key<NL> s;
+#pragma unroll
+  for (int q = 0; q < NL; ++q) s.k[q] = ~0ull;
+  s.idx = ~0u;
+  return s;
+}
+template <>
+__device__ inline Key<0> key_sentinel<0>() {
+  Key<0> s;
+  s.k = ~0ull;
+  return s;
+}
+
+template <int NL>
+__device__ inline uint32_t key_index(const Key<NL>& v) { return v.idx; }
+template <>
+__device__ inline uint32_t key_index<0>(const Key<0>& v) { return (uint32_t)v.k; }
+
+template <int NL>
+__device__ inline Key<NL> gload(const KeyBuf& b, size_t p) {
+  Key<NL> v;
+#pragma unroll
+  for (int q = 0; q < NL; ++q) v.k[q] = b.k[q][p];
+  v.idx = b.idx[p];
+  return v;
+}
+template <>
+__device__ inline Key<0> gload<0>(const KeyBuf& b, size_t p) {
+  Key<0> v;
+  v.k = b.k[0][p];
+  return v;
+}
+
+template <int NL>
+__device__ inline void gstore(const KeyBuf& b, size_t p, const Key<NL>& v) {
+#pragma unroll
+  for (int q = 0; q < NL; ++q) b.k[q][p] = v.k[q];
+  b.idx[p] = v.idx;
+}
+template <>
+__device__ inline void gstore<0>(const KeyBuf& b, size_t p, const Key<0>& v) {
+  b.k[0][p] = v.k;
+}
+
+template <int NL>
+__device__ inline Key<NL> key_select(bool c, const Key<NL>& x, const Key<NL>& y) {
+  Key<NL> r;
+#pragma unroll
+  for (int q = 0; q < NL; ++q) r.k[q] = c ? x.k[q] : y.k[q];
+  r.idx = c ? x.idx : y.idx;
+  return r;
+}
+template <>
+__device__ inline Key<0> key_select<0>(bool c, const Key<0>& x, const Key<0>& y) {
+  Key<0> r;
+  r.k = c ? x.k : y.k;
+  return r;
+}
+
+__device__ inline uint64_t shfl64(uint64_t v, int src) {
+  const uint32_t lo = __shfl((uint32_t)v, src);
+  const uint32_t hi = __shfl((uint32_t)(v >> 32), src);
+  return ((uint64_t)hi << 32) | lo;
+}
+
+template <int NL>
+__device__ inline Key<NL> key_shfl(const Key<NL>& v, int src) {
+  Key<NL> r;
+#pragma unroll
+  for (int q = 0; q < NL; ++q) r.k[q] = shfl64(v.k[q], src);
+  r.idx = __shfl(v.idx, src);
+  return r;
+}
+template <>
+__device__ inline Key<0> key_shfl<0>(const Key<0>& v, int src) {
+  Key<0> r;
+  r.k = shfl64(v.k, src);
+  return r;
+}
+
+// Compare-exchange: afterwards a <= b.  Returns whether they were exchanged.
+template <int NL>
+__device__ inline bool cmp_xchg(Key<NL>& a, Key<NL>& b) {
+  const bool sw = key_less(b, a);
+  const Key<NL> lo = key_select(sw, b, a);
+  const Key<NL> hi = key_select(sw, a, b);
+  a = lo;
+  b = hi;
+  return sw;
+}
+
+// ---------------------------------------------------------------- LDS tile
+// Structure-of-arrays tile of CAP keys.  One pad slot every 16 items keeps a
+// thread's 16 consecutive items (blocked layout) off its neighbours' banks.
+template <int NL, int CAP>
+struct LdsTile {
+  static constexpr int kPadded = CAP + CAP / 16;
+  static constexpr int kLanes = NL ? NL : 1;
+  uint64_t k[kLanes][kPadded];
+  uint32_t idx[NL ? kPadded : 1];
+
+  __device__ static int pos(int i) { return i + (i >> 4); }
+  __device__ Key<NL> get(int i) const {
+    const int p = pos(i);
+    Key<NL> v;
+#pragma unroll
+    for (int q = 0; q < NL; ++q) v.k[q] = k[q][p];
+    v.idx = idx[p];
+    return v;
+  }
+  __device__ void put(int i, const Key<NL>& v) {
+    const int p = pos(i);
+#pragma unroll
+    for (int q = 0; q < NL; ++q) k[q][p] = v.k[q];
+    idx[p] = v.idx;
+  }
+};
+template <int CAP>
+struct LdsTile<0, CAP> {
+  static constexpr int kPadded = CAP + CAP / 16;
+  uint64_t k[kPadded];
+  __device__ static int pos(int i) { return i + (i >> 4); }
+  __device__ Key<0> get(int i) const {
+    Key<0> v;
+    v.k = k[pos(i)];
+    return v;
+  }
+  __device__ void put(int i, const Key<0>& v) { k[pos(i)] = v.k; }
+};
+
+}  // namespace sw

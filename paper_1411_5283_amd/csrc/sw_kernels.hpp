@@ -1,0 +1,732 @@
+// sw_kernels.hpp -- HIP kernels of the gfx950 word sort.
+//
+// One pass (arXiv:1411.5283, section 3 "Pre-processing" phases 2-3, sections
+// 3.2 and 4 for the chunked parallel form):
+//   k_begin        run descriptor into the workspace, status cleared
+//   k_doc_plan     documents -> word blocks (a block never spans documents)
+//   k_hist         per-block length histogram; offsets validated
+//   k_scan_rows    prefix of the histogram over blocks, per length
+//   k_segments     per (document, length) segment: size and first position;
+//                  the document's bucket offsets
+//   k_seg_count / k_scan_rows / k_seg_scatter
+//                  segments ordered by (key class, merge levels descending) so
+//                  that the segments still merging at level l are a prefix
+//   k_tile_prefix  per class: tiles of the chunk sort and of a merge level
+//   k_scatter_pack stable distribution of the words into their segment, as
+//                  big-endian key lanes + index (the sub-arrays of phase 2)
+//   k_sort_tiles   per tile: odd-even transposition on chunks (bubble sort's
+//                  parallel form), then merge-path merges in LDS up to the tile
+//   k_merge        one merge-path level over HBM; the last level of a segment
+//                  writes the output permutation
+// Every kernel after k_begin reads the run from the workspace, so the same
+// sequence runs eagerly or as one captured HIP graph.
+#pragma once
+#include "sw_device.hpp"
+
+namespace sw {
+
+
+// ---------------------------------------------------------------- k_begin
+__global__ void k_begin(Ws w, RunDesc d) {
+  if (threadIdx.x == 0) {
+    Header* h = w.h;
+    h->d = d;
+    h->status = 0;
+    h->abort = 0;
+    h->n_docs = d.doc_offsets ? d.n_docs : 1u;
+    h->n_words = 0;
+    h->n_blocks = 0;
+    h->n_segs = 0;
+    h->n_segblocks = 0;
+  }
+}
+
+// ---------------------------------------------------------------- k_doc_plan
+// One workgroup.  Copies (or synthesizes) the document offsets, validates
+// them, and gives every document ceil(words / kWordsPerBlock) word blocks.
+template <int NT>
+__global__ __launch_bounds__(NT) void k_doc_plan(Ws w) {
+  __shared__ uint32_t s_tmp[NT / 64];
+  __shared__ uint32_t s_bad;
+  Header* h = w.h;
+  const RunDesc d = h->d;
+  const uint32_t D = h->n_docs;
+  if (threadIdx.x == 0) s_bad = 0;
+  __syncthreads();
+  uint32_t carry = 0;
+  uint32_t bad = 0;
+  for (uint32_t base = 0; base <= D; base += NT) {
+    const uint32_t j = base + threadIdx.x;
+    uint32_t nb = 0;
+    if (j <= D) {
+      const uint32_t s = d.doc_offsets ? d.doc_offsets[j] : (j == 0 ? 0u : d.n_words);
+      w.doc_off[j] = s;
+      if (j == 0 && s != 0) bad |= ST_INVALID;
+      if (j > 0) {
+        const uint32_t prev = d.doc_offsets ? d.doc_offsets[j - 1] : 0u;
+        if (s < prev)
+          bad |= ST_INVALID;
+        else
+          nb = (s - prev + kWordsPerBlock - 1) / kWordsPerBlock;
+      }
+      if (j == D && s > w.Nmax) bad |= ST_WORKSPACE;
+    }
+    uint32_t total;
+    const uint32_t ex = block_excl_scan<NT>(nb, s_tmp, total);
+    if (j <= D) w.doc_blk[j] = carry + ex + nb;   // blocks of documents 0..j-1
+    carry += total;
+  }
+  if (bad) atomicOr(&s_bad, bad);
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    if (s_bad) {
+      atomicOr(&h->status, s_bad);
+      atomicOr(&h->abort, 1u);
+    } else {
+      h->n_words = w.doc_off[D];
+      h->n_blocks = carry;
+      h->n_segs = D * (uint32_t)kNB;
+      h->n_segblocks = (D * (uint32_t)kNB + kSegsPerBlock - 1) / kSegsPerBlock;
+    }
+  }
+}
+
+// Word range of word block b: its document and [ws, we).
+struct BlockRange {
+  uint32_t doc, ws, we;
+};
+template <int NT>
+__device__ inline BlockRange block_range(const Ws& w, uint32_t b, uint32_t D, uint32_t* s_doc) {
+  if (threadIdx.x < 64) {
+    const uint32_t dd = wave_find(w.doc_blk, D + 1, b);
+    if (threadIdx.x == 0) *s_doc = dd;
+  }
+  __syncthreads();
+  BlockRange r;
+  r.doc = *s_doc;
+  r.ws = w.doc_off[r.doc] + (b - w.doc_blk[r.doc]) * kWordsPerBlock;
+  r.we = min(r.ws + kWordsPerBlock, w.doc_off[r.doc + 1]);
+  return r;
+}
+
+// ---------------------------------------------------------------- k_hist
+// Length histogram per word block (phase 2: sub-array sizes are the counts
+// of words of each length).  Also validates the offsets.
+template <int NT>
+__global__ __launch_bounds__(NT) void k_hist(Ws w) {
+  __shared__ uint32_t s_cnt[kNB];
+  __shared__ uint32_t s_doc;
+  Header* h = w.h;
+  if (h->abort) return;
+  const uint32_t nblk = h->n_blocks;
+  const uint32_t D = h->n_docs;
+  const uint32_t N = h->n_words;
+  const uint32_t* off = h->d.offsets;
+  const bool no_chars = h->d.chars == nullptr;
+  const uint32_t off_lo = off[0], off_hi = off[N];
+  const uint32_t rs = w.Bmax + 1;
+  uint32_t flags = 0;
+  for (uint32_t b = blockIdx.x; b < nblk; b += gridDim.x) {
+    if (threadIdx.x < kNB) s_cnt[threadIdx.x] = 0;
+    const BlockRange r = block_range<NT>(w, b, D, &s_doc);   // has a barrier
+    for (uint32_t i = r.ws + threadIdx.x; i < r.we; i += NT) {
+      const uint32_t a = off[i], e = off[i + 1];
+      uint32_t L = e - a;
+      if (e < a || a < off_lo || e > off_hi || (no_chars && e != a)) {
+        flags |= ST_INVALID;
+        L = 0;
+      } else if (L > (uint32_t)kMaxLen) {
+        flags |= ST_TOO_LONG;
+        L = kMaxLen;
+      }
+      atomicAdd(&s_cnt[L], 1u);
+    }
+    __syncthreads();
+    if (threadIdx.x < kNB) w.cnt[threadIdx.x * rs + b] = s_cnt[threadIdx.x];
+    __syncthreads();
+  }
+  if (__any(flags != 0)) {
+    // one atomic per wave
+    uint32_t f = flags;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) f |= __shfl_xor(f, o);
+    if (__lane_id() == 0 && f) {
+      atomicOr(&h->status, f);
+      atomicOr(&h->abort, 1u);
+    }
+  }
+}
+
+// ---------------------------------------------------------------- k_scan_rows
+// Exclusive prefix of each row over its first *ncols entries; the row total
+// goes to entry *ncols.  One workgroup per row (grid-stride over rows).
+template <int NT, int IPT>
+__global__ __launch_bounds__(NT) void k_scan_rows(Ws w, uint32_t* rows, uint32_t nrows,
+                                                   uint32_t stride, int which) {
+  __shared__ uint32_t s_tmp[NT / 64];
+  const Header* h = w.h;
+  if (h->abort) return;
+  const uint32_t ncols = which == 0 ? h->n_blocks : h->n_segblocks;
+  for (uint32_t r = blockIdx.x; r < nrows; r += gridDim.x) {
+    uint32_t* row = rows + (size_t)r * stride;
+    uint32_t carry = 0;
+    for (uint32_t base = 0; base < ncols; base += NT * IPT) {
+      uint32_t v[IPT];
+      uint32_t sum = 0;
+#pragma unroll
+      for (int k = 0; k < IPT; ++k) {
+        const uint32_t i = base + threadIdx.x * IPT + k;
+        v[k] = i < ncols ? row[i] : 0u;
+        sum += v[k];
+      }
+      uint32_t total;
+      uint32_t run = carry + block_excl_scan<NT>(sum, s_tmp, total);
+#pragma unroll
+      for (int k = 0; k < IPT; ++k) {
+        const uint32_t i = base + threadIdx.x * IPT + k;
+        if (i < ncols) row[i] = run;
+        run += v[k];
+      }
+      carry += total;
+    }
+    if (threadIdx.x == 0) row[ncols] = carry;
+    __syncthreads();
+  }
+}
+
+// ---------------------------------------------------------------- k_segments
+// One wave per document: counts of its 33 lengths, their exclusive prefix
+// (the document's bucket offsets, an output), and the segment table.
+template <int NT>
+__global__ __launch_bounds__(NT) void k_segments(Ws w) {
+  Header* h = w.h;
+  if (h->abort) return;
+  const uint32_t D = h->n_docs;
+  const uint32_t rs = w.Bmax + 1;
+  const uint32_t lane = __lane_id();
+  const uint32_t waves = gridDim.x * (NT / 64);
+  uint32_t* out_boff = h->d.out_boff;
+  for (uint32_t dd = blockIdx.x * (NT / 64) + (threadIdx.x >> 6); dd < D; dd += waves) {
+    const uint32_t b0 = w.doc_blk[dd], b1 = w.doc_blk[dd + 1];
+    const uint32_t c = lane < (uint32_t)kNB ? w.cnt[lane * rs + b1] - w.cnt[lane * rs + b0] : 0u;
+    const uint32_t ex = wave_incl_scan(c) - c;
+    if (lane < (uint32_t)kNOff) out_boff[(size_t)dd * kNOff + lane] = ex;
+    if (lane < (uint32_t)kNB) {
+      w.seg_n[dd * kNB + lane] = c;
+      w.seg_base[dd * kNB + lane] = w.doc_off[dd] + ex;
+    }
+  }
+}
+
+// Segment order key: (class, merge levels descending); empty segments last.
+__device__ inline uint32_t seg_key(const Ws& w, uint32_t s) {
+  const uint32_t n = w.seg_n[s];
+  if (n == 0) return kNKeys - 1;
+  const int c = class_of_len(s % kNB);
+  const uint32_t m = levels_for(n, w.T[c]);
+  return (uint32_t)c * kMaxLev + (kMaxLev - 1 - m);
+}
+
+template <int NT>
+__global__ __launch_bounds__(NT) void k_seg_count(Ws w) {
+  __shared__ uint32_t s_cnt[kNKeys];
+  Header* h = w.h;
+  if (h->abort) return;
+  const uint32_t S = h->n_segs, nsb = h->n_segblocks;
+  const uint32_t rs = w.SBmax + 1;
+  for (uint32_t b = blockIdx.x; b < nsb; b += gridDim.x) {
+    for (uint32_t k = threadIdx.x; k < (uint32_t)kNKeys; k += NT) s_cnt[k] = 0;
+    __syncthreads();
+    const uint32_t lo = b * kSegsPerBlock, hi = min(S, lo + kSegsPerBlock);
+    for (uint32_t s = lo + threadIdx.x; s < hi; s += NT) atomicAdd(&s_cnt[seg_key(w, s)], 1u);
+    __syncthreads();
+    for (uint32_t k = threadIdx.x; k < (uint32_t)kNKeys; k += NT) w.segcnt[k * rs + b] = s_cnt[k];
+    __syncthreads();
+  }
+}
+
+// Stable counting-sort scatter of the segments by seg_key.  Each wave ranks a
+// contiguous quarter of the block: lanes with equal keys are found with
+// ballots, a per-wave running count carries ranks across iterations.
+template <int NT>
+__global__ __launch_bounds__(NT) void k_seg_scatter(Ws w) {
+  constexpr int NW = NT / 64;
+  constexpr uint32_t PER_WAVE = kSegsPerBlock / NW;
+  constexpr int IT = PER_WAVE / 64;
+  __shared__ uint32_t s_run[NW][kNKeys];
+  __shared__ uint32_t s_kbase[kNKeys];
+  __shared__ uint32_t s_tmp[NW];
+  Header* h = w.h;
+  if (h->abort) return;
+  const uint32_t S = h->n_segs, nsb = h->n_segblocks;
+  const uint32_t rs = w.SBmax + 1;
+  const uint32_t lane = __lane_id(), wave = threadIdx.x >> 6;
+  {
+    const uint32_t tot = threadIdx.x < (uint32_t)kNKeys ? w.segcnt[threadIdx.x * rs + nsb] : 0u;
+    uint32_t total;
+    const uint32_t ex = block_excl_scan<NT>(tot, s_tmp, total);
+    if (threadIdx.x < (uint32_t)kNKeys) s_kbase[threadIdx.x] = ex;
+    __syncthreads();
+  }
+  if (blockIdx.x == 0) {
+    if (threadIdx.x <= (uint32_t)kNClass) h->cls_start[threadIdx.x] = s_kbase[threadIdx.x * kMaxLev];
+    for (uint32_t i = threadIdx.x; i < (uint32_t)(kNClass * kMaxLev); i += NT) {
+      const uint32_t c = i / kMaxLev, l = i % kMaxLev;
+      h->active[c][l] = s_kbase[c * kMaxLev + (kMaxLev - 1 - l)] - s_kbase[c * kMaxLev];
+    }
+  }
+  for (uint32_t b = blockIdx.x; b < nsb; b += gridDim.x) {
+    for (uint32_t k = threadIdx.x; k < (uint32_t)(NW * kNKeys); k += NT) (&s_run[0][0])[k] = 0;
+    __syncthreads();
+    const uint32_t wbeg = b * kSegsPerBlock + wave * PER_WAVE;
+    uint32_t pk[IT];
+#pragma unroll
+    for (int it = 0; it < IT; ++it) {
+      const uint32_t s = wbeg + it * 64 + lane;
+      const bool valid = s < S;
+      const uint32_t key = valid ? seg_key(w, s) : 0u;
+      const uint64_t mm = match_mask<kKeyBits>(key, valid);
+      const uint32_t r = lanes_below(mm);
+      const uint32_t old = valid ? s_run[wave][key] : 0u;
+      if (valid && r == 0) s_run[wave][key] = old + (uint32_t)__popcll(mm);
+      pk[it] = key | ((old + r) << kKeyBits);
+    }
+    __syncthreads();
+    for (uint32_t k = threadIdx.x; k < (uint32_t)kNKeys; k += NT) {
+      uint32_t acc = 0;
+      for (int v = 0; v < NW; ++v) {
+        const uint32_t t = s_run[v][k];
+        s_run[v][k] = acc;
+        acc += t;
+      }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int it = 0; it < IT; ++it) {
+      const uint32_t s = wbeg + it * 64 + lane;
+      const uint32_t key = pk[it] & ((1u << kKeyBits) - 1);
+      if (s < S && key != (uint32_t)(kNKeys - 1)) {
+        const uint32_t dest = s_kbase[key] + w.segcnt[key * rs + b] + s_run[wave][key] + (pk[it] >> kKeyBits);
+        w.sorted[dest] = s;
+      }
+    }
+    __syncthreads();
+  }
+}
+
+// Per class (blockIdx.x / 2) and kind (blockIdx.x % 2: chunk-sort tiles or
+// merge tiles): exclusive prefix of the tile counts over the class's sublist.
+template <int NT>
+__global__ __launch_bounds__(NT) void k_tile_prefix(Ws w) {
+  __shared__ uint32_t s_tmp[NT / 64];
+  Header* h = w.h;
+  if (h->abort) return;
+  const uint32_t c = blockIdx.x >> 1, kind = blockIdx.x & 1;
+  const uint32_t cs = h->cls_start[c], ce = h->cls_start[c + 1];
+  uint32_t* out = (kind ? w.mt : w.st) + cs + c;
+  const uint32_t div = kind ? w.P[c] : w.T[c];
+  uint32_t carry = 0;
+  for (uint32_t base = cs; base < ce; base += NT) {
+    const uint32_t i = base + threadIdx.x;
+    const uint32_t v = i < ce ? (w.seg_n[w.sorted[i]] + div - 1) / div : 0u;
+    uint32_t total;
+    const uint32_t ex = block_excl_scan<NT>(v, s_tmp, total);
+    if (i < ce) out[i - cs] = carry + ex;
+    carry += total;
+  }
+  if (threadIdx.x == 0) {
+    out[ce - cs] = carry;
+    if (kind == 0) h->sort_tiles[c] = carry;
+  }
+}
+
+// ---------------------------------------------------------------- packing
+// Big-endian lanes of the L-byte word at p, zero padded.  Reads only the
+// aligned dwords that hold at least one byte of the word.
+template <int NQ>
+__device__ inline void load_be_lanes(const uint8_t* p, uint32_t L, uint64_t (&lane)[NQ]) {
+  const uintptr_t addr = (uintptr_t)p;
+  const uint32_t* base = (const uint32_t*)(addr & ~(uintptr_t)3);
+  const uint32_t s = (uint32_t)(addr & 3);
+  const uint32_t nd = L ? (s + L + 3) >> 2 : 0u;
+  uint32_t wv[2 * NQ + 1];
+#pragma unroll
+  for (int j = 0; j < 2 * NQ + 1; ++j) wv[j] = (uint32_t)j < nd ? __builtin_bswap32(base[j]) : 0u;
+#pragma unroll
+  for (int q = 0; q < NQ; ++q) {
+    const uint64_t hi = ((uint64_t)wv[2 * q] << 32) | wv[2 * q + 1];
+    uint64_t v = s ? (hi << (8 * s)) | (uint64_t)(wv[2 * q + 2] >> (32 - 8 * s)) : hi;
+    const int rem = (int)L - 8 * q;
+    v = rem >= 8 ? v : (rem <= 0 ? 0ull : (v & (~0ull << (64 - 8 * rem))));
+    lane[q] = v;
+  }
+}
+
+// ---------------------------------------------------------------- k_scatter_pack
+// Stable scatter of every word into its (document, length) segment, packed
+// into key lanes.  Rank of a word inside its block = words of the same
+// length before it in the block; found per wave with ballots.
+template <int NT>
+__global__ __launch_bounds__(NT) void k_scatter_pack(Ws w) {
+  constexpr int NW = NT / 64;
+  constexpr uint32_t PER_WAVE = kWordsPerBlock / NW;
+  constexpr int IT = PER_WAVE / 64;
+  __shared__ uint32_t s_run[NW][kNB];
+  __shared__ uint32_t s_base[kNB];
+  __shared__ uint32_t s_doc;
+  Header* h = w.h;
+  if (h->abort) return;
+  const uint32_t nblk = h->n_blocks, D = h->n_docs;
+  const uint32_t* off = h->d.offsets;
+  const uint8_t* chars = h->d.chars;
+  const uint32_t rs = w.Bmax + 1;
+  const uint32_t lane = __lane_id(), wave = threadIdx.x >> 6;
+  for (uint32_t b = blockIdx.x; b < nblk; b += gridDim.x) {
+    for (uint32_t k = threadIdx.x; k < (uint32_t)(NW * kNB); k += NT) (&s_run[0][0])[k] = 0;
+    const BlockRange r = block_range<NT>(w, b, D, &s_doc);   // has a barrier
+    if (threadIdx.x < (uint32_t)kNB) {
+      const uint32_t L = threadIdx.x;
+      s_base[L] = w.seg_base[r.doc * kNB + L] + w.cnt[L * rs + b] - w.cnt[L * rs + w.doc_blk[r.doc]];
+    }
+    const uint32_t wbeg = r.ws + wave * PER_WAVE;
+    uint32_t pk[IT];
+#pragma unroll
+    for (int it = 0; it < IT; ++it) {
+      const uint32_t i = wbeg + it * 64 + lane;
+      const bool valid = i < r.we;
+      uint32_t L = 0;
+      if (valid) L = min(off[i + 1] - off[i], (uint32_t)kMaxLen);
+      const uint64_t mm = match_mask<6>(L, valid);
+      const uint32_t rk = lanes_below(mm);
+      const uint32_t old = valid ? s_run[wave][L] : 0u;
+      if (valid && rk == 0) s_run[wave][L] = old + (uint32_t)__popcll(mm);
+      pk[it] = L | ((old + rk) << 6);
+    }
+    __syncthreads();
+    if (threadIdx.x < (uint32_t)kNB) {
+      uint32_t acc = 0;
+      for (int v = 0; v < NW; ++v) {
+        const uint32_t t = s_run[v][threadIdx.x];
+        s_run[v][threadIdx.x] = acc;
+        acc += t;
+      }
+    }
+    __syncthreads();
+    const uint32_t doc0 = w.doc_off[r.doc];
+#pragma unroll 4
+    for (int it = 0; it < IT; ++it) {
+      const uint32_t i = wbeg + it * 64 + lane;
+      if (i < r.we) {
+        const uint32_t L = pk[it] & 63u;
+        const uint32_t dest = s_base[L] + s_run[wave][L] + (pk[it] >> 6);
+        const uint32_t idx = i - doc0;
+        uint64_t ln[4];
+        load_be_lanes<4>(chars + off[i], L, ln);
+        const int c = class_of_len(L);
+        if (c == 0) {
+          w.a.k[0][dest] = (ln[0] & 0xFFFFFFFF00000000ull) | idx;
+        } else {
+          w.a.k[0][dest] = ln[0];
+          if (c >= 2) w.a.k[1][dest] = ln[1];
+          if (c >= 3) {
+            w.a.k[2][dest] = ln[2];
+            w.a.k[3][dest] = ln[3];
+          }
+          w.a.idx[dest] = idx;
+        }
+      }
+    }
+    __syncthreads();
+  }
+}
+
+// ---------------------------------------------------------------- chunk sort
+// Odd-even transposition (the parallel form of bubble sort's adjacent
+// compare-exchanges, section 2) on chunks of C consecutive items.  Thread t of
+// a wave holds items t*E .. t*E+E-1 in registers; a chunk spans C/E lanes
+// (E <= C <= 64*E, both powers of two).  C phases sort a chunk; the loop also
+// stops early once an even and an odd phase exchange nothing anywhere in the
+// wave, bubble sort's own stopping rule.
+template <int NL, int E>
+__device__ inline void oddeven_chunks(Key<NL> (&e)[E], uint32_t C) {
+  const uint32_t lane = __lane_id();
+  const bool cross = C > (uint32_t)E;
+  const bool has_next = cross && (((lane + 1) * E) & (C - 1)) != 0;
+  const bool has_prev = cross && ((lane * E) & (C - 1)) != 0;
+  for (uint32_t p = 0; p < C; p += 2) {
+    bool sw = false;
+#pragma unroll
+    for (int j = 0; j + 1 < E; j += 2) sw |= cmp_xchg(e[j], e[j + 1]);
+#pragma unroll
+    for (int j = 1; j + 1 < E; j += 2) sw |= cmp_xchg(e[j], e[j + 1]);
+    if (cross) {
+      const Key<NL> nx = key_shfl(e[0], (int)min(lane + 1, 63u));
+      const Key<NL> pv = key_shfl(e[E - 1], (int)(lane ? lane - 1 : 0u));
+      if (has_next && key_less(nx, e[E - 1])) {
+        e[E - 1] = nx;
+        sw = true;
+      }
+      if (has_prev && key_less(e[0], pv)) e[0] = pv;
+    }
+    if (!__any(sw)) break;
+  }
+}
+
+// Merge path (Odeh et al., "Merge Path - Parallel Merging Made Simple", 2012):
+// number of A items among the first d outputs of the stable merge of A and B
+// (A first on ties).  In LDS, binary search by one thread.
+template <int NL, class Tile>
+__device__ inline int lds_merge_path(const Tile& t, int a0, int la, int b0, int lb, int d) {
+  int lo = d > lb ? d - lb : 0;
+  int hi = d < la ? d : la;
+  while (lo < hi) {
+    const int mid = (lo + hi) >> 1;
+    if (!key_less<NL>(t.get(b0 + d - 1 - mid), t.get(a0 + mid)))
+      lo = mid + 1;
+    else
+      hi = mid;
+  }
+  return lo;
+}
+
+// E outputs of the merge starting at A[ai], B[bi] (LDS), into registers.
+template <int NL, int E, class Tile>
+__device__ inline void lds_serial_merge(const Tile& t, int a0, int la, int b0, int lb, int ai, int bi,
+                                        Key<NL> (&out)[E]) {
+  Key<NL> ha = ai < la ? t.get(a0 + ai) : key_sentinel<NL>();
+  Key<NL> hb = bi < lb ? t.get(b0 + bi) : key_sentinel<NL>();
+#pragma unroll
+  for (int j = 0; j < E; ++j) {
+    const bool takeB = ai >= la || (bi < lb && key_less<NL>(hb, ha));
+    out[j] = key_select<NL>(takeB, hb, ha);
+    if (takeB) {
+      ++bi;
+      hb = bi < lb ? t.get(b0 + bi) : key_sentinel<NL>();
+    } else {
+      ++ai;
+      ha = ai < la ? t.get(a0 + ai) : key_sentinel<NL>();
+    }
+  }
+}
+
+// Merge path on the diagonal d over global memory, by one wave: 64 probes per
+// round.
+template <int NL>
+__device__ inline uint32_t wave_merge_path(const KeyBuf& buf, size_t a_base, uint32_t la, size_t b_base,
+                                           uint32_t lb, uint32_t d) {
+  const uint32_t lane = __lane_id();
+  uint32_t lo = d > lb ? d - lb : 0u;
+  uint32_t hi = d < la ? d : la;
+  while (lo < hi) {
+    const uint32_t step = (hi - lo + 63) >> 6;
+    const uint32_t a = lo + lane * step;
+    bool p = false;
+    if (a < hi) {
+      const Key<NL> A = gload<NL>(buf, a_base + a);
+      const Key<NL> B = gload<NL>(buf, b_base + (d - 1 - a));
+      p = !key_less<NL>(B, A);
+    }
+    const uint32_t c = __popcll(__ballot(p));
+    if (c == 0) {
+      hi = lo;
+    } else {
+      const uint32_t nlo = lo + (c - 1) * step + 1;
+      hi = min(lo + c * step, hi);
+      lo = nlo;
+    }
+  }
+  return lo;
+}
+
+// Segment of a tile from the device lists: k-th segment of the class sublist
+// whose tile prefix covers t.
+struct TileSeg {
+  uint32_t base, n, j;
+};
+__device__ inline TileSeg find_tile(const Ws& w, const uint32_t* prefix, uint32_t cstart, uint32_t count,
+                                    uint32_t t) {
+  const uint32_t k = wave_find(prefix, count, t);
+  const uint32_t s = w.sorted[cstart + k];
+  TileSeg r;
+  r.base = w.seg_base[s];
+  r.n = w.seg_n[s];
+  r.j = t - prefix[k];
+  return r;
+}
+
+// ---------------------------------------------------------------- k_sort_tiles
+// Chunk sort of one tile of T = NT*E items of a segment (class cls), then
+// merges in LDS up to T.  A segment that fits one tile is finished here and
+// its indices go straight to the output permutation; otherwise the sorted
+// tile is written back in place for the merge levels.
+template <int NL, int NT, int E>
+__global__ __launch_bounds__(NT) void k_sort_tiles(Ws w, int cls, TileWork tw) {
+  constexpr int T = NT * E;
+  __shared__ LdsTile<NL, T> tile;
+  Header* h = w.h;
+  if (h->abort) return;
+  uint32_t C = w.chunk[cls];
+  C = C < (uint32_t)E ? (uint32_t)E : (C > 64u * E ? 64u * E : C);
+  uint32_t ntiles, cstart = 0, ccount = 0;
+  const uint32_t* st = nullptr;
+  if (tw.direct) {
+    ntiles = (tw.n + T - 1) / T;
+  } else {
+    cstart = h->cls_start[cls];
+    ccount = h->cls_start[cls + 1] - cstart;
+    st = w.st + cstart + cls;
+    ntiles = h->sort_tiles[cls];
+  }
+  uint32_t* out_perm = h->d.out_perm;
+  for (uint32_t t = blockIdx.x; t < ntiles; t += gridDim.x) {
+    TileSeg g;
+    if (tw.direct) {
+      g.base = tw.base;
+      g.n = tw.n;
+      g.j = t;
+    } else {
+      g = find_tile(w, st, cstart, ccount, t);
+    }
+    const uint32_t lo = g.j * T;
+    const uint32_t cnt = min((uint32_t)T, g.n - lo);
+    const bool final = g.n <= (uint32_t)T;
+    const size_t gb = (size_t)g.base + lo;
+#pragma unroll
+    for (int r = 0; r < E; ++r) {
+      const uint32_t i = threadIdx.x + r * NT;
+      tile.put(i, i < cnt ? gload<NL>(w.a, gb + i) : key_sentinel<NL>());
+    }
+    __syncthreads();
+    Key<NL> e[E];
+#pragma unroll
+    for (int r = 0; r < E; ++r) e[r] = tile.get(threadIdx.x * E + r);
+    oddeven_chunks<NL, E>(e, C);
+    for (uint32_t R = C; R < (uint32_t)T; R <<= 1) {
+      __syncthreads();
+#pragma unroll
+      for (int r = 0; r < E; ++r) tile.put(threadIdx.x * E + r, e[r]);
+      __syncthreads();
+      const int o = threadIdx.x * E;
+      const int p0 = o & ~(int)(2 * R - 1);
+      const int d = o - p0;
+      const int a = lds_merge_path<NL>(tile, p0, (int)R, p0 + (int)R, (int)R, d);
+      lds_serial_merge<NL, E>(tile, p0, (int)R, p0 + (int)R, (int)R, a, d - a, e);
+    }
+    __syncthreads();
+#pragma unroll
+    for (int r = 0; r < E; ++r) tile.put(threadIdx.x * E + r, e[r]);
+    __syncthreads();
+#pragma unroll
+    for (int r = 0; r < E; ++r) {
+      const uint32_t i = threadIdx.x + r * NT;
+      if (i < cnt) {
+        const Key<NL> v = tile.get(i);
+        if (final)
+          out_perm[gb + i] = key_index<NL>(v);
+        else
+          gstore<NL>(w.a, gb + i, v);
+      }
+    }
+    __syncthreads();
+  }
+}
+
+// ---------------------------------------------------------------- k_merge
+// One merge level of class cls: every segment still merging has runs of
+// R = T << level sorted items; pairs of runs are merged into runs of 2R.
+// Work is cut into tiles of P = NT*E outputs by merge path; a tile's two
+// splits are found by two waves in parallel, its inputs staged in LDS and each
+// thread merges E outputs.  The segment's last level writes indices to the
+// output permutation.
+template <int NL, int NT, int E>
+__global__ __launch_bounds__(NT) void k_merge(Ws w, int cls, int level, TileWork tw) {
+  constexpr int P = NT * E;
+  __shared__ LdsTile<NL, P> tile;
+  __shared__ uint32_t s_split[2];
+  Header* h = w.h;
+  if (h->abort) return;
+  const uint32_t Tc = w.T[cls];
+  const uint64_t R = (uint64_t)Tc << level;
+  uint32_t ntiles, cstart = 0, cact = 0;
+  const uint32_t* mt = nullptr;
+  if (tw.direct) {
+    if ((uint32_t)level >= tw.m) return;
+    ntiles = (tw.n + P - 1) / P;
+  } else {
+    cstart = h->cls_start[cls];
+    cact = h->active[cls][level];
+    mt = w.mt + cstart + cls;
+    ntiles = cact ? mt[cact] : 0u;
+  }
+  const KeyBuf src = (level & 1) ? w.b : w.a;
+  const KeyBuf dst = (level & 1) ? w.a : w.b;
+  uint32_t* out_perm = h->d.out_perm;
+  const uint32_t wave = threadIdx.x >> 6;
+  for (uint32_t t = blockIdx.x; t < ntiles; t += gridDim.x) {
+    TileSeg g;
+    if (tw.direct) {
+      g.base = tw.base;
+      g.n = tw.n;
+      g.j = t;
+    } else {
+      g = find_tile(w, mt, cstart, cact, t);
+    }
+    const bool final = levels_for(g.n, Tc) == (uint32_t)level + 1;
+    const uint64_t o0 = (uint64_t)g.j * P;
+    const uint64_t ps = o0 / (2 * R) * (2 * R);
+    const uint32_t rem = g.n - (uint32_t)ps;
+    const uint32_t la = (uint32_t)min((uint64_t)rem, R);
+    const uint32_t lb = rem - la < R ? rem - la : (uint32_t)R;
+    const uint32_t tot = la + lb;
+    const uint32_t d0 = (uint32_t)(o0 - ps);
+    const uint32_t d1 = min(d0 + (uint32_t)P, tot);
+    const size_t abase = (size_t)g.base + ps, bbase = abase + la;
+    if (wave == 0) {
+      const uint32_t s = wave_merge_path<NL>(src, abase, la, bbase, lb, d0);
+      if (threadIdx.x == 0) s_split[0] = s;
+    } else if (wave == 1) {
+      const uint32_t s = d1 == tot ? la : wave_merge_path<NL>(src, abase, la, bbase, lb, d1);
+      if (threadIdx.x == 64) s_split[1] = s;
+    }
+    __syncthreads();
+    const uint32_t a0 = s_split[0], a1 = s_split[1];
+    const uint32_t b0 = d0 - a0;
+    const int na = (int)(a1 - a0), cnt = (int)(d1 - d0), nb = cnt - na;
+#pragma unroll
+    for (int r = 0; r < E; ++r) {
+      const int i = threadIdx.x + r * NT;
+      if (i < na)
+        tile.put(i, gload<NL>(src, abase + a0 + i));
+      else if (i < cnt)
+        tile.put(i, gload<NL>(src, bbase + b0 + (i - na)));
+    }
+    __syncthreads();
+    Key<NL> e[E];
+    const int diag = threadIdx.x * E;
+    if (diag < cnt) {
+      const int a = lds_merge_path<NL>(tile, 0, na, na, nb, diag);
+      lds_serial_merge<NL, E>(tile, 0, na, na, nb, a, diag - a, e);
+    }
+    __syncthreads();
+    if (diag < cnt) {
+#pragma unroll
+      for (int r = 0; r < E; ++r) tile.put(diag + r, e[r]);
+    }
+    __syncthreads();
+    const size_t ob = (size_t)g.base + o0;
+#pragma unroll
+    for (int r = 0; r < E; ++r) {
+      const int i = threadIdx.x + r * NT;
+      if (i < cnt) {
+        const Key<NL> v = tile.get(i);
+        if (final)
+          out_perm[ob + i] = key_index<NL>(v);
+        else
+          gstore<NL>(dst, ob + i, v);
+      }
+    }
+    __syncthreads();
+  }
+}
+
+}  // namespace sw

@@ -54,15 +54,17 @@ def check_invariants(chars, offsets, perm, boff):
     pl = lens[perm] if n else lens
     for L in range(MAX_LEN + 1):
         assert np.all(pl[boff[L]:boff[L + 1]] == L)
-    # I2
+    # I2: compare neighbours column by column, 8 bytes (big-endian) at a time
     if n > 1:
-        M = padded_bytes(chars, offsets)
+        width = int(lens.max())
+        M = padded_bytes(chars, offsets, width=-(-max(width, 1) // 8) * 8)
+        cols = M.view(">u8")
         a, b = perm[:-1], perm[1:]
         la, lb = lens[a], lens[b]
         lt = la < lb
         eq = la == lb
-        for j in range(M.shape[1]):
-            ca, cb = M[a, j], M[b, j]
+        for j in range(cols.shape[1]):
+            ca, cb = cols[a, j], cols[b, j]
             lt |= eq & (ca < cb)
             eq &= ca == cb
         lt |= eq & (a < b)

@@ -1,0 +1,63 @@
+"""The C ABI library: it loads without a GPU and exports every declared symbol."""
+import os
+import re
+import ctypes
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "sort_words.h")
+
+
+def declared_functions():
+    src = open(HEADER).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    names = re.findall(r"^[A-Za-z_][\w \*]*?\b(\w+)\s*\(", src, flags=re.M)
+    return sorted(set(n for n in names if n not in ("defined",)))
+
+
+def test_header_declares_the_boundary():
+    names = declared_functions()
+    for must in ("sort_words", "sort_words_ex", "sort_words_batch", "sort_words_plain",
+                 "sort_words_status", "sort_words_workspace_size", "sw_plan_create", "sw_plan_run",
+                 "sw_plan_destroy", "sort_words_last_error"):
+        assert must in names
+
+
+def test_library_exports_every_declared_symbol():
+    import paper_1411_5283_amd as sw
+    if not os.path.exists(sw.LIB_PATH):
+        pytest.skip("library not built")
+    lib = ctypes.CDLL(sw.LIB_PATH)
+    missing = [n for n in declared_functions() if not hasattr(lib, n)]
+    assert not missing, missing
+    assert set(sw.EXPORTED) == set(declared_functions())
+
+
+def test_host_side_calls_without_gpu():
+    import paper_1411_5283_amd as sw
+    if not os.path.exists(sw.LIB_PATH):
+        pytest.skip("library not built")
+    L = sw.lib()
+    assert sw.version().startswith("sortwords-gfx950")
+    # workspace sizes: monotone in words and documents; 0 when out of range
+    a = sw.sort_words_workspace_size(1000, 1)
+    b = sw.sort_words_workspace_size(100000, 1)
+    c = sw.sort_words_workspace_size(100000, 4096)
+    assert 0 < a < b < c
+    assert sw.sort_words_workspace_size(1000, 0xFFFFFFFF) == 0
+    # argument validation happens on the host before any device call
+    assert L.sort_words(None, None, 5, None, None) == sw.ERR_INVALID_ARG
+    assert L.sort_words_ex(None, None, 0, None, None, None, 0, None) == sw.ERR_INVALID_ARG
+    assert L.sort_words_batch(None, None, None, 1, None, None, None, 0, None) == sw.ERR_INVALID_ARG
+    assert b"null" in L.sort_words_last_error()
+    # config validation
+    cfg = sw.sw_config()
+    assert L.sw_get_config(ctypes.byref(cfg)) == 0
+    bad = sw.sw_config()
+    for k in range(4):
+        bad.chunk[k] = 48            # not a power of two
+    assert L.sw_set_config(ctypes.byref(bad)) == sw.ERR_INVALID_ARG
+    assert sw.num_variants(0) >= 1 and sw.num_variants(7) == 0
+    t, p = sw.variant_tiles(0, 0)
+    assert t >= 1024 and p >= 1024 and (t & (t - 1)) == 0

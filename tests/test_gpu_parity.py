@@ -1,0 +1,219 @@
+"""GPU parity: the HIP path against the CPU oracle, bit for bit.
+
+Every case sorts through the C ABI (sort_words, sort_words_ex,
+sort_words_batch, sort_words_plain, sw_plan_*) and compares the permutation
+and the bucket offsets with the oracle on the same seeded input.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+from checks import check_invariants
+from paper_1411_5283_amd import wordgen
+
+pytestmark = pytest.mark.gpu
+
+
+def _say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def gpu():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_1411_5283_amd as sw
+    sw.lib()
+    torch.cuda.set_device(0)
+    return sw
+
+
+@pytest.fixture
+def default_config(gpu):
+    cfg = gpu.get_config()
+    yield
+    gpu.set_config(**cfg)
+
+
+def _expect(oracle_mod, wl, bubble=True):
+    if wl.doc_offsets is not None:
+        return oracle_mod.oracle_batch(wl.chars, wl.offsets, wl.doc_offsets,
+                                       fn="oracle_bubble" if bubble else "oracle_def")
+    fn = oracle_mod.oracle_bubble if bubble else oracle_mod.oracle_def
+    return fn(wl.chars, wl.offsets)
+
+
+def _same(got, exp, what):
+    gp, gb = got
+    ep, eb = exp
+    assert gp.shape == ep.shape, what
+    bad = np.nonzero(gp != ep)[0]
+    assert bad.size == 0, "%s: permutation differs at %d positions, first %s" % (what, bad.size, bad[:5])
+    assert np.array_equal(gb, eb), "%s: bucket offsets differ" % what
+
+
+def test_config1_bit_exact(gpu, oracle_mod):
+    wl = wordgen.config(1)
+    _say("case config1 n=%d" % wl.n)
+    _same(gpu.sort_wordlist(wl), _expect(oracle_mod, wl), "config1")
+
+
+def test_config2_chunk1024_bit_exact(gpu, oracle_mod, default_config):
+    wl = wordgen.config(2)
+    _say("case config2 n=%d chunk=1024" % wl.n)
+    gpu.set_config(chunk=[1024] * 4, variant=[0] * 4)
+    _same(gpu.sort_wordlist(wl), _expect(oracle_mod, wl, bubble=False), "config2")
+
+
+@pytest.mark.parametrize("chunk", [16, 32, 64, 128, 256, 512, 1024])
+@pytest.mark.parametrize("variant", [0, 1])
+def test_chunk_and_variant_sweep(gpu, oracle_mod, default_config, chunk, variant):
+    # several tiles, merge levels and a ragged tail in every class
+    wl = wordgen.single(41_000, 3000, 1.0, 32, seed=77)
+    _say("case sweep chunk=%d variant=%d" % (chunk, variant))
+    gpu.set_config(chunk=[chunk] * 4, variant=[variant] * 4)
+    _same(gpu.sort_wordlist(wl), _expect(oracle_mod, wl, bubble=False),
+          "chunk %d variant %d" % (chunk, variant))
+
+
+def _edge_lists():
+    rng = np.random.default_rng(11)
+    out = {
+        "empty": [],
+        "one": [b"w"],
+        "one_empty_word": [b""],
+        "all_empty_words": [b""] * 5000,
+        "all_equal": [b"zzz"] * 9000,
+        "reversed_distinct": [("%06d" % (99999 - k)).encode() for k in range(12000)],
+        "already_sorted": sorted([bytes(rng.integers(97, 123, 6, dtype=np.uint8)) for _ in range(9000)]),
+        "all_lengths": [bytes(rng.integers(0, 256, L, dtype=np.uint8)) for L in rng.integers(0, 33, 20000)],
+        "unsigned_bytes": [bytes([b]) * L for b in (0, 1, 127, 128, 254, 255) for L in (1, 4, 5, 8, 9, 16, 17, 32)] * 50,
+        "lane_edges": [bytes(rng.integers(97, 100, L, dtype=np.uint8)) for L in (8, 9, 16, 17, 24, 25, 32) for _ in range(1500)],
+    }
+    for n in (4095, 4096, 4097, 8193, 2 * 4096 * 4 + 3):
+        out["n=%d" % n] = [bytes(rng.integers(97, 99, 3, dtype=np.uint8)) for _ in range(n)]
+    return out
+
+
+EDGES = _edge_lists()
+
+
+@pytest.mark.parametrize("name", sorted(EDGES))
+def test_edge_cases(gpu, oracle_mod, name):
+    wl = wordgen.from_words(EDGES[name])
+    _say("case edge %s n=%d" % (name, wl.n))
+    _same(gpu.sort_wordlist(wl), _expect(oracle_mod, wl, bubble=False), name)
+
+
+def test_nonzero_first_offset_and_unaligned_chars(gpu, oracle_mod):
+    import torch
+    base = wordgen.config(1, 0.3)
+    pad = 3
+    chars = np.concatenate([np.full(pad, 7, np.uint8), base.chars])
+    offs = (base.offsets + pad).astype(np.uint32)
+    _say("case offset0=%d n=%d" % (pad, base.n))
+    dchars = torch.from_numpy(chars).cuda()
+    doffs = torch.from_numpy(offs.view(np.int32)).cuda()
+    perm = torch.empty(base.n, dtype=torch.int32, device="cuda")
+    boff = torch.empty(34, dtype=torch.int32, device="cuda")
+    gpu.sort_words(dchars, doffs, base.n, perm, boff)
+    _same((gpu.to_u32(perm), gpu.to_u32(boff)), oracle_mod.oracle_def(chars, offs), "offset0")
+
+
+def test_batch_bit_exact(gpu, oracle_mod):
+    wl = wordgen.config(3, 0.03)
+    _say("case batch docs=%d n=%d" % (wl.n_docs, wl.n))
+    got = gpu.sort_wordlist(wl)
+    _same(got, _expect(oracle_mod, wl, bubble=False), "batch")
+
+
+def test_batch_with_empty_docs(gpu, oracle_mod):
+    docs = [wordgen.from_words([]), wordgen.config(1, 0.1), wordgen.from_words([]),
+            wordgen.from_words([b"b", b"a", b""]), wordgen.config(2, 0.05), wordgen.from_words([])]
+    wl = wordgen.concat_docs(docs)
+    _say("case batch_empty_docs n=%d" % wl.n)
+    _same(gpu.sort_wordlist(wl), _expect(oracle_mod, wl), "batch empty docs")
+
+
+def test_plain_form_equals_batched(gpu, oracle_mod):
+    import torch
+    wl = wordgen.config(3, 0.01)
+    _say("case plain-vs-batch docs=%d n=%d" % (wl.n_docs, wl.n))
+    chars, offs, docs = gpu.device_words(wl)
+    ws = torch.empty(gpu.sort_words_workspace_size(wl.n, wl.n_docs), dtype=torch.uint8, device="cuda")
+    outs = []
+    for fn in (gpu.sort_words_plain, gpu.sort_words_batch):
+        perm = torch.empty(wl.n, dtype=torch.int32, device="cuda")
+        boff = torch.empty(wl.n_docs * 34, dtype=torch.int32, device="cuda")
+        fn(chars, offs, docs, wl.n_docs, perm, boff, ws)
+        gpu.sort_words_status(ws)
+        outs.append((gpu.to_u32(perm), gpu.to_u32(boff).reshape(wl.n_docs, 34)))
+    _same(outs[0], outs[1], "plain vs batch")
+    _same(outs[1], _expect(oracle_mod, wl, bubble=False), "batch vs oracle")
+
+
+def test_plan_graph_replays(gpu, oracle_mod):
+    import torch
+    big = wordgen.config(3, 0.02)
+    small = wordgen.config(1, 0.5)
+    _say("case plan big=%d small=%d" % (big.n, small.n))
+    plan = gpu.Plan(big.n, big.n_docs)
+    try:
+        for rep in range(3):
+            for wl in (big, small):
+                chars, offs, docs = gpu.device_words(wl)
+                perm = torch.empty(wl.n, dtype=torch.int32, device="cuda")
+                boff = torch.empty(wl.n_docs * 34, dtype=torch.int32, device="cuda")
+                plan.run(chars, offs, docs, wl.n_docs, wl.n, perm, boff)
+                plan.status()
+                got = (gpu.to_u32(perm), gpu.to_u32(boff).reshape(wl.n_docs, 34))
+                if docs is None:
+                    got = (got[0], got[1][0])
+                _same(got, _expect(oracle_mod, wl, bubble=False), "plan rep %d n=%d" % (rep, wl.n))
+                torch.cuda.synchronize()
+    finally:
+        plan.close()
+
+
+def test_device_detected_errors(gpu):
+    import torch
+    _say("case errors")
+    n = 3
+    perm = torch.empty(8, dtype=torch.int32, device="cuda")
+    boff = torch.empty(34 * 4, dtype=torch.int32, device="cuda")
+    chars = torch.zeros(100, dtype=torch.uint8, device="cuda")
+
+    def run(offs):
+        o = torch.tensor(np.asarray(offs, np.uint32).view(np.int32), device="cuda")
+        try:
+            gpu.sort_words(chars, o, len(offs) - 1, perm, boff)
+            return 0
+        except gpu.SortWordsError as e:
+            return e.code
+
+    assert run([0, 3, 40, 41]) == gpu.ERR_WORD_TOO_LONG
+    assert run([0, 5, 3, 9]) == gpu.ERR_INVALID_ARG
+    assert run([0, 50, 40, 99]) == gpu.ERR_INVALID_ARG      # decreasing beats too long
+    assert run([0, 32, 64, 96]) == gpu.OK
+    # batch: doc_offsets must start at 0 and not decrease; N above capacity
+    o = torch.tensor(np.arange(0, 10, 2, dtype=np.uint32).view(np.int32), device="cuda")
+    ws = torch.empty(gpu.sort_words_workspace_size(4, 2), dtype=torch.uint8, device="cuda")
+    for docs, code in (([1, 4], gpu.ERR_INVALID_ARG), ([0, 3, 2], gpu.ERR_INVALID_ARG),
+                       ([0, 4], gpu.OK)):
+        d = torch.tensor(np.asarray(docs, np.uint32).view(np.int32), device="cuda")
+        gpu.sort_words_batch(chars, o, d, len(docs) - 1, perm, boff, ws)
+        assert gpu.sort_words_status_code(ws) == code, docs
+    # 100 words in a workspace sized for 10: the device sees N above capacity
+    o100 = torch.tensor(np.arange(0, 101, dtype=np.uint32).view(np.int32), device="cuda")
+    perm100 = torch.empty(100, dtype=torch.int32, device="cuda")
+    ws_small = torch.empty(gpu.sort_words_workspace_size(10, 1), dtype=torch.uint8, device="cuda")
+    d = torch.tensor(np.asarray([0, 100], np.uint32).view(np.int32), device="cuda")
+    gpu.sort_words_batch(chars, o100, d, 1, perm100, boff, ws_small)
+    assert gpu.sort_words_status_code(ws_small) == gpu.ERR_WORKSPACE
+    # after errors the library still sorts correctly
+    wl = wordgen.from_words([b"b", b"a"])
+    p, b = gpu.sort_wordlist(wl)
+    assert list(p) == [1, 0]

@@ -188,3 +188,24 @@ def test_paper_table3_derived_columns():
             tp = float(r[tc])
             assert abs(report.speedup(t1[d], tp) - float(r[sc])) < 1e-3
             assert abs(report.efficiency(t1[d], tp, p) - float(r[ec])) < 1e-3
+
+
+def test_invariant_checker_rejects_wrong_orders(oracle_mod):
+    wl = wordgen.config(1, 0.05)
+    perm, boff = oracle_mod.oracle_def(wl.chars, wl.offsets)
+    check_invariants(wl.chars, wl.offsets, perm, boff)
+    lens = np.diff(wl.offsets.astype(np.int64))
+    # swap two neighbours of equal length (a byte- or index-order violation)
+    k = next(k for k in range(len(perm) - 1) if lens[perm[k]] == lens[perm[k + 1]])
+    bad = perm.copy()
+    bad[k], bad[k + 1] = bad[k + 1], bad[k]
+    with pytest.raises(AssertionError):
+        check_invariants(wl.chars, wl.offsets, bad, boff)
+    bad = perm.copy()
+    bad[-1] = bad[0]                                   # not a permutation
+    with pytest.raises(AssertionError):
+        check_invariants(wl.chars, wl.offsets, bad, boff)
+    badb = boff.copy()
+    badb[5] += 1                                       # bucket offset off by one
+    with pytest.raises(AssertionError):
+        check_invariants(wl.chars, wl.offsets, perm, badb)
