@@ -215,7 +215,9 @@ def main():
     n, nd = wl.n, wl.n_docs
     perm = torch.empty(max(n, 1), dtype=torch.int32, device=dev)
     boff = torch.empty(nd * 34, dtype=torch.int32, device=dev)
-    stream = torch.cuda.current_stream()
+    # one dedicated stream: the plan's graph, the eager launches and the timing events share it
+    stream = torch.cuda.Stream(device=dev)
+    torch.cuda.set_stream(stream)
     torch.cuda.synchronize()
 
     # ---- batched form: graph-captured plan
