@@ -189,6 +189,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-check", action="store_true")
     ap.add_argument("--no-plain", action="store_true")
+    ap.add_argument("--untuned", action="store_true", help="ignore the autotuner cache")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py: this build runs on one GPU only; --gpus %d is not supported "
@@ -204,8 +205,12 @@ def main():
     t0 = time.perf_counter()
     wl = wordgen.config(cfg_no)
     log("generated %d words in %.1f s" % (wl.n, time.perf_counter() - t0))
+    tuned = None
     if "chunk" in wl.meta:
         sw.set_config(chunk=[wl.meta["chunk"]] * 4, variant=[0] * 4)
+    elif not args.untuned:
+        from paper_1411_5283_amd import tune
+        tuned = tune.apply(args.workload)
     cfg = sw.get_config()
     tiles = [sw.variant_tiles(c, cfg["variant"][c])[0] for c in range(4)]
 
@@ -267,6 +272,22 @@ def main():
         log("plain: %.3f ms/step, %.1f Mwords/s, same=%s" % (pms, plain["value"], same))
         del perm2
 
+    # ---- the same pass launched eagerly (no graph), classes forked onto side streams
+    def eager():
+        if docs is None:
+            sw.sort_words_ex(chars, offs, n, perm, boff, ws, stream)
+        else:
+            sw.sort_words_batch(chars, offs, docs, nd, perm, boff, ws, stream)
+    eager()
+    torch.cuda.synchronize()
+    ev0.record(stream)
+    for _ in range(args.profile_steps):
+        eager()
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    eager_ms = ev0.elapsed_time(ev1) / args.profile_steps
+    log("eager: %.3f ms/step" % eager_ms)
+
     # ---- per-kernel timing of the same pass (eager launches, HIP events on this stream)
     sw.profile_reset()
     sw.profile_enable(True)
@@ -317,7 +338,9 @@ def main():
         "vs_baseline": None, "dtype": "u64", "data": "synthetic",
         "config": {"workload": "%s: %s" % (args.workload, desc), "n_words": n, "n_docs": nd,
                    "form": "graph-captured plan (batched, device-side segment scheduling)",
-                   "chunk": cfg["chunk"], "variant": cfg["variant"], "sort_tile": tiles},
+                   "chunk": cfg["chunk"], "variant": cfg["variant"], "sort_tile": tiles,
+                   "tuned": tuned is not None},
+        "eager_ms_per_step": eager_ms,
         "per_bucket_launch": plain,
         "batched_over_plain": (value / plain["value"]) if plain else None,
         "check": check,

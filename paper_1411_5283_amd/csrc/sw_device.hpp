@@ -27,6 +27,7 @@ constexpr int kNClass = 4;
 constexpr int kMaxLev = 24;             // merge levels a segment may need
 constexpr uint32_t kWordsPerBlock = 4096;
 constexpr uint32_t kSegsPerBlock = 4096;
+constexpr uint32_t kMinMergeTile = 512;      // smallest merge tile of any variant
 constexpr int kNKeys = kNClass * kMaxLev + 1;   // segment-order keys (+1: empty)
 constexpr int kKeyBits = 7;
 static_assert(kNKeys <= (1 << kKeyBits), "segment key bits");
@@ -94,6 +95,8 @@ struct Ws {
   uint32_t* sorted;     // [Smax]      non-empty segments by (class, levels desc)
   uint32_t* st;         // [Smax+kNClass]  chunk-sort tile prefix per class
   uint32_t* mt;         // [Smax+kNClass]  merge tile prefix per class
+  uint4* rec;           // [kNClass][rec_stride]  record of each merge tile (k_partition)
+  uint32_t rec_stride;  // Nmax/kMinMergeTile + Smax + 2
   KeyBuf a;             // key buffer 0 (scatter output, chunk sort in place)
   KeyBuf b;             // key buffer 1 (ping-pong for merge levels)
   uint32_t Nmax, Dmax, Bmax, Smax, SBmax;
@@ -292,16 +295,17 @@ __device__ inline bool cmp_xchg(Key<NL>& a, Key<NL>& b) {
 }
 
 // ---------------------------------------------------------------- LDS tile
-// Structure-of-arrays tile of CAP keys.  One pad slot every 16 items keeps a
-// thread's 16 consecutive items (blocked layout) off its neighbours' banks.
-template <int NL, int CAP>
+// Structure-of-arrays tile of CAP keys.  One pad slot every 2^PADSH items
+// keeps a thread's consecutive items (blocked layout) off its neighbours'
+// banks.
+template <int NL, int CAP, int PADSH = 4>
 struct LdsTile {
-  static constexpr int kPadded = CAP + CAP / 16;
+  static constexpr int kPadded = CAP + (CAP >> PADSH);
   static constexpr int kLanes = NL ? NL : 1;
   uint64_t k[kLanes][kPadded];
   uint32_t idx[NL ? kPadded : 1];
 
-  __device__ static int pos(int i) { return i + (i >> 4); }
+  __device__ static int pos(int i) { return i + (i >> PADSH); }
   __device__ Key<NL> get(int i) const {
     const int p = pos(i);
     Key<NL> v;
@@ -317,11 +321,11 @@ struct LdsTile {
     idx[p] = v.idx;
   }
 };
-template <int CAP>
-struct LdsTile<0, CAP> {
-  static constexpr int kPadded = CAP + CAP / 16;
+template <int CAP, int PADSH>
+struct LdsTile<0, CAP, PADSH> {
+  static constexpr int kPadded = CAP + (CAP >> PADSH);
   uint64_t k[kPadded];
-  __device__ static int pos(int i) { return i + (i >> 4); }
+  __device__ static int pos(int i) { return i + (i >> PADSH); }
   __device__ Key<0> get(int i) const {
     Key<0> v;
     v.k = k[pos(i)];

@@ -364,16 +364,24 @@ __device__ inline void load_be_lanes(const uint8_t* p, uint32_t L, uint64_t (&la
 
 // ---------------------------------------------------------------- k_scatter_pack
 // Stable scatter of every word into its (document, length) segment, packed
-// into key lanes.  Rank of a word inside its block = words of the same
-// length before it in the block; found per wave with ballots.
+// into key lanes.  Pass 1: the rank of a word among the words of the same
+// length before it in the block (per wave with ballots, a running count per
+// wave carries ranks across iterations) gives its slot in the block's
+// length-sorted order; LDS records which word holds each slot.  Pass 2 walks
+// the slots in order, so consecutive lanes write consecutive positions of one
+// segment (coalesced stores); its loads of offsets and characters stay inside
+// the block's small, cached span.
 template <int NT>
 __global__ __launch_bounds__(NT) void k_scatter_pack(Ws w) {
   constexpr int NW = NT / 64;
   constexpr uint32_t PER_WAVE = kWordsPerBlock / NW;
   constexpr int IT = PER_WAVE / 64;
   __shared__ uint32_t s_run[NW][kNB];
-  __shared__ uint32_t s_base[kNB];
+  __shared__ uint32_t s_bstart[kNB + 1];
+  __shared__ uint32_t s_gbase[kNB];
+  __shared__ uint16_t s_slot[kWordsPerBlock];
   __shared__ uint32_t s_doc;
+  static_assert(kWordsPerBlock <= 65536, "slot index is 16-bit");
   Header* h = w.h;
   if (h->abort) return;
   const uint32_t nblk = h->n_blocks, D = h->n_docs;
@@ -386,7 +394,7 @@ __global__ __launch_bounds__(NT) void k_scatter_pack(Ws w) {
     const BlockRange r = block_range<NT>(w, b, D, &s_doc);   // has a barrier
     if (threadIdx.x < (uint32_t)kNB) {
       const uint32_t L = threadIdx.x;
-      s_base[L] = w.seg_base[r.doc * kNB + L] + w.cnt[L * rs + b] - w.cnt[L * rs + w.doc_blk[r.doc]];
+      s_gbase[L] = w.seg_base[r.doc * kNB + L] + w.cnt[L * rs + b] - w.cnt[L * rs + w.doc_blk[r.doc]];
     }
     const uint32_t wbeg = r.ws + wave * PER_WAVE;
     uint32_t pk[IT];
@@ -403,37 +411,51 @@ __global__ __launch_bounds__(NT) void k_scatter_pack(Ws w) {
       pk[it] = L | ((old + rk) << 6);
     }
     __syncthreads();
-    if (threadIdx.x < (uint32_t)kNB) {
-      uint32_t acc = 0;
-      for (int v = 0; v < NW; ++v) {
-        const uint32_t t = s_run[v][threadIdx.x];
-        s_run[v][threadIdx.x] = acc;
-        acc += t;
+    if (wave == 0) {
+      // per length: prefix over waves, then the block's length-sorted starts
+      uint32_t tot = 0;
+      if (lane < (uint32_t)kNB) {
+        for (int v = 0; v < NW; ++v) {
+          const uint32_t t = s_run[v][lane];
+          s_run[v][lane] = tot;
+          tot += t;
+        }
       }
+      const uint32_t ex = wave_incl_scan(tot) - tot;
+      if (lane <= (uint32_t)kNB) s_bstart[lane] = ex;
     }
     __syncthreads();
-    const uint32_t doc0 = w.doc_off[r.doc];
-#pragma unroll 4
+#pragma unroll
     for (int it = 0; it < IT; ++it) {
       const uint32_t i = wbeg + it * 64 + lane;
       if (i < r.we) {
         const uint32_t L = pk[it] & 63u;
-        const uint32_t dest = s_base[L] + s_run[wave][L] + (pk[it] >> 6);
-        const uint32_t idx = i - doc0;
-        uint64_t ln[4];
-        load_be_lanes<4>(chars + off[i], L, ln);
-        const int c = class_of_len(L);
-        if (c == 0) {
-          w.a.k[0][dest] = (ln[0] & 0xFFFFFFFF00000000ull) | idx;
-        } else {
-          w.a.k[0][dest] = ln[0];
-          if (c >= 2) w.a.k[1][dest] = ln[1];
-          if (c >= 3) {
-            w.a.k[2][dest] = ln[2];
-            w.a.k[3][dest] = ln[3];
-          }
-          w.a.idx[dest] = idx;
+        s_slot[s_bstart[L] + s_run[wave][L] + (pk[it] >> 6)] = (uint16_t)(i - r.ws);
+      }
+    }
+    __syncthreads();
+    const uint32_t nw = r.we - r.ws;
+    const uint32_t doc0 = w.doc_off[r.doc];
+#pragma unroll 4
+    for (uint32_t p = threadIdx.x; p < nw; p += NT) {
+      const uint32_t i = r.ws + s_slot[p];
+      const uint32_t a = off[i];
+      const uint32_t L = min(off[i + 1] - a, (uint32_t)kMaxLen);
+      const uint32_t dest = s_gbase[L] + (p - s_bstart[L]);
+      const uint32_t idx = i - doc0;
+      uint64_t ln[4];
+      load_be_lanes<4>(chars + a, L, ln);
+      const int c = class_of_len(L);
+      if (c == 0) {
+        w.a.k[0][dest] = (ln[0] & 0xFFFFFFFF00000000ull) | idx;
+      } else {
+        w.a.k[0][dest] = ln[0];
+        if (c >= 2) w.a.k[1][dest] = ln[1];
+        if (c >= 3) {
+          w.a.k[2][dest] = ln[2];
+          w.a.k[3][dest] = ln[3];
         }
+        w.a.idx[dest] = idx;
       }
     }
     __syncthreads();
@@ -472,16 +494,23 @@ __device__ inline void oddeven_chunks(Key<NL> (&e)[E], uint32_t C) {
   }
 }
 
+// Accessor of a sorted run held contiguously in LDS.
+template <int NL, class Tile>
+struct LinRun {
+  const Tile& t;
+  int base;
+  __device__ Key<NL> operator()(int i) const { return t.get(base + i); }
+};
 // Merge path (Odeh et al., "Merge Path - Parallel Merging Made Simple", 2012):
 // number of A items among the first d outputs of the stable merge of A and B
-// (A first on ties).  In LDS, binary search by one thread.
-template <int NL, class Tile>
-__device__ inline int lds_merge_path(const Tile& t, int a0, int la, int b0, int lb, int d) {
+// (A first on ties).  Binary search by one thread.
+template <int NL, class RA, class RB>
+__device__ inline int run_merge_path(const RA& A, int la, const RB& B, int lb, int d) {
   int lo = d > lb ? d - lb : 0;
   int hi = d < la ? d : la;
   while (lo < hi) {
     const int mid = (lo + hi) >> 1;
-    if (!key_less<NL>(t.get(b0 + d - 1 - mid), t.get(a0 + mid)))
+    if (!key_less<NL>(B(d - 1 - mid), A(mid)))
       lo = mid + 1;
     else
       hi = mid;
@@ -489,24 +518,66 @@ __device__ inline int lds_merge_path(const Tile& t, int a0, int la, int b0, int 
   return lo;
 }
 
-// E outputs of the merge starting at A[ai], B[bi] (LDS), into registers.
-template <int NL, int E, class Tile>
-__device__ inline void lds_serial_merge(const Tile& t, int a0, int la, int b0, int lb, int ai, int bi,
+// E outputs of the merge starting at A[ai], B[bi], one after another.  An
+// exhausted side shows the sentinel, which no real key reaches, so the next
+// output is always the smaller head; one load per output refills the side
+// that was taken.
+template <int NL, int E, class RA, class RB>
+__device__ inline void run_serial_merge(const RA& A, int la, const RB& B, int lb, int ai, int bi,
                                         Key<NL> (&out)[E]) {
-  Key<NL> ha = ai < la ? t.get(a0 + ai) : key_sentinel<NL>();
-  Key<NL> hb = bi < lb ? t.get(b0 + bi) : key_sentinel<NL>();
+  Key<NL> ha = ai < la ? A(ai) : key_sentinel<NL>();
+  Key<NL> hb = bi < lb ? B(bi) : key_sentinel<NL>();
 #pragma unroll
   for (int j = 0; j < E; ++j) {
-    const bool takeB = ai >= la || (bi < lb && key_less<NL>(hb, ha));
+    const bool takeB = key_less<NL>(hb, ha);
     out[j] = key_select<NL>(takeB, hb, ha);
-    if (takeB) {
-      ++bi;
-      hb = bi < lb ? t.get(b0 + bi) : key_sentinel<NL>();
-    } else {
-      ++ai;
-      ha = ai < la ? t.get(a0 + ai) : key_sentinel<NL>();
-    }
+    const int ni = takeB ? ++bi : ++ai;
+    const int lim = takeB ? lb : la;
+    Key<NL> nv = key_sentinel<NL>();
+    if (ni < lim) nv = takeB ? B(ni) : A(ni);
+    ha = key_select<NL>(takeB, ha, nv);
+    hb = key_select<NL>(takeB, nv, hb);
   }
+}
+
+// The E smallest items of A[ai..ai+E) and B[bi..bi+E), in order, into
+// registers: the candidates are loaded independently (no dependent load
+// chain), min(x[i], y[E-1-i]) keeps the E smallest as a bitonic sequence
+// (half-cleaner of x followed by y reversed), and log2(E) half-cleaner stages
+// sort it (Batcher's bitonic merge).  Items past a run's end read as the
+// sentinel.
+template <int NL, int E, class RA, class RB>
+__device__ inline void run_bitonic_merge(const RA& A, int la, const RB& B, int lb, int ai, int bi,
+                                         Key<NL> (&out)[E]) {
+  Key<NL> x[E], y[E];
+#pragma unroll
+  for (int i = 0; i < E; ++i) {
+    x[i] = ai + i < la ? A(ai + i) : key_sentinel<NL>();
+    y[i] = bi + i < lb ? B(bi + i) : key_sentinel<NL>();
+  }
+#pragma unroll
+  for (int i = 0; i < E; ++i) out[i] = key_select<NL>(key_less<NL>(y[E - 1 - i], x[i]), y[E - 1 - i], x[i]);
+#pragma unroll
+  for (int st = E / 2; st >= 1; st >>= 1) {
+#pragma unroll
+    for (int i = 0; i < E; ++i)
+      if ((i & st) == 0) cmp_xchg<NL>(out[i], out[i + st]);
+  }
+}
+
+template <int NL, class Tile>
+__device__ inline int lds_merge_path(const Tile& t, int a0, int la, int b0, int lb, int d) {
+  return run_merge_path<NL>(LinRun<NL, Tile>{t, a0}, la, LinRun<NL, Tile>{t, b0}, lb, d);
+}
+
+// E merged outputs into registers: MM = 0 serial merge, MM = 1 bitonic merge.
+template <int NL, int E, int MM, class Tile>
+__device__ inline void lds_register_merge(const Tile& t, int a0, int la, int b0, int lb, int ai, int bi,
+                                          Key<NL> (&out)[E]) {
+  if (MM == 0)
+    run_serial_merge<NL, E>(LinRun<NL, Tile>{t, a0}, la, LinRun<NL, Tile>{t, b0}, lb, ai, bi, out);
+  else
+    run_bitonic_merge<NL, E>(LinRun<NL, Tile>{t, a0}, la, LinRun<NL, Tile>{t, b0}, lb, ai, bi, out);
 }
 
 // Merge path on the diagonal d over global memory, by one wave: 64 probes per
@@ -559,7 +630,7 @@ __device__ inline TileSeg find_tile(const Ws& w, const uint32_t* prefix, uint32_
 // merges in LDS up to T.  A segment that fits one tile is finished here and
 // its indices go straight to the output permutation; otherwise the sorted
 // tile is written back in place for the merge levels.
-template <int NL, int NT, int E>
+template <int NL, int NT, int E, int MM>
 __global__ __launch_bounds__(NT) void k_sort_tiles(Ws w, int cls, TileWork tw) {
   constexpr int T = NT * E;
   __shared__ LdsTile<NL, T> tile;
@@ -610,7 +681,7 @@ __global__ __launch_bounds__(NT) void k_sort_tiles(Ws w, int cls, TileWork tw) {
       const int p0 = o & ~(int)(2 * R - 1);
       const int d = o - p0;
       const int a = lds_merge_path<NL>(tile, p0, (int)R, p0 + (int)R, (int)R, d);
-      lds_serial_merge<NL, E>(tile, p0, (int)R, p0 + (int)R, (int)R, a, d - a, e);
+      lds_register_merge<NL, E, MM>(tile, p0, (int)R, p0 + (int)R, (int)R, a, d - a, e);
     }
     __syncthreads();
 #pragma unroll
@@ -631,22 +702,40 @@ __global__ __launch_bounds__(NT) void k_sort_tiles(Ws w, int cls, TileWork tw) {
   }
 }
 
-// ---------------------------------------------------------------- k_merge
-// One merge level of class cls: every segment still merging has runs of
-// R = T << level sorted items; pairs of runs are merged into runs of 2R.
-// Work is cut into tiles of P = NT*E outputs by merge path; a tile's two
-// splits are found by two waves in parallel, its inputs staged in LDS and each
-// thread merges E outputs.  The segment's last level writes indices to the
-// output permutation.
-template <int NL, int NT, int E>
-__global__ __launch_bounds__(NT) void k_merge(Ws w, int cls, int level, TileWork tw) {
-  constexpr int P = NT * E;
-  __shared__ LdsTile<NL, P> tile;
-  __shared__ uint32_t s_split[2];
+// ---------------------------------------------------------------- merge levels
+// Geometry of merge tile j (P outputs) of a segment of n items at a level
+// whose runs hold R items: the pair of runs it reads and its diagonal range.
+struct MergeTile {
+  uint64_t o0, ps;
+  uint32_t la, lb, d0, d1;
+};
+__device__ inline MergeTile merge_tile(uint32_t n, uint32_t j, uint64_t R, uint32_t P) {
+  MergeTile m;
+  m.o0 = (uint64_t)j * P;
+  m.ps = m.o0 / (2 * R) * (2 * R);
+  const uint32_t rem = n - (uint32_t)m.ps;
+  m.la = (uint32_t)min((uint64_t)rem, R);
+  m.lb = rem - m.la < R ? rem - m.la : (uint32_t)R;
+  m.d0 = (uint32_t)(m.o0 - m.ps);
+  m.d1 = min(m.d0 + P, m.la + m.lb);
+  return m;
+}
+
+// Per merge tile record written by k_partition: the tile's segment (first
+// position, size), its index in the segment, and the merge-path split at its
+// first output (A items before it).
+struct TileRec {
+  uint32_t base, n, j, split;
+};
+
+// k_partition: the record of every tile of one merge level (one wave per
+// tile, 64 probes per round for the split), so that merge workgroups need a
+// single 16-byte load to place a tile.
+template <int NL, int NT>
+__global__ __launch_bounds__(NT) void k_partition(Ws w, int cls, int level, TileWork tw, uint32_t P) {
   Header* h = w.h;
   if (h->abort) return;
-  const uint32_t Tc = w.T[cls];
-  const uint64_t R = (uint64_t)Tc << level;
+  const uint64_t R = (uint64_t)w.T[cls] << level;
   uint32_t ntiles, cstart = 0, cact = 0;
   const uint32_t* mt = nullptr;
   if (tw.direct) {
@@ -659,10 +748,9 @@ __global__ __launch_bounds__(NT) void k_merge(Ws w, int cls, int level, TileWork
     ntiles = cact ? mt[cact] : 0u;
   }
   const KeyBuf src = (level & 1) ? w.b : w.a;
-  const KeyBuf dst = (level & 1) ? w.a : w.b;
-  uint32_t* out_perm = h->d.out_perm;
-  const uint32_t wave = threadIdx.x >> 6;
-  for (uint32_t t = blockIdx.x; t < ntiles; t += gridDim.x) {
+  TileRec* rec = (TileRec*)w.rec + (size_t)cls * w.rec_stride;
+  const uint32_t nw = gridDim.x * (NT / 64);
+  for (uint32_t t = blockIdx.x * (NT / 64) + (threadIdx.x >> 6); t < ntiles; t += nw) {
     TileSeg g;
     if (tw.direct) {
       g.base = tw.base;
@@ -671,41 +759,110 @@ __global__ __launch_bounds__(NT) void k_merge(Ws w, int cls, int level, TileWork
     } else {
       g = find_tile(w, mt, cstart, cact, t);
     }
-    const bool final = levels_for(g.n, Tc) == (uint32_t)level + 1;
-    const uint64_t o0 = (uint64_t)g.j * P;
-    const uint64_t ps = o0 / (2 * R) * (2 * R);
-    const uint32_t rem = g.n - (uint32_t)ps;
-    const uint32_t la = (uint32_t)min((uint64_t)rem, R);
-    const uint32_t lb = rem - la < R ? rem - la : (uint32_t)R;
-    const uint32_t tot = la + lb;
-    const uint32_t d0 = (uint32_t)(o0 - ps);
-    const uint32_t d1 = min(d0 + (uint32_t)P, tot);
-    const size_t abase = (size_t)g.base + ps, bbase = abase + la;
-    if (wave == 0) {
-      const uint32_t s = wave_merge_path<NL>(src, abase, la, bbase, lb, d0);
-      if (threadIdx.x == 0) s_split[0] = s;
-    } else if (wave == 1) {
-      const uint32_t s = d1 == tot ? la : wave_merge_path<NL>(src, abase, la, bbase, lb, d1);
-      if (threadIdx.x == 64) s_split[1] = s;
-    }
-    __syncthreads();
-    const uint32_t a0 = s_split[0], a1 = s_split[1];
-    const uint32_t b0 = d0 - a0;
-    const int na = (int)(a1 - a0), cnt = (int)(d1 - d0), nb = cnt - na;
+    const MergeTile m = merge_tile(g.n, g.j, R, P);
+    const size_t abase = (size_t)g.base + m.ps;
+    const uint32_t sp = wave_merge_path<NL>(src, abase, m.la, abase + m.la, m.lb, m.d0);
+    if (__lane_id() == 0) rec[t] = TileRec{g.base, g.n, g.j, sp};
+  }
+}
+
+// Where a merge tile reads and writes, from its record and the split of the
+// next tile.
+struct TileIO {
+  size_t apos, bpos, ob;
+  int na, cnt;
+  bool final;
+};
+__device__ inline TileIO tile_io(const TileRec& r, uint32_t next_split, uint64_t R, uint32_t P, uint32_t Tc,
+                                 int level) {
+  const MergeTile m = merge_tile(r.n, r.j, R, P);
+  const uint32_t a1 = m.d1 == m.la + m.lb ? m.la : next_split;
+  TileIO io;
+  io.apos = (size_t)r.base + m.ps + r.split;
+  io.bpos = (size_t)r.base + m.ps + m.la + (m.d0 - r.split);
+  io.ob = (size_t)r.base + m.o0;
+  io.na = (int)(a1 - r.split);
+  io.cnt = (int)(m.d1 - m.d0);
+  io.final = levels_for(r.n, Tc) == (uint32_t)level + 1;
+  return io;
+}
+
+template <int NL, int NT, int E>
+__device__ inline void load_tile_regs(const KeyBuf& src, const TileIO& io, Key<NL> (&pf)[E]) {
+#pragma unroll
+  for (int r = 0; r < E; ++r) {
+    const int i = threadIdx.x + r * NT;
+    if (i < io.na)
+      pf[r] = gload<NL>(src, io.apos + i);
+    else if (i < io.cnt)
+      pf[r] = gload<NL>(src, io.bpos + (i - io.na));
+  }
+}
+
+// ---------------------------------------------------------------- k_merge
+// One merge level of class cls: every segment still merging has runs of
+// R = T << level sorted items; pairs of runs are merged into runs of 2R.
+// Work is cut into tiles of P = NT*E outputs placed by k_partition.  Each
+// workgroup walks its tiles (grid stride) as a pipeline: while it merges tile
+// t, the inputs of its next tile are already on their way into registers and
+// the record of the tile after that is being fetched.  A tile's inputs are
+// staged in LDS, each thread finds its diagonal by merge path and merges E
+// outputs in registers (method MM), the outputs are staged back in LDS and
+// stored in order.  The segment's last level writes indices to the output
+// permutation.
+template <int NL, int NT, int E, int MM>
+__global__ __launch_bounds__(NT) void k_merge(Ws w, int cls, int level, TileWork tw) {
+  constexpr int P = NT * E;
+  __shared__ LdsTile<NL, P> tile;
+  Header* h = w.h;
+  if (h->abort) return;
+  const uint32_t Tc = w.T[cls];
+  const uint64_t R = (uint64_t)Tc << level;
+  uint32_t ntiles;
+  if (tw.direct) {
+    if ((uint32_t)level >= tw.m) return;
+    ntiles = (tw.n + P - 1) / P;
+  } else {
+    const uint32_t cact = h->active[cls][level];
+    ntiles = cact ? (w.mt + h->cls_start[cls] + cls)[cact] : 0u;
+  }
+  const uint32_t G = gridDim.x;
+  uint32_t t = blockIdx.x;
+  if (t >= ntiles) return;
+  const KeyBuf src = (level & 1) ? w.b : w.a;
+  const KeyBuf dst = (level & 1) ? w.a : w.b;
+  const TileRec* rec = (const TileRec*)w.rec + (size_t)cls * w.rec_stride;
+  uint32_t* out_perm = h->d.out_perm;
+
+  TileIO cur = tile_io(rec[t], rec[t + 1].split, R, P, Tc, level);
+  Key<NL> pf[E];
+  load_tile_regs<NL, NT, E>(src, cur, pf);
+  TileRec rn = rec[t + G < ntiles ? t + G : t];
+  uint32_t rn1 = rec[t + G < ntiles ? t + G + 1 : t].split;
+  for (; t < ntiles; t += G) {
 #pragma unroll
     for (int r = 0; r < E; ++r) {
       const int i = threadIdx.x + r * NT;
-      if (i < na)
-        tile.put(i, gload<NL>(src, abase + a0 + i));
-      else if (i < cnt)
-        tile.put(i, gload<NL>(src, bbase + b0 + (i - na)));
+      if (i < cur.cnt) tile.put(i, pf[r]);
     }
     __syncthreads();
-    Key<NL> e[E];
+    // the next tile's inputs and the record of the one after
+    const bool has_next = t + G < ntiles;
+    TileIO nxt = cur;
+    if (has_next) {
+      nxt = tile_io(rn, rn1, R, P, Tc, level);
+      load_tile_regs<NL, NT, E>(src, nxt, pf);
+      if (t + 2 * G < ntiles) {
+        rn = rec[t + 2 * G];
+        rn1 = rec[t + 2 * G + 1].split;
+      }
+    }
+    const int cnt = cur.cnt, na = cur.na, nb = cnt - na;
     const int diag = threadIdx.x * E;
+    Key<NL> e[E];
     if (diag < cnt) {
-      const int a = lds_merge_path<NL>(tile, 0, na, na, nb, diag);
-      lds_serial_merge<NL, E>(tile, 0, na, na, nb, a, diag - a, e);
+      const int sa = lds_merge_path<NL>(tile, 0, na, na, nb, diag);
+      lds_register_merge<NL, E, MM>(tile, 0, na, na, nb, sa, diag - sa, e);
     }
     __syncthreads();
     if (diag < cnt) {
@@ -713,19 +870,19 @@ __global__ __launch_bounds__(NT) void k_merge(Ws w, int cls, int level, TileWork
       for (int r = 0; r < E; ++r) tile.put(diag + r, e[r]);
     }
     __syncthreads();
-    const size_t ob = (size_t)g.base + o0;
 #pragma unroll
     for (int r = 0; r < E; ++r) {
-      const int i = threadIdx.x + r * NT;
-      if (i < cnt) {
-        const Key<NL> v = tile.get(i);
-        if (final)
-          out_perm[ob + i] = key_index<NL>(v);
+      const int o = threadIdx.x + r * NT;
+      if (o < cnt) {
+        const Key<NL> v = tile.get(o);
+        if (cur.final)
+          out_perm[cur.ob + o] = key_index<NL>(v);
         else
-          gstore<NL>(dst, ob + i, v);
+          gstore<NL>(dst, cur.ob + o, v);
       }
     }
     __syncthreads();
+    cur = nxt;
   }
 }
 

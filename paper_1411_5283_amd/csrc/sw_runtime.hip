@@ -42,37 +42,55 @@ int fail(int code, const char* fmt, ...) {
 constexpr int kNT = 256;   // threads per workgroup of the streaming kernels
 
 // ------------------------------------------------------------------ variants
+// A variant fixes, for one key class, the chunk-sort tile (NTS threads x ES
+// items) and the merge tile (NTM threads x EM items).
 struct Variant {
   void (*sort)(const Ws&, int, TileWork, unsigned, hipStream_t);
+  void (*partition)(const Ws&, int, int, TileWork, unsigned, hipStream_t);
   void (*merge)(const Ws&, int, int, TileWork, unsigned, hipStream_t);
   const void* sort_fn;
   const void* merge_fn;
   uint32_t T, P;
-  int nt;
+  int nts, ntm;
 };
 
-template <int NL, int NT, int ES, int EM>
+constexpr int kPartNT = 256;
+
+template <int NL, int NTS, int ES, int NTM, int EM, int MM = 0>
 struct V {
   static void sort(const Ws& w, int c, TileWork tw, unsigned grid, hipStream_t s) {
-    sw::k_sort_tiles<NL, NT, ES><<<grid, NT, 0, s>>>(w, c, tw);
+    sw::k_sort_tiles<NL, NTS, ES, MM><<<grid, NTS, 0, s>>>(w, c, tw);
+  }
+  static void partition(const Ws& w, int c, int l, TileWork tw, unsigned grid, hipStream_t s) {
+    sw::k_partition<NL, kPartNT><<<grid, kPartNT, 0, s>>>(w, c, l, tw, (uint32_t)(NTM * EM));
   }
   static void merge(const Ws& w, int c, int l, TileWork tw, unsigned grid, hipStream_t s) {
-    sw::k_merge<NL, NT, EM><<<grid, NT, 0, s>>>(w, c, l, tw);
+    sw::k_merge<NL, NTM, EM, MM><<<grid, NTM, 0, s>>>(w, c, l, tw);
   }
   static Variant get() {
-    return Variant{sort, merge, (const void*)sw::k_sort_tiles<NL, NT, ES>, (const void*)sw::k_merge<NL, NT, EM>,
-                   (uint32_t)(NT * ES), (uint32_t)(NT * EM), NT};
+    static_assert(NTM * EM >= (int)sw::kMinMergeTile, "merge tile below the split-array sizing");
+    static_assert(NTM * EM <= 2 * NTS * ES, "merge tile must divide a pair of sorted tiles");
+    return Variant{sort, partition, merge, (const void*)sw::k_sort_tiles<NL, NTS, ES, MM>,
+                   (const void*)sw::k_merge<NL, NTM, EM, MM>, (uint32_t)(NTS * ES), (uint32_t)(NTM * EM), NTS, NTM};
   }
 };
 
-constexpr int kMaxVariants = 2;
+// The last template argument picks the register merge: 0 serial, 1 bitonic.
+constexpr int kMaxVariants = 6;
 const Variant* variants(int c, int* count) {
-  static const Variant v0[] = {V<0, 256, 16, 16>::get(), V<0, 256, 8, 8>::get()};
-  static const Variant v1[] = {V<1, 256, 16, 16>::get(), V<1, 256, 8, 8>::get()};
-  static const Variant v2[] = {V<2, 256, 16, 16>::get(), V<2, 256, 8, 8>::get()};
-  static const Variant v3[] = {V<4, 256, 16, 16>::get(), V<4, 256, 8, 8>::get()};
+  static const Variant v0[] = {V<0, 256, 16, 256, 16, 0>::get(), V<0, 256, 8, 256, 8, 0>::get(),
+                               V<0, 512, 16, 256, 16, 0>::get(), V<0, 512, 16, 256, 8, 0>::get(),
+                               V<0, 512, 16, 256, 16, 1>::get(), V<0, 512, 16, 256, 8, 1>::get()};
+  static const Variant v1[] = {V<1, 256, 16, 256, 16, 0>::get(), V<1, 256, 8, 256, 8, 0>::get(),
+                               V<1, 512, 16, 256, 8, 0>::get(), V<1, 512, 16, 256, 16, 0>::get(),
+                               V<1, 512, 16, 256, 8, 1>::get(), V<1, 256, 8, 256, 8, 1>::get()};
+  static const Variant v2[] = {V<2, 256, 16, 256, 16, 0>::get(), V<2, 256, 8, 256, 8, 0>::get(),
+                               V<2, 256, 8, 256, 16, 0>::get(), V<2, 256, 8, 256, 8, 1>::get()};
+  static const Variant v3[] = {V<4, 256, 16, 256, 16, 0>::get(), V<4, 256, 8, 256, 8, 0>::get(),
+                               V<4, 128, 16, 128, 16, 0>::get()};
   static const Variant* all[] = {v0, v1, v2, v3};
-  *count = kMaxVariants;
+  static const int counts[] = {6, 6, 4, 3};
+  *count = counts[c];
   return all[c];
 }
 
@@ -111,8 +129,8 @@ int device_info(DevInfo** out) {
       int nv;
       const Variant* vs = variants(c, &nv);
       for (int v = 0; v < nv; ++v) {
-        HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(&d.occ_sort[c][v], vs[v].sort_fn, vs[v].nt, 0));
-        HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(&d.occ_merge[c][v], vs[v].merge_fn, vs[v].nt, 0));
+        HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(&d.occ_sort[c][v], vs[v].sort_fn, vs[v].nts, 0));
+        HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(&d.occ_merge[c][v], vs[v].merge_fn, vs[v].ntm, 0));
         d.occ_sort[c][v] = std::max(d.occ_sort[c][v], 1);
         d.occ_merge[c][v] = std::max(d.occ_merge[c][v], 1);
       }
@@ -127,8 +145,8 @@ int device_info(DevInfo** out) {
 
 // ------------------------------------------------------------------ layout
 struct Layout {
-  uint64_t Nmax = 0, Dmax = 0, Bmax = 0, Smax = 0, SBmax = 0;
-  size_t o_hdr, o_doc_off, o_doc_blk, o_cnt, o_seg_n, o_seg_base, o_segcnt, o_sorted, o_st, o_mt;
+  uint64_t Nmax = 0, Dmax = 0, Bmax = 0, Smax = 0, SBmax = 0, rec_stride = 0;
+  size_t o_hdr, o_doc_off, o_doc_blk, o_cnt, o_seg_n, o_seg_base, o_segcnt, o_sorted, o_st, o_mt, o_rec;
   size_t o_a[4], o_ai, o_b[4], o_bi;
   size_t total = 0;
 };
@@ -158,6 +176,8 @@ bool make_layout(uint64_t Nmax, uint64_t Dmax, Layout& L) {
   L.o_sorted = take(4 * L.Smax);
   L.o_st = take(4 * (L.Smax + sw::kNClass));
   L.o_mt = take(4 * (L.Smax + sw::kNClass));
+  L.rec_stride = Nmax / sw::kMinMergeTile + L.Smax + 2;
+  L.o_rec = take(16 * sw::kNClass * L.rec_stride);
   for (int q = 0; q < 4; ++q) L.o_a[q] = take(8 * N1);
   L.o_ai = take(4 * N1);
   for (int q = 0; q < 4; ++q) L.o_b[q] = take(8 * N1);
@@ -194,6 +214,8 @@ Ws make_ws(void* base, const Layout& L, const sw_config& cfg) {
   w.sorted = (uint32_t*)(p + L.o_sorted);
   w.st = (uint32_t*)(p + L.o_st);
   w.mt = (uint32_t*)(p + L.o_mt);
+  w.rec = (uint4*)(p + L.o_rec);
+  w.rec_stride = (uint32_t)L.rec_stride;
   for (int q = 0; q < 4; ++q) {
     w.a.k[q] = (uint64_t*)(p + L.o_a[q]);
     w.b.k[q] = (uint64_t*)(p + L.o_b[q]);
@@ -218,12 +240,14 @@ Ws make_ws(void* base, const Layout& L, const sw_config& cfg) {
 // ------------------------------------------------------------------ profiling
 enum KernelId {
   K_BEGIN, K_DOC_PLAN, K_HIST, K_SCAN, K_SEGMENTS, K_SEG_COUNT, K_SEG_SCATTER, K_TILE_PREFIX, K_SCATTER,
-  K_SORT0, K_SORT1, K_SORT2, K_SORT3, K_MERGE0, K_MERGE1, K_MERGE2, K_MERGE3, K_COUNT
+  K_SORT0, K_SORT1, K_SORT2, K_SORT3, K_MERGE0, K_MERGE1, K_MERGE2, K_MERGE3,
+  K_PART0, K_PART1, K_PART2, K_PART3, K_COUNT
 };
 const char* const kKernelNames[K_COUNT] = {
     "begin", "doc_plan", "hist", "scan_rows", "segments", "seg_count", "seg_scatter", "tile_prefix",
     "scatter_pack", "sort_tiles_c0", "sort_tiles_c1", "sort_tiles_c2", "sort_tiles_c3",
-    "merge_c0", "merge_c1", "merge_c2", "merge_c3"};
+    "merge_c0", "merge_c1", "merge_c2", "merge_c3",
+    "partition_c0", "partition_c1", "partition_c2", "partition_c3"};
 
 struct ProfRec {
   int kid;
@@ -272,7 +296,7 @@ struct ProfScope {
 // ------------------------------------------------------------------ launch sequence
 struct Grids {
   unsigned words, docs, segs;
-  unsigned sort[sw::kNClass], merge[sw::kNClass];
+  unsigned sort[sw::kNClass], merge[sw::kNClass], part[sw::kNClass];
   int levels[sw::kNClass];
   const Variant* var[sw::kNClass];
 };
@@ -295,14 +319,57 @@ int make_grids(const Ws& w, const sw_config& cfg, Grids& g) {
     const uint64_t maxtiles_m = (uint64_t)w.Nmax / vs[v].P + w.Smax;
     g.sort[c] = clampg(maxtiles_s, cus * (uint64_t)d->occ_sort[c][v]);
     g.merge[c] = clampg(maxtiles_m, cus * (uint64_t)d->occ_merge[c][v]);
+    g.part[c] = clampg((maxtiles_m + kPartNT / 64 - 1) / (kPartNT / 64), cus * 8);
     g.levels[c] = (int)sw::levels_for(w.Nmax, vs[v].T);
   }
   return SW_OK;
 }
 
+// Side streams and events for running the four key classes concurrently:
+// after the scatter the classes share nothing, so each class's chain (chunk
+// sort, then partition + merge per level) goes on its own stream, forked
+// from and joined back into the caller's stream.  Under graph capture the
+// chains become parallel branches of the graph.
+struct Fork {
+  hipStream_t side[sw::kNClass] = {};   // side[0] unused: class 0 stays on the main stream
+  hipEvent_t fork = nullptr;
+  hipEvent_t join[sw::kNClass] = {};
+  bool ready = false;
+};
+
+int fork_init(Fork& f) {
+  if (f.ready) return SW_OK;
+  for (int c = 1; c < sw::kNClass; ++c) HIP_TRY(hipStreamCreateWithFlags(&f.side[c], hipStreamNonBlocking));
+  HIP_TRY(hipEventCreateWithFlags(&f.fork, hipEventDisableTiming));
+  for (int c = 1; c < sw::kNClass; ++c) HIP_TRY(hipEventCreateWithFlags(&f.join[c], hipEventDisableTiming));
+  f.ready = true;
+  return SW_OK;
+}
+
+void fork_free(Fork& f) {
+  if (!f.ready) return;
+  for (int c = 1; c < sw::kNClass; ++c) {
+    if (f.side[c]) (void)hipStreamSynchronize(f.side[c]);
+  }
+  for (int c = 1; c < sw::kNClass; ++c) {
+    if (f.side[c]) (void)hipStreamDestroy(f.side[c]);
+    if (f.join[c]) (void)hipEventDestroy(f.join[c]);
+  }
+  if (f.fork) (void)hipEventDestroy(f.fork);
+  f = Fork();
+}
+
+bool profiling_on() {
+  std::lock_guard<std::mutex> lk(g_prof_mu);
+  return g_prof_on;
+}
+
 // Everything after k_begin.  With `through_scatter` only the pre-pass and the
 // scatter are enqueued (the per-bucket-launch form continues on the host).
-int enqueue_body(const Ws& w, const Grids& g, hipStream_t s, bool capture, bool through_scatter) {
+// With a Fork the key classes run on parallel streams; without one (or while
+// profiling, so that every kernel is timed alone) they run one after another.
+int enqueue_body(const Ws& w, const Grids& g, hipStream_t s, bool capture, bool through_scatter,
+                 Fork* fork = nullptr) {
   {
     ProfScope p(K_DOC_PLAN, s, capture);
     sw::k_doc_plan<1024><<<1, 1024, 0, s>>>(w);
@@ -342,15 +409,31 @@ int enqueue_body(const Ws& w, const Grids& g, hipStream_t s, bool capture, bool 
     sw::k_scatter_pack<kNT><<<g.words, kNT, 0, s>>>(w);
   }
   if (through_scatter) return SW_OK;
+  const bool par = fork && fork->ready && !(!capture && profiling_on());
+  if (par) {
+    HIP_TRY(hipEventRecord(fork->fork, s));
+    for (int c = 1; c < sw::kNClass; ++c) HIP_TRY(hipStreamWaitEvent(fork->side[c], fork->fork, 0));
+  }
   const TileWork none{0, 0, 0, 0};
   for (int c = 0; c < sw::kNClass; ++c) {
+    hipStream_t cs = (par && c > 0) ? fork->side[c] : s;
     {
-      ProfScope p(K_SORT0 + c, s, capture);
-      g.var[c]->sort(w, c, none, g.sort[c], s);
+      ProfScope p(K_SORT0 + c, cs, capture);
+      g.var[c]->sort(w, c, none, g.sort[c], cs);
     }
     for (int l = 0; l < g.levels[c]; ++l) {
-      ProfScope p(K_MERGE0 + c, s, capture);
-      g.var[c]->merge(w, c, l, none, g.merge[c], s);
+      {
+        ProfScope p(K_PART0 + c, cs, capture);
+        g.var[c]->partition(w, c, l, none, g.part[c], cs);
+      }
+      ProfScope p(K_MERGE0 + c, cs, capture);
+      g.var[c]->merge(w, c, l, none, g.merge[c], cs);
+    }
+  }
+  if (par) {
+    for (int c = 1; c < sw::kNClass; ++c) {
+      HIP_TRY(hipEventRecord(fork->join[c], fork->side[c]));
+      HIP_TRY(hipStreamWaitEvent(s, fork->join[c], 0));
     }
   }
   HIP_TRY(hipGetLastError());
@@ -377,6 +460,11 @@ int read_status(const void* ws, hipStream_t s) {
   return status_to_code(st);
 }
 
+// Side streams of the eager path, one set per device; the mutex keeps each
+// fork (event record + waits) of concurrent callers consistent.
+std::mutex g_fork_mu;
+Fork g_fork[64];
+
 int run_eager(const uint8_t* chars, const uint32_t* offsets, const uint32_t* doc_offsets, uint32_t n_docs,
               uint32_t n_words, uint32_t* out_perm, uint32_t* out_boff, void* ws, const Layout& L,
               hipStream_t s) {
@@ -388,7 +476,12 @@ int run_eager(const uint8_t* chars, const uint32_t* offsets, const uint32_t* doc
   RunDesc d{chars, offsets, doc_offsets, out_perm, out_boff, n_words, n_docs};
   rc = enqueue_begin(w, d, s);
   if (rc) return rc;
-  return enqueue_body(w, g, s, false, false);
+  int dev = 0;
+  HIP_TRY(hipGetDevice(&dev));
+  std::lock_guard<std::mutex> lk(g_fork_mu);
+  Fork& f = g_fork[dev & 63];
+  if ((rc = fork_init(f))) return rc;
+  return enqueue_body(w, g, s, false, false, &f);
 }
 
 // Library-owned workspace of the simple form, one per device.
@@ -405,7 +498,7 @@ Cache g_cache[64];
 extern "C" {
 
 const char* sort_words_last_error(void) { return g_err.c_str(); }
-const char* sort_words_version(void) { return "sortwords-gfx950 0.1"; }
+const char* sort_words_version(void) { return "sortwords-gfx950 0.4"; }
 
 size_t sort_words_workspace_size(uint32_t max_words, uint32_t max_docs) {
   Layout L;
@@ -510,9 +603,14 @@ int sort_words_plain(const uint8_t* chars, const uint32_t* offsets, const uint32
       ProfScope p(K_SORT0 + c, s, false);
       v.sort(w, c, tw, (n + v.T - 1) / v.T, s);
     }
+    const uint32_t mtiles = (n + v.P - 1) / v.P;
     for (uint32_t l = 0; l < m; ++l) {
+      {
+        ProfScope p(K_PART0 + c, s, false);
+        v.partition(w, c, (int)l, tw, (mtiles + kPartNT / 64 - 1) / (kPartNT / 64), s);
+      }
       ProfScope p(K_MERGE0 + c, s, false);
-      v.merge(w, c, (int)l, tw, (n + v.P - 1) / v.P, s);
+      v.merge(w, c, (int)l, tw, mtiles, s);
     }
   }
   HIP_TRY(hipGetLastError());
@@ -529,6 +627,7 @@ struct sw_plan {
   bool own_stream = false;
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
+  Fork fork;
 };
 
 static void plan_free(sw_plan* p) {
@@ -536,6 +635,7 @@ static void plan_free(sw_plan* p) {
   if (p->s) (void)hipStreamSynchronize(p->s);
   if (p->exec) (void)hipGraphExecDestroy(p->exec);
   if (p->graph) (void)hipGraphDestroy(p->graph);
+  fork_free(p->fork);
   if (p->ws) (void)hipFree(p->ws);
   if (p->own_stream && p->s) (void)hipStreamDestroy(p->s);
   delete p;
@@ -571,11 +671,15 @@ int sw_plan_create(uint32_t max_words, uint32_t max_docs, void* stream, sw_plan*
     plan_free(p);
     return rc;
   }
+  if ((rc = fork_init(p->fork))) {
+    plan_free(p);
+    return rc;
+  }
   if (hipStreamBeginCapture(p->s, hipStreamCaptureModeThreadLocal) != hipSuccess) {
     plan_free(p);
     return fail(SW_ERR_HIP, "sw_plan_create: stream capture failed to begin");
   }
-  rc = enqueue_body(p->w, p->g, p->s, true, false);
+  rc = enqueue_body(p->w, p->g, p->s, true, false, &p->fork);
   hipGraph_t graph = nullptr;
   const hipError_t ec = hipStreamEndCapture(p->s, &graph);
   p->graph = graph;

@@ -1,0 +1,148 @@
+"""Autotuner for the chunk size and tile variant of each key class.
+
+For every key class it times each compiled tile variant with each chunk size
+on a real workload (kernel time of that class's chunk sort, partition and
+merge levels, from the library's HIP-event timing), checks that every
+candidate returns exactly the same permutation and bucket offsets as the
+first run, and keeps the fastest.  Results are cached in a JSON file keyed by
+GPU architecture, compute-unit count and library version, one entry per
+workload name.
+
+    python -m paper_1411_5283_amd.tune --workload c4
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+from . import NUM_CLASSES
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+CACHE = os.environ.get("SW_TUNE_CACHE", os.path.join(HERE, "tuned.json"))
+CHUNKS = (16, 32, 64, 128, 256)
+
+
+def device_key() -> str:
+    import torch
+    import paper_1411_5283_amd as sw
+    p = torch.cuda.get_device_properties(torch.cuda.current_device())
+    arch = getattr(p, "gcnArchName", "unknown").split(":")[0]
+    return "%s/%dcu/%s" % (arch, p.multi_processor_count, sw.version())
+
+
+def _run_once(sw, chars, offs, docs, n, nd, perm, boff, ws, stream):
+    if docs is None:
+        sw.sort_words_ex(chars, offs, n, perm, boff, ws, stream)
+    else:
+        sw.sort_words_batch(chars, offs, docs, nd, perm, boff, ws, stream)
+
+
+def tune(wl, name: str, reps: int = 2, chunks=CHUNKS, log=print) -> dict:
+    import torch
+    import paper_1411_5283_amd as sw
+
+    dev = torch.device("cuda", torch.cuda.current_device())
+    stream = torch.cuda.Stream(device=dev)
+    torch.cuda.set_stream(stream)
+    chars, offs, docs = sw.device_words(wl, dev)
+    n, nd = wl.n, wl.n_docs
+    perm = torch.empty(max(n, 1), dtype=torch.int32, device=dev)
+    boff = torch.empty(nd * 34, dtype=torch.int32, device=dev)
+    ws = torch.empty(sw.sort_words_workspace_size(n, nd), dtype=torch.uint8, device=dev)
+    start = sw.get_config()
+    best = {"chunk": list(start["chunk"]), "variant": list(start["variant"])}
+
+    _run_once(sw, chars, offs, docs, n, nd, perm, boff, ws, stream)
+    sw.sort_words_status(ws, stream)
+    ref_perm, ref_boff = perm.clone(), boff.clone()
+    trials = []
+    for c in range(NUM_CLASSES):
+        best_t = None
+        for v in range(sw.num_variants(c)):
+            for C in chunks:
+                cfg = {"chunk": list(best["chunk"]), "variant": list(best["variant"])}
+                cfg["chunk"][c], cfg["variant"][c] = C, v
+                sw.set_config(**cfg)
+                _run_once(sw, chars, offs, docs, n, nd, perm, boff, ws, stream)   # warm
+                sw.profile_reset()
+                sw.profile_enable(True)
+                for _ in range(reps):
+                    _run_once(sw, chars, offs, docs, n, nd, perm, boff, ws, stream)
+                torch.cuda.synchronize()
+                prof = sw.profile_read()
+                sw.profile_enable(False)
+                sw.sort_words_status(ws, stream)
+                same = bool(torch.equal(perm, ref_perm) and torch.equal(boff, ref_boff))
+                if not same:
+                    raise RuntimeError("class %d variant %d chunk %d changed the result" % (c, v, C))
+                ms = sum(prof.get(k, (0, 0.0))[1] for k in
+                         ("sort_tiles_c%d" % c, "partition_c%d" % c, "merge_c%d" % c)) / reps
+                trials.append({"class": c, "variant": v, "chunk": C, "ms": ms})
+                log("class %d variant %d chunk %4d: %.4f ms" % (c, v, C, ms))
+                if best_t is None or ms < best_t:
+                    best_t = ms
+                    bc, bv = C, v
+        best["chunk"][c], best["variant"][c] = bc, bv
+        sw.set_config(**best)
+    total = 0.0
+    sw.profile_reset()
+    sw.profile_enable(True)
+    for _ in range(reps):
+        _run_once(sw, chars, offs, docs, n, nd, perm, boff, ws, stream)
+    torch.cuda.synchronize()
+    total = sum(v[1] for v in sw.profile_read().values()) / reps
+    sw.profile_enable(False)
+    return {"workload": name, "config": best, "kernel_ms": total, "trials": trials,
+            "when": time.strftime("%Y-%m-%d %H:%M:%S")}
+
+
+def load_cache(path: str = CACHE) -> dict:
+    try:
+        with open(path) as f:
+            return json.load(f)
+    except (OSError, ValueError):
+        return {}
+
+
+def save(result: dict, path: str = CACHE) -> None:
+    cache = load_cache(path)
+    cache.setdefault(device_key(), {})[result["workload"]] = result
+    tmp = path + ".tmp"
+    with open(tmp, "w") as f:
+        json.dump(cache, f, indent=1, sort_keys=True)
+    os.replace(tmp, path)
+
+
+def apply(workload: str, path: str = CACHE) -> dict | None:
+    """Set the library's config to the cached best for this device and workload."""
+    import paper_1411_5283_amd as sw
+    entry = load_cache(path).get(device_key(), {}).get(workload)
+    if not entry:
+        return None
+    return sw.set_config(**entry["config"])
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--workload", default="c4")
+    ap.add_argument("--scale", type=float, default=1.0)
+    ap.add_argument("--reps", type=int, default=2)
+    ap.add_argument("--out", default=CACHE)
+    args = ap.parse_args()
+    from . import wordgen
+    cfg = int(args.workload.lstrip("c"))
+    wl = wordgen.config(cfg, args.scale)
+    print("tuning on %s (%d words, %d documents)" % (args.workload, wl.n, wl.n_docs), flush=True)
+    res = tune(wl, args.workload, reps=args.reps, log=lambda *a: print(*a, flush=True))
+    save(res, args.out)
+    print(json.dumps({"workload": res["workload"], "config": res["config"], "kernel_ms": res["kernel_ms"]}),
+          flush=True)
+
+
+if __name__ == "__main__":
+    sys.exit(main())

@@ -55,6 +55,16 @@ def _same(got, exp, what):
     assert np.array_equal(gb, eb), "%s: bucket offsets differ" % what
 
 
+@pytest.mark.parametrize("variant", [0, 1, 2, 3, 4, 5])
+def test_long_segments_every_variant(gpu, oracle_mod, default_config, variant):
+    # 1.5M words over few lengths: many merge levels and many tiles per workgroup
+    wl = wordgen.single(1_500_000, 40_000, 1.1, 20, seed=5)
+    _say("case long segments variant=%d n=%d" % (variant, wl.n))
+    gpu.set_config(chunk=[16, 32, 64, 16],
+                   variant=[min(variant, gpu.num_variants(c) - 1) for c in range(4)])
+    _same(gpu.sort_wordlist(wl), _expect(oracle_mod, wl, bubble=False), "long variant %d" % variant)
+
+
 def test_config1_bit_exact(gpu, oracle_mod):
     wl = wordgen.config(1)
     _say("case config1 n=%d" % wl.n)
@@ -69,12 +79,13 @@ def test_config2_chunk1024_bit_exact(gpu, oracle_mod, default_config):
 
 
 @pytest.mark.parametrize("chunk", [16, 32, 64, 128, 256, 512, 1024])
-@pytest.mark.parametrize("variant", [0, 1])
+@pytest.mark.parametrize("variant", [0, 1, 2, 3, 4, 5])
 def test_chunk_and_variant_sweep(gpu, oracle_mod, default_config, chunk, variant):
     # several tiles, merge levels and a ragged tail in every class
     wl = wordgen.single(41_000, 3000, 1.0, 32, seed=77)
     _say("case sweep chunk=%d variant=%d" % (chunk, variant))
-    gpu.set_config(chunk=[chunk] * 4, variant=[variant] * 4)
+    gpu.set_config(chunk=[chunk] * 4,
+                   variant=[min(variant, gpu.num_variants(c) - 1) for c in range(4)])
     _same(gpu.sort_wordlist(wl), _expect(oracle_mod, wl, bubble=False),
           "chunk %d variant %d" % (chunk, variant))
 
