@@ -32,6 +32,8 @@ WORKLOADS = {
     "c2": (2, "250k words, 20k-word Zipf(1.0) vocabulary, lengths 1-20, odd-even chunks of 1024"),
     "c3": (3, "4096 documents of 100-50k words (log-uniform), 50k-word Zipf(1.1) vocabulary, lengths 1-20"),
     "c4": (4, "64M words, 1M-word Zipf(1.1) vocabulary, lengths 1-24"),
+    "c5": (5, "serving: Poisson arrivals, request sizes lognormal (median 20k words, 1k-1M), "
+              "20k-word Zipf(1.0) vocabulary, lengths 1-20, 8 GiB HBM budget"),
 }
 CSRC = [os.path.join(ROOT, "paper_1411_5283_amd", "csrc", f)
         for f in ("sw_device.hpp", "sw_kernels.hpp", "sw_runtime.hip")]
@@ -177,6 +179,89 @@ def hbm_traffic(dominant_kernel: str):
     return None if k is None else k.get("bytes_per_launch")
 
 
+# ------------------------------------------------------------------ serving
+def serve_bench(args, sw, wordgen, torch):
+    """Continuous batching under Poisson arrivals (see paper_1411_5283_amd/serve.py)."""
+    from paper_1411_5283_amd.serve import GpuExecutor, SortServer
+    n_warm, n_meas = args.serve_warmup, args.serve_requests
+    log("generating %d requests" % (n_warm + n_meas))
+    reqs = list(wordgen.serving_requests(n_warm + n_meas))
+    warm, meas = reqs[:n_warm], reqs[n_warm:]
+    ex = GpuExecutor(slots=args.serve_slots, max_batch_words=args.serve_batch_words,
+                     max_batch_docs=args.serve_batch_docs, max_batch_chars=args.serve_batch_words * 8)
+    budget = (8 << 30) - ex.fixed_bytes()
+
+    def run(rset, rate):
+        srv = SortServer(ex, budget_bytes=budget, max_batch_words=args.serve_batch_words,
+                         max_batch_docs=args.serve_batch_docs, min_batch_words=args.serve_min_words,
+                         max_wait_s=args.serve_max_wait_ms * 1e-3)
+        srv.start()
+        rng = np.random.default_rng(1)
+        t0 = time.perf_counter()
+        futs = []
+        if rate is None:                      # closed burst: everything arrives at once
+            futs = [srv.submit(r.chars, r.offsets) for r in rset]
+        else:
+            t = t0
+            for r in rset:
+                t += rng.exponential(1.0 / rate)
+                wait = t - time.perf_counter()
+                if wait > 0:
+                    time.sleep(wait)          # sleeping releases the interpreter to the server thread
+                futs.append(srv.submit(r.chars, r.offsets))
+        for f in futs:
+            f.result(timeout=300)
+        t1 = time.perf_counter()
+        srv.stop()
+        words = sum(r.n for r in rset)
+        return {"requests": len(rset), "words": words, "seconds": t1 - t0,
+                "mwords_s": words / (t1 - t0) / 1e6, "p50_ms": srv.stats.percentile(50) * 1e3,
+                "p99_ms": srv.stats.percentile(99) * 1e3, "batches": srv.stats.batches,
+                "max_bytes_in_use": srv.stats.max_bytes_in_use}
+
+    sat = run(warm, None)
+    log("saturation (closed burst): %s" % sat)
+    sat_rate = sat["requests"] / sat["seconds"]
+    points = []
+    for frac in (0.5, 0.8, 1.0):
+        r = run(meas, frac * sat_rate)
+        r["lambda_req_s"] = frac * sat_rate
+        r["lambda_frac"] = frac
+        points.append(r)
+        log("lambda %.1f x saturation: %s" % (frac, r))
+    ex.close()
+    main_pt = points[1]
+    cpu = None
+    if not args.no_cpu_baseline:
+        import oracle
+        oracle.build(force=False)
+        t0 = time.perf_counter()
+        nw = 0
+        for r in meas:
+            oracle.oracle_def(r.chars, r.offsets)
+            nw += r.n
+            if time.perf_counter() - t0 > 10:
+                break
+        dt = time.perf_counter() - t0
+        cpu = {"value": nw / dt / 1e6, "unit": "Mwords/s", "cores": 1, "kind": "oracle",
+               "sample": "oracle_def on measured requests in arrival order until 10 s (%d words), "
+                         "one thread" % nw}
+    sizes = np.array([r.n for r in meas])
+    return {
+        "metric": METRIC, "value": main_pt["mwords_s"], "unit": "Mwords/s", "n_gpus": 1,
+        "steps": len(meas), "warmup": len(warm), "ms_per_step": main_pt["seconds"] * 1e3 / len(meas),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "u64",
+        "data": "synthetic",
+        "config": {"workload": "c5: " + WORKLOADS["c5"][1], "request_median": float(np.median(sizes)),
+                   "request_mean": float(sizes.mean()), "slots": args.serve_slots,
+                   "max_batch_words": args.serve_batch_words, "budget_bytes": budget,
+                   "min_batch_words": args.serve_min_words, "max_wait_ms": args.serve_max_wait_ms,
+                   "value_at": "lambda = 0.8 x closed-burst saturation rate"},
+        "serving": {"saturation": sat, "points": points},
+        "roofline": None, "cpu_baseline": cpu, "kernel_source": kernel_source_hash(),
+    }
+
+
 # ------------------------------------------------------------------ main
 def main():
     ap = argparse.ArgumentParser()
@@ -190,6 +275,15 @@ def main():
     ap.add_argument("--no-check", action="store_true")
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--untuned", action="store_true", help="ignore the autotuner cache")
+    ap.add_argument("--serial", action="store_true",
+                    help="run the key classes one after another (for per-kernel profiling)")
+    ap.add_argument("--serve-warmup", type=int, default=200)
+    ap.add_argument("--serve-requests", type=int, default=1000)
+    ap.add_argument("--serve-slots", type=int, default=2)
+    ap.add_argument("--serve-batch-words", type=int, default=1 << 22)
+    ap.add_argument("--serve-batch-docs", type=int, default=256)
+    ap.add_argument("--serve-min-words", type=int, default=1 << 20)
+    ap.add_argument("--serve-max-wait-ms", type=float, default=1.0)
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py: this build runs on one GPU only; --gpus %d is not supported "
@@ -200,6 +294,10 @@ def main():
     import paper_1411_5283_amd as sw
     from paper_1411_5283_amd import wordgen
 
+    if args.workload == "c5":
+        torch.cuda.set_device(0)
+        print(json.dumps(serve_bench(args, sw, wordgen, torch)), flush=True)
+        return
     cfg_no, desc = WORKLOADS[args.workload]
     log("generating workload %s: %s" % (args.workload, desc))
     t0 = time.perf_counter()
@@ -211,6 +309,8 @@ def main():
     elif not args.untuned:
         from paper_1411_5283_amd import tune
         tuned = tune.apply(args.workload)
+    if args.serial:
+        sw.set_config(flags=sw.FLAG_SERIAL_CLASSES)
     cfg = sw.get_config()
     tiles = [sw.variant_tiles(c, cfg["variant"][c])[0] for c in range(4)]
 
@@ -339,7 +439,7 @@ def main():
         "config": {"workload": "%s: %s" % (args.workload, desc), "n_words": n, "n_docs": nd,
                    "form": "graph-captured plan (batched, device-side segment scheduling)",
                    "chunk": cfg["chunk"], "variant": cfg["variant"], "sort_tile": tiles,
-                   "tuned": tuned is not None},
+                   "tuned": tuned is not None, "classes": "serial" if args.serial else "parallel streams"},
         "eager_ms_per_step": eager_ms,
         "per_bucket_launch": plain,
         "batched_over_plain": (value / plain["value"]) if plain else None,

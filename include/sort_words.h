@@ -120,6 +120,14 @@ int sort_words_plain(const uint8_t *chars, const uint32_t *offsets,
  * `workspace` for the last call enqueued with it (SW_OK or an error). */
 int sort_words_status(const void *workspace, void *stream);
 
+/* Asynchronous status read for callers that must not block: enqueues on
+ * `stream` a copy of the device status word of the last call enqueued with
+ * `workspace` into *status_dst (pinned host or device memory, caller-owned,
+ * 4 bytes); once the stream has reached it, sort_words_decode_status() turns
+ * the word into an sw_status.  Returns SW_OK or a host-side error. */
+int sort_words_status_async(const void *workspace, uint32_t *status_dst, void *stream);
+int sort_words_decode_status(uint32_t status_word);
+
 /* Persistent plan for repeated batched sorts (serving, benchmarks): owns its
  * workspace and a captured HIP graph of the whole pass, so one run is one
  * small descriptor kernel plus one hipGraphLaunch on the plan's stream.
@@ -138,6 +146,8 @@ int sw_plan_run(sw_plan *plan, const uint8_t *chars, const uint32_t *offsets,
                 const uint32_t *doc_offsets, uint32_t n_docs, uint32_t n_words,
                 uint32_t *out_perm, uint32_t *out_bucket_offsets);
 int sw_plan_status(sw_plan *plan);
+/* sort_words_status_async for a plan (copy enqueued on the plan's stream). */
+int sw_plan_status_async(sw_plan *plan, uint32_t *status_dst);
 void sw_plan_destroy(sw_plan *plan);
 
 /* Tuning knobs, process-wide, read when work is enqueued (and when a plan's
@@ -148,7 +158,11 @@ void sw_plan_destroy(sw_plan *plan);
 typedef struct {
     uint32_t chunk[SW_NUM_CLASSES];
     uint32_t variant[SW_NUM_CLASSES];
+    uint32_t flags;   /* SW_FLAG_* */
 } sw_config;
+/* Run the key classes one after another on the caller's stream instead of on
+ * parallel streams (for per-kernel measurement; results are identical). */
+#define SW_FLAG_SERIAL_CLASSES 1u
 int sw_get_config(sw_config *out);
 int sw_set_config(const sw_config *cfg);
 /* Number of compiled variants of class c, and the chunk-sort tile (words per

@@ -35,8 +35,12 @@ class SortWordsError(RuntimeError):
         self.code = code
 
 
+FLAG_SERIAL_CLASSES = 1
+
+
 class sw_config(ctypes.Structure):
-    _fields_ = [("chunk", ctypes.c_uint32 * NUM_CLASSES), ("variant", ctypes.c_uint32 * NUM_CLASSES)]
+    _fields_ = [("chunk", ctypes.c_uint32 * NUM_CLASSES), ("variant", ctypes.c_uint32 * NUM_CLASSES),
+                ("flags", ctypes.c_uint32)]
 
 
 _lib = None
@@ -62,6 +66,9 @@ def lib() -> ctypes.CDLL:
         "sw_plan_create": ([u32, u32, vp, ctypes.POINTER(vp)], i32),
         "sw_plan_run": ([vp, vp, vp, vp, u32, u32, vp, vp], i32),
         "sw_plan_status": ([vp], i32),
+        "sw_plan_status_async": ([vp, vp], i32),
+        "sort_words_status_async": ([vp, vp, vp], i32),
+        "sort_words_decode_status": ([u32], i32),
         "sw_plan_destroy": ([vp], None),
         "sw_get_config": ([ctypes.POINTER(sw_config)], i32),
         "sw_set_config": ([ctypes.POINTER(sw_config)], i32),
@@ -83,8 +90,9 @@ def lib() -> ctypes.CDLL:
 
 
 EXPORTED = ("sort_words", "sort_words_workspace_size", "sort_words_ex", "sort_words_batch",
-            "sort_words_plain", "sort_words_status", "sw_plan_create", "sw_plan_run",
-            "sw_plan_status", "sw_plan_destroy", "sw_get_config", "sw_set_config",
+            "sort_words_plain", "sort_words_status", "sort_words_status_async",
+            "sort_words_decode_status", "sw_plan_create", "sw_plan_run",
+            "sw_plan_status", "sw_plan_status_async", "sw_plan_destroy", "sw_get_config", "sw_set_config",
             "sw_num_variants", "sw_variant_tiles", "sw_profile_enable", "sw_profile_reset",
             "sw_profile_read", "sort_words_last_error", "sort_words_version")
 
@@ -153,6 +161,15 @@ def sort_words_status_code(workspace, stream=None) -> int:
     return int(lib().sort_words_status(_ptr(workspace), _stream(stream)))
 
 
+def sort_words_status_async(workspace, status_dst, stream=None) -> int:
+    """Enqueue a copy of the device status word into status_dst (a 1-element int32 tensor)."""
+    return _check(lib().sort_words_status_async(_ptr(workspace), _ptr(status_dst), _stream(stream)))
+
+
+def decode_status(word: int) -> int:
+    return int(lib().sort_words_decode_status(int(word) & 0xFFFFFFFF))
+
+
 class Plan:
     """Graph-captured persistent plan (sw_plan_*)."""
 
@@ -174,6 +191,10 @@ class Plan:
     def status_code(self) -> int:
         return int(lib().sw_plan_status(self._h))
 
+    def status_async(self, status_dst) -> int:
+        """Enqueue a copy of the device status word into status_dst (1-element int32 tensor)."""
+        return _check(lib().sw_plan_status_async(self._h, _ptr(status_dst)))
+
     def close(self):
         if self._h:
             lib().sw_plan_destroy(self._h)
@@ -189,15 +210,16 @@ class Plan:
 def get_config() -> dict:
     c = sw_config()
     _check(lib().sw_get_config(ctypes.byref(c)))
-    return {"chunk": list(c.chunk), "variant": list(c.variant)}
+    return {"chunk": list(c.chunk), "variant": list(c.variant), "flags": int(c.flags)}
 
 
-def set_config(chunk=None, variant=None) -> dict:
+def set_config(chunk=None, variant=None, flags=None) -> dict:
     cur = get_config()
     c = sw_config()
     for k in range(NUM_CLASSES):
         c.chunk[k] = int((chunk if chunk is not None else cur["chunk"])[k])
         c.variant[k] = int((variant if variant is not None else cur["variant"])[k])
+    c.flags = int(flags if flags is not None else cur["flags"])
     _check(lib().sw_set_config(ctypes.byref(c)))
     return get_config()
 

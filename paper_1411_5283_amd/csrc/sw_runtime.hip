@@ -96,7 +96,7 @@ const Variant* variants(int c, int* count) {
 
 // ------------------------------------------------------------------ config
 std::mutex g_cfg_mu;
-sw_config g_cfg = {{64, 64, 64, 64}, {0, 0, 0, 0}};
+sw_config g_cfg = {{16, 16, 16, 16}, {0, 0, 0, 0}, 0};
 
 sw_config current_config() {
   std::lock_guard<std::mutex> lk(g_cfg_mu);
@@ -295,6 +295,7 @@ struct ProfScope {
 
 // ------------------------------------------------------------------ launch sequence
 struct Grids {
+  uint32_t flags;
   unsigned words, docs, segs;
   unsigned sort[sw::kNClass], merge[sw::kNClass], part[sw::kNClass];
   int levels[sw::kNClass];
@@ -307,6 +308,7 @@ int make_grids(const Ws& w, const sw_config& cfg, Grids& g) {
   if (rc) return rc;
   const uint64_t cus = (uint64_t)d->cus;
   auto clampg = [](uint64_t want, uint64_t cap) { return (unsigned)std::max<uint64_t>(1, std::min(want, cap)); };
+  g.flags = cfg.flags;
   g.words = clampg(w.Bmax, cus * (uint64_t)std::min(d->occ_hist, d->occ_scatter));
   g.docs = clampg((w.Dmax + 3) / 4, cus * 4);
   g.segs = clampg(w.SBmax, cus * 2);
@@ -409,7 +411,7 @@ int enqueue_body(const Ws& w, const Grids& g, hipStream_t s, bool capture, bool 
     sw::k_scatter_pack<kNT><<<g.words, kNT, 0, s>>>(w);
   }
   if (through_scatter) return SW_OK;
-  const bool par = fork && fork->ready && !(!capture && profiling_on());
+  const bool par = fork && fork->ready && !(!capture && profiling_on()) && !(g.flags & SW_FLAG_SERIAL_CLASSES);
   if (par) {
     HIP_TRY(hipEventRecord(fork->fork, s));
     for (int c = 1; c < sw::kNClass; ++c) HIP_TRY(hipStreamWaitEvent(fork->side[c], fork->fork, 0));
@@ -560,6 +562,15 @@ int sort_words_batch(const uint8_t* chars, const uint32_t* offsets, const uint32
   return run_eager(chars, offsets, doc_offsets, n_docs, 0, out_perm, out_bucket_offsets, workspace, L,
                    (hipStream_t)stream);
 }
+
+int sort_words_status_async(const void* workspace, uint32_t* status_dst, void* stream) {
+  if (!workspace || !status_dst) return fail(SW_ERR_INVALID_ARG, "sort_words_status_async: null argument");
+  HIP_TRY(hipMemcpyAsync(status_dst, &((const Header*)workspace)->status, sizeof(uint32_t), hipMemcpyDefault,
+                         (hipStream_t)stream));
+  return SW_OK;
+}
+
+int sort_words_decode_status(uint32_t status_word) { return status_to_code(status_word); }
 
 int sort_words_status(const void* workspace, void* stream) {
   if (!workspace) return fail(SW_ERR_INVALID_ARG, "sort_words_status: null workspace");
@@ -716,6 +727,12 @@ int sw_plan_run(sw_plan* p, const uint8_t* chars, const uint32_t* offsets, const
   return SW_OK;
 }
 
+int sw_plan_status_async(sw_plan* p, uint32_t* status_dst) {
+  if (!p || !status_dst) return fail(SW_ERR_INVALID_ARG, "sw_plan_status_async: null argument");
+  HIP_TRY(hipMemcpyAsync(status_dst, &((const Header*)p->ws)->status, sizeof(uint32_t), hipMemcpyDefault, p->s));
+  return SW_OK;
+}
+
 int sw_plan_status(sw_plan* p) {
   if (!p) return fail(SW_ERR_INVALID_ARG, "sw_plan_status: null plan");
   return read_status(p->ws, p->s);
@@ -741,6 +758,7 @@ int sw_set_config(const sw_config* cfg) {
     if (cfg->variant[c] >= (uint32_t)nv)
       return fail(SW_ERR_INVALID_ARG, "sw_set_config: variant[%d]=%u out of range", c, cfg->variant[c]);
   }
+  if (cfg->flags & ~SW_FLAG_SERIAL_CLASSES) return fail(SW_ERR_INVALID_ARG, "sw_set_config: unknown flags");
   std::lock_guard<std::mutex> lk(g_cfg_mu);
   g_cfg = *cfg;
   return SW_OK;

@@ -124,7 +124,8 @@ def apply(workload: str, path: str = CACHE) -> dict | None:
     entry = load_cache(path).get(device_key(), {}).get(workload)
     if not entry:
         return None
-    return sw.set_config(**entry["config"])
+    cfg = entry["config"]
+    return sw.set_config(chunk=cfg["chunk"], variant=cfg["variant"])
 
 
 def main():
