@@ -672,7 +672,9 @@ __global__ __launch_bounds__(NT) void k_sort_tiles(Ws w, int cls, TileWork tw) {
 #pragma unroll
     for (int r = 0; r < E; ++r) e[r] = tile.get(threadIdx.x * E + r);
     oddeven_chunks<NL, E>(e, C);
-    for (uint32_t R = C; R < (uint32_t)T; R <<= 1) {
+    // once one run covers every real item the rest of the tile is sentinels
+    // and already in place, so the merge rounds stop there
+    for (uint32_t R = C; R < (uint32_t)T && R < cnt; R <<= 1) {
       __syncthreads();
 #pragma unroll
       for (int r = 0; r < E; ++r) tile.put(threadIdx.x * E + r, e[r]);

@@ -1,0 +1,43 @@
+"""Host-side logic that needs no GPU."""
+import sys
+import os
+
+import numpy as np
+
+sys.path.insert(0, os.path.dirname(os.path.dirname(os.path.abspath(__file__))))
+import bench  # noqa: E402
+
+
+def test_big_endian_lanes_order_equals_byte_order():
+    """Equal-length byte strings zero-padded to whole 8-byte lanes compare like
+    memcmp when the lanes are compared as big-endian unsigned integers, most
+    significant lane first (the fixed-width key rows the GPU sorts)."""
+    rng = np.random.default_rng(14)
+    for L in (1, 3, 4, 5, 8, 9, 15, 16, 17, 24, 31, 32):
+        W = -(-L // 8) * 8
+        A = np.zeros((4000, W), np.uint8)
+        A[:, :L] = rng.integers(0, 256, (4000, L), dtype=np.uint8)
+        A[::7, :L] = A[1::7, :L][: A[::7].shape[0]]      # plenty of equal words
+        lanes = A.view(">u8")
+        by_bytes = sorted(range(len(A)), key=lambda i: (A[i].tobytes(), i))
+        by_lanes = sorted(range(len(A)), key=lambda i: (tuple(int(x) for x in lanes[i]), i))
+        assert by_bytes == by_lanes, L
+
+
+def test_class_of_length_and_element_bytes():
+    assert [bench.class_of_len(L) for L in (0, 4, 5, 8, 9, 16, 17, 32)] == [0, 0, 1, 1, 2, 2, 3, 3]
+    assert [bench.element_bytes(c) for c in range(4)] == [8, 12, 20, 36]
+
+
+def test_levels_and_byte_model():
+    assert bench.levels_for(1, 4096) == 0 and bench.levels_for(4096, 4096) == 0
+    assert bench.levels_for(4097, 4096) == 1 and bench.levels_for(8192, 4096) == 1
+    assert bench.levels_for(8193, 4096) == 2
+    fam = bench.algorithmic_bytes([(3, 10000), (6, 100)], [4096] * 4)
+    # class 0 segment of 10000: m = 2 levels; chunk sort reads 8 and writes 8
+    assert fam["sort_tiles_c0"] == 16 * 10000
+    assert fam["merge_c0"] == (8 + 8) * 10000 + (8 + 4) * 10000
+    # class 1 segment of 100 fits one tile: finished by the chunk sort
+    assert fam["sort_tiles_c1"] == (12 + 4) * 100 and "merge_c1" not in fam
+    assert fam["hist"] == 4 * 10100
+    assert fam["scatter_pack"] == (4 + 3 + 8) * 10000 + (4 + 6 + 12) * 100
