@@ -362,20 +362,44 @@ __device__ inline void load_be_lanes(const uint8_t* p, uint32_t L, uint64_t (&la
   }
 }
 
+// Big-endian lanes of an L-byte word whose first byte is byte `pos` of a
+// dword array held in LDS (pos counts from the array's first byte).
+template <int NQ>
+__device__ inline void lds_be_lanes(const uint32_t* dw, uint32_t pos, uint32_t L, uint64_t (&lane)[NQ]) {
+  const uint32_t s = pos & 3;
+  const uint32_t* base = dw + (pos >> 2);
+  const uint32_t nd = L ? (s + L + 3) >> 2 : 0u;
+  uint32_t wv[2 * NQ + 1];
+#pragma unroll
+  for (int j = 0; j < 2 * NQ + 1; ++j) wv[j] = (uint32_t)j < nd ? __builtin_bswap32(base[j]) : 0u;
+#pragma unroll
+  for (int q = 0; q < NQ; ++q) {
+    const uint64_t hi = ((uint64_t)wv[2 * q] << 32) | wv[2 * q + 1];
+    uint64_t v = s ? (hi << (8 * s)) | (uint64_t)(wv[2 * q + 2] >> (32 - 8 * s)) : hi;
+    const int rem = (int)L - 8 * q;
+    v = rem >= 8 ? v : (rem <= 0 ? 0ull : (v & (~0ull << (64 - 8 * rem))));
+    lane[q] = v;
+  }
+}
+
 // ---------------------------------------------------------------- k_scatter_pack
 // Stable scatter of every word into its (document, length) segment, packed
-// into key lanes.  Pass 1: the rank of a word among the words of the same
-// length before it in the block (per wave with ballots, a running count per
-// wave carries ranks across iterations) gives its slot in the block's
-// length-sorted order; LDS records which word holds each slot.  Pass 2 walks
-// the slots in order, so consecutive lanes write consecutive positions of one
-// segment (coalesced stores); its loads of offsets and characters stay inside
-// the block's small, cached span.
+// into key lanes.  The block's offsets, and its characters when they fit
+// kScatterChars bytes, are first staged in LDS with coalesced loads.
+// Pass 1: the rank of a word among the words of the same length before it in
+// the block (per wave with ballots, a running count per wave carries ranks
+// across iterations) gives its slot in the block's length-sorted order; LDS
+// records which word holds each slot.  Pass 2 walks the slots in order, so
+// consecutive lanes write consecutive positions of one segment (coalesced
+// stores), reading the words from LDS.
+constexpr uint32_t kScatterChars = 32768;
 template <int NT>
 __global__ __launch_bounds__(NT) void k_scatter_pack(Ws w) {
   constexpr int NW = NT / 64;
   constexpr uint32_t PER_WAVE = kWordsPerBlock / NW;
   constexpr int IT = PER_WAVE / 64;
+  __shared__ uint32_t s_off[kWordsPerBlock + 1];
+  __shared__ uint32_t s_chr[kScatterChars / 4];
   __shared__ uint32_t s_run[NW][kNB];
   __shared__ uint32_t s_bstart[kNB + 1];
   __shared__ uint32_t s_gbase[kNB];
@@ -392,18 +416,37 @@ __global__ __launch_bounds__(NT) void k_scatter_pack(Ws w) {
   for (uint32_t b = blockIdx.x; b < nblk; b += gridDim.x) {
     for (uint32_t k = threadIdx.x; k < (uint32_t)(NW * kNB); k += NT) (&s_run[0][0])[k] = 0;
     const BlockRange r = block_range<NT>(w, b, D, &s_doc);   // has a barrier
+    const uint32_t nw = r.we - r.ws;
+    // the block's characters: whole aligned dwords covering [off[ws], off[we]),
+    // loaded together with the block's offsets
+    const uint32_t c0 = off[r.ws], c1 = off[r.we];
+    const uintptr_t abase = ((uintptr_t)(chars + c0)) & ~(uintptr_t)3;
+    const uint32_t lead = (uint32_t)((uintptr_t)(chars + c0) - abase);
+    const uint32_t span_dw = c1 > c0 ? (lead + (c1 - c0) + 3) >> 2 : 0u;
+    const bool staged = span_dw <= kScatterChars / 4;
+    {
+      const uint32_t* src = (const uint32_t*)abase;
+      const uint32_t ndw = staged ? span_dw : 0u;
+      for (uint32_t k = threadIdx.x; k < nw + 1 + ndw; k += NT) {
+        if (k <= nw)
+          s_off[k] = off[r.ws + k];
+        else
+          s_chr[k - nw - 1] = src[k - nw - 1];
+      }
+    }
     if (threadIdx.x < (uint32_t)kNB) {
       const uint32_t L = threadIdx.x;
       s_gbase[L] = w.seg_base[r.doc * kNB + L] + w.cnt[L * rs + b] - w.cnt[L * rs + w.doc_blk[r.doc]];
     }
-    const uint32_t wbeg = r.ws + wave * PER_WAVE;
+    __syncthreads();
+    const uint32_t wofs = wave * PER_WAVE;
     uint32_t pk[IT];
 #pragma unroll
     for (int it = 0; it < IT; ++it) {
-      const uint32_t i = wbeg + it * 64 + lane;
-      const bool valid = i < r.we;
+      const uint32_t i = wofs + it * 64 + lane;      // word index inside the block
+      const bool valid = i < nw;
       uint32_t L = 0;
-      if (valid) L = min(off[i + 1] - off[i], (uint32_t)kMaxLen);
+      if (valid) L = min(s_off[i + 1] - s_off[i], (uint32_t)kMaxLen);
       const uint64_t mm = match_mask<6>(L, valid);
       const uint32_t rk = lanes_below(mm);
       const uint32_t old = valid ? s_run[wave][L] : 0u;
@@ -427,24 +470,26 @@ __global__ __launch_bounds__(NT) void k_scatter_pack(Ws w) {
     __syncthreads();
 #pragma unroll
     for (int it = 0; it < IT; ++it) {
-      const uint32_t i = wbeg + it * 64 + lane;
-      if (i < r.we) {
+      const uint32_t i = wofs + it * 64 + lane;
+      if (i < nw) {
         const uint32_t L = pk[it] & 63u;
-        s_slot[s_bstart[L] + s_run[wave][L] + (pk[it] >> 6)] = (uint16_t)(i - r.ws);
+        s_slot[s_bstart[L] + s_run[wave][L] + (pk[it] >> 6)] = (uint16_t)i;
       }
     }
     __syncthreads();
-    const uint32_t nw = r.we - r.ws;
     const uint32_t doc0 = w.doc_off[r.doc];
 #pragma unroll 4
     for (uint32_t p = threadIdx.x; p < nw; p += NT) {
-      const uint32_t i = r.ws + s_slot[p];
-      const uint32_t a = off[i];
-      const uint32_t L = min(off[i + 1] - a, (uint32_t)kMaxLen);
+      const uint32_t i = s_slot[p];
+      const uint32_t a = s_off[i];
+      const uint32_t L = min(s_off[i + 1] - a, (uint32_t)kMaxLen);
       const uint32_t dest = s_gbase[L] + (p - s_bstart[L]);
-      const uint32_t idx = i - doc0;
+      const uint32_t idx = r.ws + i - doc0;
       uint64_t ln[4];
-      load_be_lanes<4>(chars + a, L, ln);
+      if (staged)
+        lds_be_lanes<4>(s_chr, lead + (a - c0), L, ln);
+      else
+        load_be_lanes<4>(chars + a, L, ln);
       const int c = class_of_len(L);
       if (c == 0) {
         w.a.k[0][dest] = (ln[0] & 0xFFFFFFFF00000000ull) | idx;
@@ -609,6 +654,43 @@ __device__ inline uint32_t wave_merge_path(const KeyBuf& buf, size_t a_base, uin
   return lo;
 }
 
+// The same search by groups of K lanes (K divides 64): each group finds the
+// split of its own diagonal, K probes per round.  Fewer probes per round
+// touch fewer cache lines; more rounds cost latency.
+template <int NL, int K>
+__device__ inline uint32_t group_merge_path(const KeyBuf& buf, size_t a_base, uint32_t la, size_t b_base,
+                                            uint32_t lb, uint32_t d, bool active) {
+  const uint32_t lane = __lane_id();
+  const uint32_t gl = lane % K;
+  const uint64_t gmask = K == 64 ? ~0ull : (((1ull << K) - 1) << (lane - gl));
+  uint32_t lo = 0, hi = 0;
+  if (active) {
+    lo = d > lb ? d - lb : 0u;
+    hi = d < la ? d : la;
+  }
+  while (__any(lo < hi)) {
+    const uint32_t step = (hi - lo + K - 1) / K;
+    const uint32_t a = lo + gl * step;
+    bool p = false;
+    if (lo < hi && a < hi) {
+      const Key<NL> A = gload<NL>(buf, a_base + a);
+      const Key<NL> B = gload<NL>(buf, b_base + (d - 1 - a));
+      p = !key_less<NL>(B, A);
+    }
+    const uint32_t c = __popcll(__ballot(p) & gmask);
+    if (lo < hi) {
+      if (c == 0) {
+        hi = lo;
+      } else {
+        const uint32_t nlo = lo + (c - 1) * step + 1;
+        hi = min(lo + c * step, hi);
+        lo = nlo;
+      }
+    }
+  }
+  return lo;
+}
+
 // Segment of a tile from the device lists: k-th segment of the class sublist
 // whose tile prefix covers t.
 struct TileSeg {
@@ -730,11 +812,14 @@ struct TileRec {
   uint32_t base, n, j, split;
 };
 
-// k_partition: the record of every tile of one merge level (one wave per
-// tile, 64 probes per round for the split), so that merge workgroups need a
-// single 16-byte load to place a tile.
+// k_partition: the record of every tile of one merge level.  Groups of
+// kPartLanes lanes each place one tile (kPartLanes probes per round), so a
+// wave places 64/kPartLanes tiles; merge workgroups then need a single
+// 16-byte load to place a tile.
+constexpr int kPartLanes = 16;
 template <int NL, int NT>
 __global__ __launch_bounds__(NT) void k_partition(Ws w, int cls, int level, TileWork tw, uint32_t P) {
+  constexpr int TPW = 64 / kPartLanes;   // tiles per wave
   Header* h = w.h;
   if (h->abort) return;
   const uint64_t R = (uint64_t)w.T[cls] << level;
@@ -751,20 +836,38 @@ __global__ __launch_bounds__(NT) void k_partition(Ws w, int cls, int level, Tile
   }
   const KeyBuf src = (level & 1) ? w.b : w.a;
   TileRec* rec = (TileRec*)w.rec + (size_t)cls * w.rec_stride;
+  const uint32_t lane = __lane_id();
   const uint32_t nw = gridDim.x * (NT / 64);
-  for (uint32_t t = blockIdx.x * (NT / 64) + (threadIdx.x >> 6); t < ntiles; t += nw) {
-    TileSeg g;
-    if (tw.direct) {
-      g.base = tw.base;
-      g.n = tw.n;
-      g.j = t;
-    } else {
-      g = find_tile(w, mt, cstart, cact, t);
+  for (uint32_t t0 = (blockIdx.x * (NT / 64) + (threadIdx.x >> 6)) * TPW; t0 < ntiles; t0 += nw * TPW) {
+    const uint32_t t = t0 + lane / kPartLanes;
+    const bool active = t < ntiles;
+    TileSeg g{0, 0, 0};
+    if (active) {
+      if (tw.direct) {
+        g.base = tw.base;
+        g.n = tw.n;
+        g.j = t;
+      } else {
+        // the group's tile: its segment by a plain search (per lane, same answer in the group)
+        uint32_t lo = 0, hi = cact;   // largest k with mt[k] <= t
+        while (hi - lo > 1) {
+          const uint32_t mid = (lo + hi) >> 1;
+          if (mt[mid] <= t)
+            lo = mid;
+          else
+            hi = mid;
+        }
+        const uint32_t s = w.sorted[cstart + lo];
+        g.base = w.seg_base[s];
+        g.n = w.seg_n[s];
+        g.j = t - mt[lo];
+      }
     }
-    const MergeTile m = merge_tile(g.n, g.j, R, P);
+    MergeTile m{};
+    if (active) m = merge_tile(g.n, g.j, R, P);
     const size_t abase = (size_t)g.base + m.ps;
-    const uint32_t sp = wave_merge_path<NL>(src, abase, m.la, abase + m.la, m.lb, m.d0);
-    if (__lane_id() == 0) rec[t] = TileRec{g.base, g.n, g.j, sp};
+    const uint32_t sp = group_merge_path<NL, kPartLanes>(src, abase, m.la, abase + m.la, m.lb, m.d0, active);
+    if (active && lane % kPartLanes == 0) rec[t] = TileRec{g.base, g.n, g.j, sp};
   }
 }
 

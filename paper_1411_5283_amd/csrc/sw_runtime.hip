@@ -39,7 +39,8 @@ int fail(int code, const char* fmt, ...) {
     if (e_ != hipSuccess) return fail(SW_ERR_HIP, "%s: %s", #expr, hipGetErrorString(e_)); \
   } while (0)
 
-constexpr int kNT = 256;   // threads per workgroup of the streaming kernels
+constexpr int kNT = 256;         // threads per workgroup of the streaming kernels
+constexpr int kScatterNT = 512;  // threads per workgroup of k_scatter_pack
 
 // ------------------------------------------------------------------ variants
 // A variant fixes, for one key class, the chunk-sort tile (NTS threads x ES
@@ -123,8 +124,8 @@ int device_info(DevInfo** out) {
   if (!d.ready) {
     HIP_TRY(hipDeviceGetAttribute(&d.cus, hipDeviceAttributeMultiprocessorCount, dev));
     HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(&d.occ_hist, (const void*)sw::k_hist<kNT>, kNT, 0));
-    HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(&d.occ_scatter, (const void*)sw::k_scatter_pack<kNT>,
-                                                         kNT, 0));
+    HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(&d.occ_scatter, (const void*)sw::k_scatter_pack<kScatterNT>,
+                                                         kScatterNT, 0));
     for (int c = 0; c < sw::kNClass; ++c) {
       int nv;
       const Variant* vs = variants(c, &nv);
@@ -296,7 +297,7 @@ struct ProfScope {
 // ------------------------------------------------------------------ launch sequence
 struct Grids {
   uint32_t flags;
-  unsigned words, docs, segs;
+  unsigned words, scatter, docs, segs;
   unsigned sort[sw::kNClass], merge[sw::kNClass], part[sw::kNClass];
   int levels[sw::kNClass];
   const Variant* var[sw::kNClass];
@@ -309,7 +310,8 @@ int make_grids(const Ws& w, const sw_config& cfg, Grids& g) {
   const uint64_t cus = (uint64_t)d->cus;
   auto clampg = [](uint64_t want, uint64_t cap) { return (unsigned)std::max<uint64_t>(1, std::min(want, cap)); };
   g.flags = cfg.flags;
-  g.words = clampg(w.Bmax, cus * (uint64_t)std::min(d->occ_hist, d->occ_scatter));
+  g.words = clampg(w.Bmax, cus * (uint64_t)d->occ_hist);
+  g.scatter = clampg(w.Bmax, cus * (uint64_t)d->occ_scatter);
   g.docs = clampg((w.Dmax + 3) / 4, cus * 4);
   g.segs = clampg(w.SBmax, cus * 2);
   for (int c = 0; c < sw::kNClass; ++c) {
@@ -321,7 +323,8 @@ int make_grids(const Ws& w, const sw_config& cfg, Grids& g) {
     const uint64_t maxtiles_m = (uint64_t)w.Nmax / vs[v].P + w.Smax;
     g.sort[c] = clampg(maxtiles_s, cus * (uint64_t)d->occ_sort[c][v]);
     g.merge[c] = clampg(maxtiles_m, cus * (uint64_t)d->occ_merge[c][v]);
-    g.part[c] = clampg((maxtiles_m + kPartNT / 64 - 1) / (kPartNT / 64), cus * 8);
+    const uint64_t tiles_per_wg = (uint64_t)(kPartNT / 64) * (64 / sw::kPartLanes);
+    g.part[c] = clampg((maxtiles_m + tiles_per_wg - 1) / tiles_per_wg, cus * 8);
     g.levels[c] = (int)sw::levels_for(w.Nmax, vs[v].T);
   }
   return SW_OK;
@@ -408,7 +411,7 @@ int enqueue_body(const Ws& w, const Grids& g, hipStream_t s, bool capture, bool 
   }
   {
     ProfScope p(K_SCATTER, s, capture);
-    sw::k_scatter_pack<kNT><<<g.words, kNT, 0, s>>>(w);
+    sw::k_scatter_pack<kScatterNT><<<g.scatter, kScatterNT, 0, s>>>(w);
   }
   if (through_scatter) return SW_OK;
   const bool par = fork && fork->ready && !(!capture && profiling_on()) && !(g.flags & SW_FLAG_SERIAL_CLASSES);
@@ -618,7 +621,8 @@ int sort_words_plain(const uint8_t* chars, const uint32_t* offsets, const uint32
     for (uint32_t l = 0; l < m; ++l) {
       {
         ProfScope p(K_PART0 + c, s, false);
-        v.partition(w, c, (int)l, tw, (mtiles + kPartNT / 64 - 1) / (kPartNT / 64), s);
+        const uint32_t tiles_per_wg = (kPartNT / 64) * (64 / sw::kPartLanes);
+        v.partition(w, c, (int)l, tw, (mtiles + tiles_per_wg - 1) / tiles_per_wg, s);
       }
       ProfScope p(K_MERGE0 + c, s, false);
       v.merge(w, c, (int)l, tw, mtiles, s);
