@@ -41,14 +41,17 @@ def footprint(n_words: int, n_chars: int) -> int:
 
 
 def check_request(chars: np.ndarray, offsets: np.ndarray) -> int:
-    """Host-side argument check of one request (0 or a library error code)."""
-    o = np.asarray(offsets, dtype=np.int64)
+    """Host-side argument check of one request (0 or a library error code).
+    Works on the uint32 offsets in place (no widening copies)."""
+    o = offsets
     if o.ndim != 1 or o.shape[0] < 1:
         return ERR_INVALID_ARG
-    d = np.diff(o)
-    if d.size and (d.min() < 0 or o[0] < 0 or o[-1] > chars.shape[0]):
+    if o.shape[0] == 1:
+        return 0
+    hi, lo = o[1:], o[:-1]
+    if (hi < lo).any() or int(o[-1]) > chars.shape[0]:
         return ERR_INVALID_ARG
-    if d.size and d.max() > MAX_LEN:
+    if int((hi - lo).max()) > MAX_LEN:
         return ERR_WORD_TOO_LONG
     return 0
 
@@ -125,7 +128,7 @@ class SortServer:
         """Queue one request (host arrays); the future yields (perm, bucket_offsets)."""
         fut = Future()
         chars = np.ascontiguousarray(chars, dtype=np.uint8)
-        offsets = np.asarray(offsets, dtype=np.int64)
+        offsets = np.ascontiguousarray(offsets, dtype=np.uint32)
         code = check_request(chars, offsets)
         with self._lock:
             rid = self._next_id
@@ -136,7 +139,7 @@ class SortServer:
             return fut
         base = int(offsets[0])
         n = offsets.shape[0] - 1
-        req = Request(rid, chars[base:int(offsets[-1])], (offsets - base).astype(np.uint32),
+        req = Request(rid, chars[base:int(offsets[-1])], offsets - np.uint32(base) if base else offsets,
                       self.clock(), fut, n=n)
         req.bytes = footprint(n, req.chars.shape[0])
         if req.bytes > self.budget or n > self.max_batch_words or not self.ex.capacity(n, 1):
