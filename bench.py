@@ -27,6 +27,7 @@ sys.path.insert(0, ROOT)
 
 METRIC = "Mwords/s sorted + achieved HBM GB/s, batched vs per-bucket launch, bit-exact"
 HBM_PEAK_GBS = 8000.0
+PACK_MAX = 1024          # segments of at most this many words are sorted several to a tile
 WORKLOADS = {
     "c1": (1, "35k words, 5k-word Zipf(1.0) vocabulary, lengths 1-16"),
     "c2": (2, "250k words, 20k-word Zipf(1.0) vocabulary, lengths 1-20, odd-even chunks of 1024"),
@@ -91,6 +92,9 @@ def algorithmic_bytes(seg_sizes, tiles):
         m = levels_for(n, tiles[c])
         add("hist", 4 * n)
         add("scatter_pack", (4 + L + e) * n)
+        if n <= PACK_MAX:       # short segments: several to a tile
+            add("sort_packed_c%d" % c, (e + 4) * n)
+            continue
         add("sort_tiles_c%d" % c, (e + (e if m else 4)) * n)
         for l in range(m):
             add("merge_c%d" % c, (e + (e if l < m - 1 else 4)) * n)

@@ -28,6 +28,10 @@ constexpr int kMaxLev = 24;             // merge levels a segment may need
 constexpr uint32_t kWordsPerBlock = 4096;
 constexpr uint32_t kSegsPerBlock = 4096;
 constexpr uint32_t kMinMergeTile = 512;      // smallest merge tile of any variant
+// Short segments (at most kPackMax words) are sorted several to a tile of
+// kPackTile items by k_sort_packed.
+constexpr uint32_t kPackTile = 2048;
+constexpr uint32_t kPackMax = kPackTile / 2;
 constexpr int kNKeys = kNClass * kMaxLev + 1;   // segment-order keys (+1: empty)
 constexpr int kKeyBits = 7;
 static_assert(kNKeys <= (1 << kKeyBits), "segment key bits");
@@ -75,7 +79,9 @@ struct Header {
   uint32_t n_segblocks;
   uint32_t cls_start[kNClass + 1];         // class sublists of the ordered segments
   uint32_t active[kNClass][kMaxLev];       // segments of a class with more levels than l
+  uint32_t pack_start[kNClass];            // first short segment of each class sublist
   uint32_t sort_tiles[kNClass];
+  uint32_t pack_words[kNClass];            // words in the short segments of each class
 };
 
 struct KeyBuf {
@@ -95,6 +101,7 @@ struct Ws {
   uint32_t* sorted;     // [Smax]      non-empty segments by (class, levels desc)
   uint32_t* st;         // [Smax+kNClass]  chunk-sort tile prefix per class
   uint32_t* mt;         // [Smax+kNClass]  merge tile prefix per class
+  uint32_t* vpre;       // [Smax+kNClass]  prefix of short-segment sizes per class
   uint4* rec;           // [kNClass][rec_stride]  record of each merge tile (k_partition)
   uint32_t rec_stride;  // Nmax/kMinMergeTile + Smax + 2
   KeyBuf a;             // key buffer 0 (scatter output, chunk sort in place)
@@ -283,23 +290,13 @@ __device__ inline Key<0> key_shfl<0>(const Key<0>& v, int src) {
   return r;
 }
 
-// Compare-exchange: afterwards a <= b.  Returns whether they were exchanged.
-template <int NL>
-__device__ inline bool cmp_xchg(Key<NL>& a, Key<NL>& b) {
-  const bool sw = key_less(b, a);
-  const Key<NL> lo = key_select(sw, b, a);
-  const Key<NL> hi = key_select(sw, a, b);
-  a = lo;
-  b = hi;
-  return sw;
-}
-
 // ---------------------------------------------------------------- LDS tile
 // Structure-of-arrays tile of CAP keys.  One pad slot every 2^PADSH items
 // keeps a thread's consecutive items (blocked layout) off its neighbours'
 // banks.
 template <int NL, int CAP, int PADSH = 4>
 struct LdsTile {
+  using value_type = Key<NL>;
   static constexpr int kPadded = CAP + (CAP >> PADSH);
   static constexpr int kLanes = NL ? NL : 1;
   uint64_t k[kLanes][kPadded];
@@ -323,6 +320,7 @@ struct LdsTile {
 };
 template <int CAP, int PADSH>
 struct LdsTile<0, CAP, PADSH> {
+  using value_type = Key<0>;
   static constexpr int kPadded = CAP + (CAP >> PADSH);
   uint64_t k[kPadded];
   __device__ static int pos(int i) { return i + (i >> PADSH); }
@@ -333,5 +331,81 @@ struct LdsTile<0, CAP, PADSH> {
   }
   __device__ void put(int i, const Key<0>& v) { k[pos(i)] = v.k; }
 };
+
+// ---------------------------------------------------------------- tagged keys
+// A key with a small tag compared first.  Several short segments packed into
+// one tile carry their ordinal in the tile as the tag, so sorting the tile by
+// (tag, key) sorts every segment in place.
+template <int NL>
+struct TKey {
+  Key<NL> k;
+  uint32_t tag;
+};
+
+template <int NL, int CAP, int PADSH = 4>
+struct TLdsTile {
+  using value_type = TKey<NL>;
+  LdsTile<NL, CAP, PADSH> t;
+  uint32_t tag[LdsTile<NL, CAP, PADSH>::kPadded];
+  __device__ TKey<NL> get(int i) const {
+    TKey<NL> v;
+    v.k = t.get(i);
+    v.tag = tag[LdsTile<NL, CAP, PADSH>::pos(i)];
+    return v;
+  }
+  __device__ void put(int i, const TKey<NL>& v) {
+    t.put(i, v.k);
+    tag[LdsTile<NL, CAP, PADSH>::pos(i)] = v.tag;
+  }
+};
+
+// Element operations, overloaded for plain and tagged keys.
+template <int NL>
+__device__ inline bool e_less(const Key<NL>& a, const Key<NL>& b) { return key_less<NL>(a, b); }
+template <int NL>
+__device__ inline bool e_less(const TKey<NL>& a, const TKey<NL>& b) {
+  return a.tag != b.tag ? a.tag < b.tag : key_less<NL>(a.k, b.k);
+}
+template <int NL>
+__device__ inline Key<NL> e_select(bool c, const Key<NL>& x, const Key<NL>& y) { return key_select<NL>(c, x, y); }
+template <int NL>
+__device__ inline TKey<NL> e_select(bool c, const TKey<NL>& x, const TKey<NL>& y) {
+  TKey<NL> r;
+  r.k = key_select<NL>(c, x.k, y.k);
+  r.tag = c ? x.tag : y.tag;
+  return r;
+}
+template <int NL>
+__device__ inline void e_set_sentinel(Key<NL>& v) { v = key_sentinel<NL>(); }
+template <int NL>
+__device__ inline void e_set_sentinel(TKey<NL>& v) {
+  v.k = key_sentinel<NL>();
+  v.tag = ~0u;
+}
+template <class K>
+__device__ inline K e_sentinel() {
+  K v;
+  e_set_sentinel(v);
+  return v;
+}
+template <int NL>
+__device__ inline Key<NL> e_shfl(const Key<NL>& v, int src) { return key_shfl<NL>(v, src); }
+template <int NL>
+__device__ inline TKey<NL> e_shfl(const TKey<NL>& v, int src) {
+  TKey<NL> r;
+  r.k = key_shfl<NL>(v.k, src);
+  r.tag = __shfl(v.tag, src);
+  return r;
+}
+// Compare-exchange: afterwards a <= b.  Returns whether they were exchanged.
+template <class K>
+__device__ inline bool e_cmp_xchg(K& a, K& b) {
+  const bool sw = e_less(b, a);
+  const K lo = e_select(sw, b, a);
+  const K hi = e_select(sw, a, b);
+  a = lo;
+  b = hi;
+  return sw;
+}
 
 }  // namespace sw

@@ -218,13 +218,15 @@ __global__ __launch_bounds__(NT) void k_segments(Ws w) {
   }
 }
 
-// Segment order key: (class, merge levels descending); empty segments last.
+// Segment order key: class, then merge levels descending, then the short
+// segments that are packed several to a tile; empty segments last.
 __device__ inline uint32_t seg_key(const Ws& w, uint32_t s) {
   const uint32_t n = w.seg_n[s];
   if (n == 0) return kNKeys - 1;
   const int c = class_of_len(s % kNB);
+  if (n <= kPackMax) return (uint32_t)c * kMaxLev + (kMaxLev - 1);
   const uint32_t m = levels_for(n, w.T[c]);
-  return (uint32_t)c * kMaxLev + (kMaxLev - 1 - m);
+  return (uint32_t)c * kMaxLev + (kMaxLev - 2 - m);
 }
 
 template <int NT>
@@ -270,9 +272,12 @@ __global__ __launch_bounds__(NT) void k_seg_scatter(Ws w) {
   }
   if (blockIdx.x == 0) {
     if (threadIdx.x <= (uint32_t)kNClass) h->cls_start[threadIdx.x] = s_kbase[threadIdx.x * kMaxLev];
+    if (threadIdx.x < (uint32_t)kNClass) h->pack_start[threadIdx.x] = s_kbase[threadIdx.x * kMaxLev + kMaxLev - 1];
     for (uint32_t i = threadIdx.x; i < (uint32_t)(kNClass * kMaxLev); i += NT) {
       const uint32_t c = i / kMaxLev, l = i % kMaxLev;
-      h->active[c][l] = s_kbase[c * kMaxLev + (kMaxLev - 1 - l)] - s_kbase[c * kMaxLev];
+      h->active[c][l] = l + 2 <= (uint32_t)kMaxLev
+                            ? s_kbase[c * kMaxLev + (kMaxLev - 2 - l)] - s_kbase[c * kMaxLev]
+                            : 0u;
     }
   }
   for (uint32_t b = blockIdx.x; b < nsb; b += gridDim.x) {
@@ -314,17 +319,20 @@ __global__ __launch_bounds__(NT) void k_seg_scatter(Ws w) {
   }
 }
 
-// Per class (blockIdx.x / 2) and kind (blockIdx.x % 2: chunk-sort tiles or
-// merge tiles): exclusive prefix of the tile counts over the class's sublist.
+// Per class (blockIdx.x / 3) and kind (blockIdx.x % 3): exclusive prefix over
+// the class sublist of the chunk-sort tiles (kind 0) or the merge tiles
+// (kind 1) of its segments that are not packed, or of the sizes of its short
+// segments (kind 2, their positions in the packed tiles).
 template <int NT>
 __global__ __launch_bounds__(NT) void k_tile_prefix(Ws w) {
   __shared__ uint32_t s_tmp[NT / 64];
   Header* h = w.h;
   if (h->abort) return;
-  const uint32_t c = blockIdx.x >> 1, kind = blockIdx.x & 1;
-  const uint32_t cs = h->cls_start[c], ce = h->cls_start[c + 1];
-  uint32_t* out = (kind ? w.mt : w.st) + cs + c;
-  const uint32_t div = kind ? w.P[c] : w.T[c];
+  const uint32_t c = blockIdx.x / 3, kind = blockIdx.x % 3;
+  const uint32_t cs = kind == 2 ? h->pack_start[c] : h->cls_start[c];
+  const uint32_t ce = kind == 2 ? h->cls_start[c + 1] : h->pack_start[c];
+  uint32_t* out = (kind == 0 ? w.st : (kind == 1 ? w.mt : w.vpre)) + (kind == 2 ? cs : h->cls_start[c]) + c;
+  const uint32_t div = kind == 0 ? w.T[c] : (kind == 1 ? w.P[c] : 1u);
   uint32_t carry = 0;
   for (uint32_t base = cs; base < ce; base += NT) {
     const uint32_t i = base + threadIdx.x;
@@ -337,6 +345,7 @@ __global__ __launch_bounds__(NT) void k_tile_prefix(Ws w) {
   if (threadIdx.x == 0) {
     out[ce - cs] = carry;
     if (kind == 0) h->sort_tiles[c] = carry;
+    if (kind == 2) h->pack_words[c] = carry;
   }
 }
 
@@ -514,8 +523,8 @@ __global__ __launch_bounds__(NT) void k_scatter_pack(Ws w) {
 // (E <= C <= 64*E, both powers of two).  C phases sort a chunk; the loop also
 // stops early once an even and an odd phase exchange nothing anywhere in the
 // wave, bubble sort's own stopping rule.
-template <int NL, int E>
-__device__ inline void oddeven_chunks(Key<NL> (&e)[E], uint32_t C) {
+template <class K, int E>
+__device__ inline void oddeven_chunks(K (&e)[E], uint32_t C) {
   const uint32_t lane = __lane_id();
   const bool cross = C > (uint32_t)E;
   const bool has_next = cross && (((lane + 1) * E) & (C - 1)) != 0;
@@ -523,39 +532,39 @@ __device__ inline void oddeven_chunks(Key<NL> (&e)[E], uint32_t C) {
   for (uint32_t p = 0; p < C; p += 2) {
     bool sw = false;
 #pragma unroll
-    for (int j = 0; j + 1 < E; j += 2) sw |= cmp_xchg(e[j], e[j + 1]);
+    for (int j = 0; j + 1 < E; j += 2) sw |= e_cmp_xchg(e[j], e[j + 1]);
 #pragma unroll
-    for (int j = 1; j + 1 < E; j += 2) sw |= cmp_xchg(e[j], e[j + 1]);
+    for (int j = 1; j + 1 < E; j += 2) sw |= e_cmp_xchg(e[j], e[j + 1]);
     if (cross) {
-      const Key<NL> nx = key_shfl(e[0], (int)min(lane + 1, 63u));
-      const Key<NL> pv = key_shfl(e[E - 1], (int)(lane ? lane - 1 : 0u));
-      if (has_next && key_less(nx, e[E - 1])) {
+      const K nx = e_shfl(e[0], (int)min(lane + 1, 63u));
+      const K pv = e_shfl(e[E - 1], (int)(lane ? lane - 1 : 0u));
+      if (has_next && e_less(nx, e[E - 1])) {
         e[E - 1] = nx;
         sw = true;
       }
-      if (has_prev && key_less(e[0], pv)) e[0] = pv;
+      if (has_prev && e_less(e[0], pv)) e[0] = pv;
     }
     if (!__any(sw)) break;
   }
 }
 
 // Accessor of a sorted run held contiguously in LDS.
-template <int NL, class Tile>
+template <class Tile>
 struct LinRun {
   const Tile& t;
   int base;
-  __device__ Key<NL> operator()(int i) const { return t.get(base + i); }
+  __device__ typename Tile::value_type operator()(int i) const { return t.get(base + i); }
 };
 // Merge path (Odeh et al., "Merge Path - Parallel Merging Made Simple", 2012):
 // number of A items among the first d outputs of the stable merge of A and B
 // (A first on ties).  Binary search by one thread.
-template <int NL, class RA, class RB>
+template <class RA, class RB>
 __device__ inline int run_merge_path(const RA& A, int la, const RB& B, int lb, int d) {
   int lo = d > lb ? d - lb : 0;
   int hi = d < la ? d : la;
   while (lo < hi) {
     const int mid = (lo + hi) >> 1;
-    if (!key_less<NL>(B(d - 1 - mid), A(mid)))
+    if (!e_less(B(d - 1 - mid), A(mid)))
       lo = mid + 1;
     else
       hi = mid;
@@ -567,21 +576,20 @@ __device__ inline int run_merge_path(const RA& A, int la, const RB& B, int lb, i
 // exhausted side shows the sentinel, which no real key reaches, so the next
 // output is always the smaller head; one load per output refills the side
 // that was taken.
-template <int NL, int E, class RA, class RB>
-__device__ inline void run_serial_merge(const RA& A, int la, const RB& B, int lb, int ai, int bi,
-                                        Key<NL> (&out)[E]) {
-  Key<NL> ha = ai < la ? A(ai) : key_sentinel<NL>();
-  Key<NL> hb = bi < lb ? B(bi) : key_sentinel<NL>();
+template <class K, int E, class RA, class RB>
+__device__ inline void run_serial_merge(const RA& A, int la, const RB& B, int lb, int ai, int bi, K (&out)[E]) {
+  K ha = ai < la ? A(ai) : e_sentinel<K>();
+  K hb = bi < lb ? B(bi) : e_sentinel<K>();
 #pragma unroll
   for (int j = 0; j < E; ++j) {
-    const bool takeB = key_less<NL>(hb, ha);
-    out[j] = key_select<NL>(takeB, hb, ha);
+    const bool takeB = e_less(hb, ha);
+    out[j] = e_select(takeB, hb, ha);
     const int ni = takeB ? ++bi : ++ai;
     const int lim = takeB ? lb : la;
-    Key<NL> nv = key_sentinel<NL>();
+    K nv = e_sentinel<K>();
     if (ni < lim) nv = takeB ? B(ni) : A(ni);
-    ha = key_select<NL>(takeB, ha, nv);
-    hb = key_select<NL>(takeB, nv, hb);
+    ha = e_select(takeB, ha, nv);
+    hb = e_select(takeB, nv, hb);
   }
 }
 
@@ -591,38 +599,58 @@ __device__ inline void run_serial_merge(const RA& A, int la, const RB& B, int lb
 // (half-cleaner of x followed by y reversed), and log2(E) half-cleaner stages
 // sort it (Batcher's bitonic merge).  Items past a run's end read as the
 // sentinel.
-template <int NL, int E, class RA, class RB>
-__device__ inline void run_bitonic_merge(const RA& A, int la, const RB& B, int lb, int ai, int bi,
-                                         Key<NL> (&out)[E]) {
-  Key<NL> x[E], y[E];
+template <class K, int E, class RA, class RB>
+__device__ inline void run_bitonic_merge(const RA& A, int la, const RB& B, int lb, int ai, int bi, K (&out)[E]) {
+  K x[E], y[E];
 #pragma unroll
   for (int i = 0; i < E; ++i) {
-    x[i] = ai + i < la ? A(ai + i) : key_sentinel<NL>();
-    y[i] = bi + i < lb ? B(bi + i) : key_sentinel<NL>();
+    x[i] = ai + i < la ? A(ai + i) : e_sentinel<K>();
+    y[i] = bi + i < lb ? B(bi + i) : e_sentinel<K>();
   }
 #pragma unroll
-  for (int i = 0; i < E; ++i) out[i] = key_select<NL>(key_less<NL>(y[E - 1 - i], x[i]), y[E - 1 - i], x[i]);
+  for (int i = 0; i < E; ++i) out[i] = e_select(e_less(y[E - 1 - i], x[i]), y[E - 1 - i], x[i]);
 #pragma unroll
   for (int st = E / 2; st >= 1; st >>= 1) {
 #pragma unroll
     for (int i = 0; i < E; ++i)
-      if ((i & st) == 0) cmp_xchg<NL>(out[i], out[i + st]);
+      if ((i & st) == 0) e_cmp_xchg(out[i], out[i + st]);
   }
 }
 
-template <int NL, class Tile>
+template <class Tile>
 __device__ inline int lds_merge_path(const Tile& t, int a0, int la, int b0, int lb, int d) {
-  return run_merge_path<NL>(LinRun<NL, Tile>{t, a0}, la, LinRun<NL, Tile>{t, b0}, lb, d);
+  return run_merge_path(LinRun<Tile>{t, a0}, la, LinRun<Tile>{t, b0}, lb, d);
 }
 
 // E merged outputs into registers: MM = 0 serial merge, MM = 1 bitonic merge.
-template <int NL, int E, int MM, class Tile>
+template <int E, int MM, class Tile>
 __device__ inline void lds_register_merge(const Tile& t, int a0, int la, int b0, int lb, int ai, int bi,
-                                          Key<NL> (&out)[E]) {
+                                          typename Tile::value_type (&out)[E]) {
   if (MM == 0)
-    run_serial_merge<NL, E>(LinRun<NL, Tile>{t, a0}, la, LinRun<NL, Tile>{t, b0}, lb, ai, bi, out);
+    run_serial_merge(LinRun<Tile>{t, a0}, la, LinRun<Tile>{t, b0}, lb, ai, bi, out);
   else
-    run_bitonic_merge<NL, E>(LinRun<NL, Tile>{t, a0}, la, LinRun<NL, Tile>{t, b0}, lb, ai, bi, out);
+    run_bitonic_merge(LinRun<Tile>{t, a0}, la, LinRun<Tile>{t, b0}, lb, ai, bi, out);
+}
+
+// Sorting core of a tile held as E items per thread in registers (blocked:
+// thread t holds items t*E..t*E+E-1 of the tile): odd-even transposition on
+// chunks of C, then merge-path rounds through LDS until one run covers the
+// tile's cnt real items (the rest of the tile is sentinels, already in place).
+template <int NT, int E, int MM, class Tile>
+__device__ inline void sort_tile_core(Tile& tile, typename Tile::value_type (&e)[E], uint32_t C, uint32_t cnt) {
+  constexpr int T = NT * E;
+  oddeven_chunks(e, C);
+  for (uint32_t R = C; R < (uint32_t)T && R < cnt; R <<= 1) {
+    __syncthreads();
+#pragma unroll
+    for (int r = 0; r < E; ++r) tile.put(threadIdx.x * E + r, e[r]);
+    __syncthreads();
+    const int o = threadIdx.x * E;
+    const int p0 = o & ~(int)(2 * R - 1);
+    const int d = o - p0;
+    const int a = lds_merge_path(tile, p0, (int)R, p0 + (int)R, (int)R, d);
+    lds_register_merge<E, MM>(tile, p0, (int)R, p0 + (int)R, (int)R, a, d - a, e);
+  }
 }
 
 // Merge path on the diagonal d over global memory, by one wave: 64 probes per
@@ -726,7 +754,7 @@ __global__ __launch_bounds__(NT) void k_sort_tiles(Ws w, int cls, TileWork tw) {
     ntiles = (tw.n + T - 1) / T;
   } else {
     cstart = h->cls_start[cls];
-    ccount = h->cls_start[cls + 1] - cstart;
+    ccount = h->pack_start[cls] - cstart;
     st = w.st + cstart + cls;
     ntiles = h->sort_tiles[cls];
   }
@@ -753,20 +781,7 @@ __global__ __launch_bounds__(NT) void k_sort_tiles(Ws w, int cls, TileWork tw) {
     Key<NL> e[E];
 #pragma unroll
     for (int r = 0; r < E; ++r) e[r] = tile.get(threadIdx.x * E + r);
-    oddeven_chunks<NL, E>(e, C);
-    // once one run covers every real item the rest of the tile is sentinels
-    // and already in place, so the merge rounds stop there
-    for (uint32_t R = C; R < (uint32_t)T && R < cnt; R <<= 1) {
-      __syncthreads();
-#pragma unroll
-      for (int r = 0; r < E; ++r) tile.put(threadIdx.x * E + r, e[r]);
-      __syncthreads();
-      const int o = threadIdx.x * E;
-      const int p0 = o & ~(int)(2 * R - 1);
-      const int d = o - p0;
-      const int a = lds_merge_path<NL>(tile, p0, (int)R, p0 + (int)R, (int)R, d);
-      lds_register_merge<NL, E, MM>(tile, p0, (int)R, p0 + (int)R, (int)R, a, d - a, e);
-    }
+    sort_tile_core<NT, E, MM>(tile, e, C, cnt);
     __syncthreads();
 #pragma unroll
     for (int r = 0; r < E; ++r) tile.put(threadIdx.x * E + r, e[r]);
@@ -780,6 +795,92 @@ __global__ __launch_bounds__(NT) void k_sort_tiles(Ws w, int cls, TileWork tw) {
           out_perm[gb + i] = key_index<NL>(v);
         else
           gstore<NL>(w.a, gb + i, v);
+      }
+    }
+    __syncthreads();
+  }
+}
+
+// ---------------------------------------------------------------- k_sort_packed
+// Short segments (at most kPackMax = kPackTile/2 words, all finished by the
+// chunk sort) are sorted several to a tile.  The class's short segments are
+// laid end to end in a virtual sequence (their sizes' prefix); packed tile k
+// takes every segment that starts in [k*kPackMax, (k+1)*kPackMax), at most
+// kPackTile items.  Each item carries its segment's ordinal in the tile as a
+// tag compared before the key, so sorting the tile (odd-even chunks, then
+// merge path in LDS) sorts every segment in place; item p of the sorted tile
+// belongs to the segment its tag names.
+template <int NL, int E, int MM>
+__global__ __launch_bounds__(kPackTile / E) void k_sort_packed(Ws w, int cls) {
+  constexpr int NT = kPackTile / E;
+  constexpr uint32_t H = kPackMax;
+  __shared__ TLdsTile<NL, kPackTile> tile;
+  __shared__ uint32_t s_start[kPackMax + 1];   // segment starts inside the tile
+  __shared__ uint32_t s_base[kPackMax];        // segment first output positions
+  __shared__ uint32_t s_rng[3];
+  Header* h = w.h;
+  if (h->abort) return;
+  uint32_t C = w.chunk[cls];
+  C = C < (uint32_t)E ? (uint32_t)E : (C > 64u * E ? 64u * E : C);
+  const uint32_t ps = h->pack_start[cls];
+  const uint32_t npack = h->cls_start[cls + 1] - ps;
+  const uint32_t* vp = w.vpre + ps + cls;     // npack + 1 entries
+  const uint32_t ntiles = (h->pack_words[cls] + H - 1) / H;
+  uint32_t* out_perm = h->d.out_perm;
+  for (uint32_t k = blockIdx.x; k < ntiles; k += gridDim.x) {
+    if (threadIdx.x < 2) {
+      // first segment starting at or after k*H (resp. (k+1)*H)
+      const uint32_t x = (k + threadIdx.x) * H;
+      uint32_t lo = 0, hi = npack;
+      while (lo < hi) {
+        const uint32_t mid = (lo + hi) >> 1;
+        if (vp[mid] < x)
+          lo = mid + 1;
+        else
+          hi = mid;
+      }
+      s_rng[threadIdx.x] = lo;
+    }
+    __syncthreads();
+    const uint32_t first = s_rng[0], last = s_rng[1];
+    const uint32_t nseg = last - first;
+    const uint32_t v0 = vp[first];
+    const uint32_t cnt = vp[last] - v0;
+    for (uint32_t j = threadIdx.x; j < nseg; j += NT) {
+      s_start[j] = vp[first + j] - v0;
+      s_base[j] = w.seg_base[w.sorted[ps + first + j]];
+    }
+    if (threadIdx.x == 0) s_start[nseg] = cnt;
+    __syncthreads();
+    TKey<NL> e[E];
+    if (nseg) {
+      // segment of this thread's first item, then walk forward
+      const uint32_t p0 = threadIdx.x * E;
+      uint32_t lo = 0, hi = nseg;
+      while (hi - lo > 1) {
+        const uint32_t mid = (lo + hi) >> 1;
+        if (s_start[mid] <= p0)
+          lo = mid;
+        else
+          hi = mid;
+      }
+      uint32_t tg = lo;
+#pragma unroll
+      for (int r = 0; r < E; ++r) {
+        const uint32_t p = p0 + r;
+        if (p < cnt) {
+          while (s_start[tg + 1] <= p) ++tg;
+          e[r].k = gload<NL>(w.a, (size_t)s_base[tg] + (p - s_start[tg]));
+          e[r].tag = tg;
+        } else {
+          e_set_sentinel(e[r]);
+        }
+      }
+      sort_tile_core<NT, E, MM>(tile, e, C, cnt);
+#pragma unroll
+      for (int r = 0; r < E; ++r) {
+        const uint32_t p = p0 + r;
+        if (p < cnt) out_perm[(size_t)s_base[e[r].tag] + (p - s_start[e[r].tag])] = key_index<NL>(e[r].k);
       }
     }
     __syncthreads();
@@ -966,8 +1067,8 @@ __global__ __launch_bounds__(NT) void k_merge(Ws w, int cls, int level, TileWork
     const int diag = threadIdx.x * E;
     Key<NL> e[E];
     if (diag < cnt) {
-      const int sa = lds_merge_path<NL>(tile, 0, na, na, nb, diag);
-      lds_register_merge<NL, E, MM>(tile, 0, na, na, nb, sa, diag - sa, e);
+      const int sa = lds_merge_path(tile, 0, na, na, nb, diag);
+      lds_register_merge<E, MM>(tile, 0, na, na, nb, sa, diag - sa, e);
     }
     __syncthreads();
     if (diag < cnt) {

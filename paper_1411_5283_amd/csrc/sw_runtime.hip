@@ -47,6 +47,7 @@ constexpr int kScatterNT = 512;  // threads per workgroup of k_scatter_pack
 // items) and the merge tile (NTM threads x EM items).
 struct Variant {
   void (*sort)(const Ws&, int, TileWork, unsigned, hipStream_t);
+  void (*packed)(const Ws&, int, unsigned, hipStream_t);
   void (*partition)(const Ws&, int, int, TileWork, unsigned, hipStream_t);
   void (*merge)(const Ws&, int, int, TileWork, unsigned, hipStream_t);
   const void* sort_fn;
@@ -62,6 +63,9 @@ struct V {
   static void sort(const Ws& w, int c, TileWork tw, unsigned grid, hipStream_t s) {
     sw::k_sort_tiles<NL, NTS, ES, MM><<<grid, NTS, 0, s>>>(w, c, tw);
   }
+  static void packed(const Ws& w, int c, unsigned grid, hipStream_t s) {
+    sw::k_sort_packed<NL, 8, 0><<<grid, sw::kPackTile / 8, 0, s>>>(w, c);
+  }
   static void partition(const Ws& w, int c, int l, TileWork tw, unsigned grid, hipStream_t s) {
     sw::k_partition<NL, kPartNT><<<grid, kPartNT, 0, s>>>(w, c, l, tw, (uint32_t)(NTM * EM));
   }
@@ -71,7 +75,7 @@ struct V {
   static Variant get() {
     static_assert(NTM * EM >= (int)sw::kMinMergeTile, "merge tile below the split-array sizing");
     static_assert(NTM * EM <= 2 * NTS * ES, "merge tile must divide a pair of sorted tiles");
-    return Variant{sort, partition, merge, (const void*)sw::k_sort_tiles<NL, NTS, ES, MM>,
+    return Variant{sort, packed, partition, merge, (const void*)sw::k_sort_tiles<NL, NTS, ES, MM>,
                    (const void*)sw::k_merge<NL, NTM, EM, MM>, (uint32_t)(NTS * ES), (uint32_t)(NTM * EM), NTS, NTM};
   }
 };
@@ -147,7 +151,7 @@ int device_info(DevInfo** out) {
 // ------------------------------------------------------------------ layout
 struct Layout {
   uint64_t Nmax = 0, Dmax = 0, Bmax = 0, Smax = 0, SBmax = 0, rec_stride = 0;
-  size_t o_hdr, o_doc_off, o_doc_blk, o_cnt, o_seg_n, o_seg_base, o_segcnt, o_sorted, o_st, o_mt, o_rec;
+  size_t o_hdr, o_doc_off, o_doc_blk, o_cnt, o_seg_n, o_seg_base, o_segcnt, o_sorted, o_st, o_mt, o_vpre, o_rec;
   size_t o_a[4], o_ai, o_b[4], o_bi;
   size_t total = 0;
 };
@@ -177,6 +181,7 @@ bool make_layout(uint64_t Nmax, uint64_t Dmax, Layout& L) {
   L.o_sorted = take(4 * L.Smax);
   L.o_st = take(4 * (L.Smax + sw::kNClass));
   L.o_mt = take(4 * (L.Smax + sw::kNClass));
+  L.o_vpre = take(4 * (L.Smax + sw::kNClass));
   L.rec_stride = Nmax / sw::kMinMergeTile + L.Smax + 2;
   L.o_rec = take(16 * sw::kNClass * L.rec_stride);
   for (int q = 0; q < 4; ++q) L.o_a[q] = take(8 * N1);
@@ -215,6 +220,7 @@ Ws make_ws(void* base, const Layout& L, const sw_config& cfg) {
   w.sorted = (uint32_t*)(p + L.o_sorted);
   w.st = (uint32_t*)(p + L.o_st);
   w.mt = (uint32_t*)(p + L.o_mt);
+  w.vpre = (uint32_t*)(p + L.o_vpre);
   w.rec = (uint4*)(p + L.o_rec);
   w.rec_stride = (uint32_t)L.rec_stride;
   for (int q = 0; q < 4; ++q) {
@@ -242,13 +248,14 @@ Ws make_ws(void* base, const Layout& L, const sw_config& cfg) {
 enum KernelId {
   K_BEGIN, K_DOC_PLAN, K_HIST, K_SCAN, K_SEGMENTS, K_SEG_COUNT, K_SEG_SCATTER, K_TILE_PREFIX, K_SCATTER,
   K_SORT0, K_SORT1, K_SORT2, K_SORT3, K_MERGE0, K_MERGE1, K_MERGE2, K_MERGE3,
-  K_PART0, K_PART1, K_PART2, K_PART3, K_COUNT
+  K_PART0, K_PART1, K_PART2, K_PART3, K_PACK0, K_PACK1, K_PACK2, K_PACK3, K_COUNT
 };
 const char* const kKernelNames[K_COUNT] = {
     "begin", "doc_plan", "hist", "scan_rows", "segments", "seg_count", "seg_scatter", "tile_prefix",
     "scatter_pack", "sort_tiles_c0", "sort_tiles_c1", "sort_tiles_c2", "sort_tiles_c3",
     "merge_c0", "merge_c1", "merge_c2", "merge_c3",
-    "partition_c0", "partition_c1", "partition_c2", "partition_c3"};
+    "partition_c0", "partition_c1", "partition_c2", "partition_c3",
+    "sort_packed_c0", "sort_packed_c1", "sort_packed_c2", "sort_packed_c3"};
 
 struct ProfRec {
   int kid;
@@ -298,7 +305,7 @@ struct ProfScope {
 struct Grids {
   uint32_t flags;
   unsigned words, scatter, docs, segs;
-  unsigned sort[sw::kNClass], merge[sw::kNClass], part[sw::kNClass];
+  unsigned sort[sw::kNClass], merge[sw::kNClass], part[sw::kNClass], packed;
   int levels[sw::kNClass];
   const Variant* var[sw::kNClass];
 };
@@ -313,6 +320,7 @@ int make_grids(const Ws& w, const sw_config& cfg, Grids& g) {
   g.words = clampg(w.Bmax, cus * (uint64_t)d->occ_hist);
   g.scatter = clampg(w.Bmax, cus * (uint64_t)d->occ_scatter);
   g.docs = clampg((w.Dmax + 3) / 4, cus * 4);
+  g.packed = clampg((uint64_t)w.Nmax / sw::kPackMax + 1, cus * 4);
   g.segs = clampg(w.SBmax, cus * 2);
   for (int c = 0; c < sw::kNClass; ++c) {
     int nv;
@@ -406,7 +414,7 @@ int enqueue_body(const Ws& w, const Grids& g, hipStream_t s, bool capture, bool 
     }
     {
       ProfScope p(K_TILE_PREFIX, s, capture);
-      sw::k_tile_prefix<1024><<<2 * sw::kNClass, 1024, 0, s>>>(w);
+      sw::k_tile_prefix<1024><<<3 * sw::kNClass, 1024, 0, s>>>(w);
     }
   }
   {
@@ -425,6 +433,10 @@ int enqueue_body(const Ws& w, const Grids& g, hipStream_t s, bool capture, bool 
     {
       ProfScope p(K_SORT0 + c, cs, capture);
       g.var[c]->sort(w, c, none, g.sort[c], cs);
+    }
+    {
+      ProfScope p(K_PACK0 + c, cs, capture);
+      g.var[c]->packed(w, c, g.packed, cs);
     }
     for (int l = 0; l < g.levels[c]; ++l) {
       {
@@ -503,7 +515,7 @@ Cache g_cache[64];
 extern "C" {
 
 const char* sort_words_last_error(void) { return g_err.c_str(); }
-const char* sort_words_version(void) { return "sortwords-gfx950 0.4"; }
+const char* sort_words_version(void) { return "sortwords-gfx950 0.5"; }
 
 size_t sort_words_workspace_size(uint32_t max_words, uint32_t max_docs) {
   Layout L;

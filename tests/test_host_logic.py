@@ -33,11 +33,13 @@ def test_levels_and_byte_model():
     assert bench.levels_for(1, 4096) == 0 and bench.levels_for(4096, 4096) == 0
     assert bench.levels_for(4097, 4096) == 1 and bench.levels_for(8192, 4096) == 1
     assert bench.levels_for(8193, 4096) == 2
-    fam = bench.algorithmic_bytes([(3, 10000), (6, 100)], [4096] * 4)
+    fam = bench.algorithmic_bytes([(3, 10000), (6, 100), (7, 3000)], [4096] * 4)
     # class 0 segment of 10000: m = 2 levels; chunk sort reads 8 and writes 8
     assert fam["sort_tiles_c0"] == 16 * 10000
     assert fam["merge_c0"] == (8 + 8) * 10000 + (8 + 4) * 10000
-    # class 1 segment of 100 fits one tile: finished by the chunk sort
-    assert fam["sort_tiles_c1"] == (12 + 4) * 100 and "merge_c1" not in fam
-    assert fam["hist"] == 4 * 10100
-    assert fam["scatter_pack"] == (4 + 3 + 8) * 10000 + (4 + 6 + 12) * 100
+    # a short class 1 segment is sorted in a packed tile; a 3000-word one fits
+    # one chunk-sort tile and is finished there
+    assert fam["sort_packed_c1"] == (12 + 4) * 100
+    assert fam["sort_tiles_c1"] == (12 + 4) * 3000 and "merge_c1" not in fam
+    assert fam["hist"] == 4 * 13100
+    assert fam["scatter_pack"] == (4 + 3 + 8) * 10000 + (4 + 6 + 12) * 100 + (4 + 7 + 12) * 3000
