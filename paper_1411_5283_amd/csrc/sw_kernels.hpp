@@ -129,17 +129,31 @@ __global__ __launch_bounds__(NT) void k_hist(Ws w) {
   for (uint32_t b = blockIdx.x; b < nblk; b += gridDim.x) {
     if (threadIdx.x < kNB) s_cnt[threadIdx.x] = 0;
     const BlockRange r = block_range<NT>(w, b, D, &s_doc);   // has a barrier
-    for (uint32_t i = r.ws + threadIdx.x; i < r.we; i += NT) {
-      const uint32_t a = off[i], e = off[i + 1];
-      uint32_t L = e - a;
-      if (e < a || a < off_lo || e > off_hi || (no_chars && e != a)) {
-        flags |= ST_INVALID;
-        L = 0;
-      } else if (L > (uint32_t)kMaxLen) {
-        flags |= ST_TOO_LONG;
-        L = kMaxLen;
+    // all of this thread's offsets are requested before any is used, so the
+    // block waits for one memory latency, not one per word
+    constexpr int IT = kWordsPerBlock / NT;
+    uint32_t oa[IT], oe[IT];
+#pragma unroll
+    for (int k = 0; k < IT; ++k) {
+      const uint32_t i = r.ws + threadIdx.x + k * NT;
+      oa[k] = i < r.we ? off[i] : 0u;
+      oe[k] = i < r.we ? off[i + 1] : 0u;
+    }
+#pragma unroll
+    for (int k = 0; k < IT; ++k) {
+      const uint32_t i = r.ws + threadIdx.x + k * NT;
+      if (i < r.we) {
+        const uint32_t a = oa[k], e = oe[k];
+        uint32_t L = e - a;
+        if (e < a || a < off_lo || e > off_hi || (no_chars && e != a)) {
+          flags |= ST_INVALID;
+          L = 0;
+        } else if (L > (uint32_t)kMaxLen) {
+          flags |= ST_TOO_LONG;
+          L = kMaxLen;
+        }
+        atomicAdd(&s_cnt[L], 1u);
       }
-      atomicAdd(&s_cnt[L], 1u);
     }
     __syncthreads();
     if (threadIdx.x < kNB) w.cnt[threadIdx.x * rs + b] = s_cnt[threadIdx.x];
@@ -434,13 +448,25 @@ __global__ __launch_bounds__(NT) void k_scatter_pack(Ws w) {
     const uint32_t span_dw = c1 > c0 ? (lead + (c1 - c0) + 3) >> 2 : 0u;
     const bool staged = span_dw <= kScatterChars / 4;
     {
+      // offsets then characters, UNR loads in flight per thread per step
+      constexpr int UNR = 8;
       const uint32_t* src = (const uint32_t*)abase;
-      const uint32_t ndw = staged ? span_dw : 0u;
-      for (uint32_t k = threadIdx.x; k < nw + 1 + ndw; k += NT) {
-        if (k <= nw)
-          s_off[k] = off[r.ws + k];
-        else
-          s_chr[k - nw - 1] = src[k - nw - 1];
+      const uint32_t ntot = nw + 1 + (staged ? span_dw : 0u);
+      for (uint32_t k0 = 0; k0 < ntot; k0 += NT * UNR) {
+        uint32_t v[UNR];
+#pragma unroll
+        for (int u = 0; u < UNR; ++u) {
+          const uint32_t k = k0 + threadIdx.x + u * NT;
+          v[u] = k < ntot ? (k <= nw ? off[r.ws + k] : src[k - nw - 1]) : 0u;
+        }
+#pragma unroll
+        for (int u = 0; u < UNR; ++u) {
+          const uint32_t k = k0 + threadIdx.x + u * NT;
+          if (k <= nw)
+            s_off[k] = v[u];
+          else if (k < ntot)
+            s_chr[k - nw - 1] = v[u];
+        }
       }
     }
     if (threadIdx.x < (uint32_t)kNB) {

@@ -228,3 +228,24 @@ def test_device_detected_errors(gpu):
     wl = wordgen.from_words([b"b", b"a"])
     p, b = gpu.sort_wordlist(wl)
     assert list(p) == [1, 0]
+
+
+def _doc_with_segment_sizes(sizes, seed):
+    """A document whose length-L bucket has sizes[L-1] words (random bytes)."""
+    rng = np.random.default_rng(seed)
+    words = []
+    for L, n in enumerate(sizes, start=1):
+        words += [bytes(rng.integers(97, 100, L, dtype=np.uint8)) for _ in range(n)]
+    order = rng.permutation(len(words))
+    return wordgen.from_words([words[i] for i in order])
+
+
+def test_packed_short_segments(gpu, oracle_mod):
+    # segment sizes around the packing threshold (1024) and many one-word segments
+    docs = [_doc_with_segment_sizes([1023, 1024, 1025, 1, 2, 511, 512, 513], seed=1),
+            _doc_with_segment_sizes([1] * 24, seed=2)]
+    docs += [_doc_with_segment_sizes([1, 0, 1, 3], seed=10 + d) for d in range(1500)]
+    docs += [_doc_with_segment_sizes([700, 300, 1024, 4], seed=3)]
+    wl = wordgen.concat_docs(docs)
+    _say("case packed segments docs=%d n=%d" % (wl.n_docs, wl.n))
+    _same(gpu.sort_wordlist(wl), _expect(oracle_mod, wl, bubble=False), "packed")
