@@ -1,0 +1,96 @@
+"""Summaries of rocprofv3 output for profiles/ (post-processing only).
+
+    python -m paper_1411_5283_amd.profsum stats <kernel_stats.csv> "<command>" <out.txt>
+    python -m paper_1411_5283_amd.profsum traffic <fetch.csv> <write.csv> <copy_fetch.csv> \
+        <copy_write.csv> <bench.json> <out.json>
+
+``traffic`` averages FETCH_SIZE and WRITE_SIZE (KiB per dispatch) per kernel
+family and scales them by what the same counters read for a plain 1 GiB
+device copy (hbm_copy_probe.py), so that the result is HBM bytes per launch.
+"""
+from __future__ import annotations
+
+import collections
+import csv
+import json
+import re
+import sys
+
+COPY_BYTES = 1 << 30
+COMMANDS = [
+    "rocprofv3 --pmc FETCH_SIZE --output-format csv -d gpurun_out/pmc_fetch -o f -- python3 bench.py "
+    "--serial --steps 1 --warmup 1 --profile-steps 1 --no-plain --no-cpu-baseline --no-check",
+    "rocprofv3 --pmc WRITE_SIZE --output-format csv -d gpurun_out/pmc_write -o w -- python3 bench.py "
+    "--serial --steps 1 --warmup 1 --profile-steps 1 --no-plain --no-cpu-baseline --no-check",
+    "rocprofv3 --pmc FETCH_SIZE --output-format csv -d gpurun_out/pmc_copyf -o cf -- python3 "
+    "paper_1411_5283_amd/hbm_copy_probe.py",
+    "rocprofv3 --pmc WRITE_SIZE --output-format csv -d gpurun_out/pmc_copyw -o cw -- python3 "
+    "paper_1411_5283_amd/hbm_copy_probe.py",
+]
+
+
+def stats(src: str, cmd: str, out: str) -> None:
+    rows = list(csv.DictReader(open(src)))
+    lines = ["# rocprofv3 kernel statistics", "#",
+             "# command (run from the repository root on one MI355X):", "#   " + cmd, "#",
+             "# %-64s %6s %14s %12s %7s" % ("kernel", "calls", "total_ns", "avg_ns", "pct")]
+    for r in rows:
+        lines.append("  %-64s %6s %14s %12.0f %7.2f" % (r["Name"][:64], r["Calls"], r["TotalDurationNs"],
+                                                       float(r["AverageNs"]), float(r["Percentage"])))
+    with open(out, "w") as f:
+        f.write("\n".join(lines) + "\n")
+
+
+def _family(kernel: str) -> str | None:
+    """Kernel name -> the bench's family name (class = template's first argument)."""
+    m = re.match(r"(?:void )?sw::k_(\w+?)<(\d+)", kernel)
+    if not m:
+        m2 = re.match(r"(?:void )?sw::k_(\w+?)[<(]", kernel)
+        return m2.group(1) if m2 else None
+    name, nl = m.group(1), int(m.group(2))
+    if name in ("scatter_pack", "hist"):
+        return name
+    cls = {0: 0, 1: 1, 2: 2, 4: 3}.get(nl)
+    return None if cls is None else "%s_c%d" % (name, cls)
+
+
+def _per_dispatch(path: str, counter: str) -> dict:
+    agg = collections.defaultdict(list)
+    for r in csv.DictReader(open(path)):
+        if r["Counter_Name"] == counter:
+            agg[r["Kernel_Name"].split("(")[0].replace("void ", "")].append(float(r["Counter_Value"]))
+    return {k: (sum(v) / len(v), len(v)) for k, v in agg.items()}
+
+
+def traffic(fetch: str, write: str, cfetch: str, cwrite: str, bench_json: str, out: str) -> None:
+    f = _per_dispatch(fetch, "FETCH_SIZE")
+    w = _per_dispatch(write, "WRITE_SIZE")
+    cf = _per_dispatch(cfetch, "FETCH_SIZE")["__amd_rocclr_copyBuffer"][0]
+    cw = _per_dispatch(cwrite, "WRITE_SIZE")["__amd_rocclr_copyBuffer"][0]
+    fs, wsc = COPY_BYTES / 1024 / cf, COPY_BYTES / 1024 / cw
+    with open(bench_json) as fh:
+        b = json.loads(fh.read().strip().splitlines()[-1])
+    kern = {}
+    for k, (fk, nd) in f.items():
+        fam = _family(k)
+        if fam is None or k not in w:
+            continue
+        wk = w[k][0]
+        kern[fam] = {"kernel": k, "dispatches": nd, "fetch_kib_per_dispatch": fk, "write_kib_per_dispatch": wk,
+                     "bytes_per_launch": fk * 1024 * fs + wk * 1024 * wsc}
+    res = {"source_hash": b["kernel_source"], "workload": b["config"]["workload"] + " (bench.py --serial)",
+           "fetch_scale": fs, "write_scale": wsc,
+           "calibration": "plain device copy of 1 GiB (__amd_rocclr_copyBuffer): FETCH_SIZE %.0f KiB, "
+                          "WRITE_SIZE %.0f KiB per dispatch" % (cf, cw),
+           "commands": COMMANDS, "kernels": kern}
+    with open(out, "w") as fh:
+        json.dump(res, fh, indent=1, sort_keys=True)
+
+
+if __name__ == "__main__":
+    if sys.argv[1] == "stats":
+        stats(*sys.argv[2:5])
+    elif sys.argv[1] == "traffic":
+        traffic(*sys.argv[2:8])
+    else:
+        raise SystemExit(__doc__)
