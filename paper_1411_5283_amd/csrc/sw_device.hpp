@@ -57,6 +57,14 @@ __host__ __device__ inline uint32_t levels_for(uint32_t n, uint32_t T) {
   return m;
 }
 
+// The same for a power-of-two tile T = 2^lt: the smallest m with T*2^m >= n is
+// ceil(log2 n) - lt (at least 0), and ceil(log2 n) is the bit length of n-1.
+__device__ inline uint32_t levels_pow2(uint32_t n, uint32_t lt) {
+  if (n <= 1) return 0;
+  const uint32_t bits = 32u - (uint32_t)__clz(n - 1);
+  return bits > lt ? bits - lt : 0u;
+}
+
 // ---------------------------------------------------------------- run state
 struct RunDesc {
   const uint8_t* chars;

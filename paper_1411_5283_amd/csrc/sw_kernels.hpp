@@ -581,6 +581,9 @@ struct LinRun {
   int base;
   __device__ typename Tile::value_type operator()(int i) const { return t.get(base + i); }
 };
+// Bit length of x (0 for 0): 2^bitlen(x) - 1 >= x.
+__device__ inline int bitlen(uint32_t x) { return 32 - (int)__clz(x); }
+
 // Merge path (Odeh et al., "Merge Path - Parallel Merging Made Simple", 2012):
 // number of A items among the first d outputs of the stable merge of A and B
 // (A first on ties).  Binary search by one thread.
@@ -594,6 +597,25 @@ __device__ inline int run_merge_path(const RA& A, int la, const RB& B, int lb, i
       lo = mid + 1;
     else
       hi = mid;
+  }
+  return lo;
+}
+
+// The same search by K halving steps, where 2^K - 1 >= min(la, lb) bounds the
+// search range.  With K the same for the whole wave the loop does not
+// diverge; each step reads A and B at indices clamped into the runs and only
+// counts when the probe lies in range, so no step branches on data.  A[0] and
+// B[0] must be readable.
+template <class RA, class RB>
+__device__ inline int run_merge_path_steps(const RA& A, int la, const RB& B, int lb, int d, int K) {
+  int lo = d > lb ? d - lb : 0;
+  const int hi = d < la ? d : la;
+  for (int k = K - 1; k >= 0; --k) {
+    const int a = lo + (1 << k) - 1;   // lo advances by 2^k when A[a] precedes B[d-1-a]
+    const int ai = a < la ? a : (la > 0 ? la - 1 : 0);
+    const int bi = d - 1 - a > 0 ? d - 1 - a : 0;
+    const bool take = a < hi && !e_less(B(bi), A(ai));
+    lo = take ? lo + (1 << k) : lo;
   }
   return lo;
 }
@@ -656,6 +678,44 @@ __device__ inline void lds_register_merge(const Tile& t, int a0, int la, int b0,
     run_serial_merge(LinRun<Tile>{t, a0}, la, LinRun<Tile>{t, b0}, lb, ai, bi, out);
   else
     run_bitonic_merge(LinRun<Tile>{t, a0}, la, LinRun<Tile>{t, b0}, lb, ai, bi, out);
+}
+
+// The same two steps on a merge tile laid out with sentinels: run A at
+// [0, la), a sentinel at la, run B at [la+1, la+1+lb), a sentinel after it,
+// and at least E more readable slots.  Reads past both sentinels only feed
+// outputs beyond the tile's count, which are never stored, so the serial
+// merge needs no clamping.
+template <class Tile>
+__device__ inline int padded_merge_path(const Tile& t, int la, int lb, int d) {
+  return run_merge_path_steps(LinRun<Tile>{t, 0}, la, LinRun<Tile>{t, la + 1}, lb, d,
+                              bitlen((uint32_t)(la < lb ? la : lb)));
+}
+
+template <int E, class Tile>
+__device__ inline void padded_serial_merge(const Tile& t, int la, int ai, int bi,
+                                           typename Tile::value_type (&out)[E]) {
+  using K = typename Tile::value_type;
+  int pa = ai, pb = la + 1 + bi;
+  K ha = t.get(pa), hb = t.get(pb);
+#pragma unroll
+  for (int j = 0; j < E; ++j) {
+    const bool takeB = e_less(hb, ha);
+    out[j] = e_select(takeB, hb, ha);
+    pa += takeB ? 0 : 1;
+    pb += takeB ? 1 : 0;
+    const K nv = t.get(takeB ? pb : pa);
+    ha = e_select(takeB, ha, nv);
+    hb = e_select(takeB, nv, hb);
+  }
+}
+
+template <int E, int MM, class Tile>
+__device__ inline void padded_register_merge(const Tile& t, int la, int lb, int ai, int bi,
+                                             typename Tile::value_type (&out)[E]) {
+  if (MM == 0)
+    padded_serial_merge<E>(t, la, ai, bi, out);
+  else
+    run_bitonic_merge(LinRun<Tile>{t, 0}, la, LinRun<Tile>{t, la + 1}, lb, ai, bi, out);
 }
 
 // Sorting core of a tile held as E items per thread in registers (blocked:
@@ -920,10 +980,11 @@ struct MergeTile {
   uint64_t o0, ps;
   uint32_t la, lb, d0, d1;
 };
+// R and P are powers of two, so the pair start is a mask, not a division.
 __device__ inline MergeTile merge_tile(uint32_t n, uint32_t j, uint64_t R, uint32_t P) {
   MergeTile m;
   m.o0 = (uint64_t)j * P;
-  m.ps = m.o0 / (2 * R) * (2 * R);
+  m.ps = m.o0 & ~(2 * R - 1);
   const uint32_t rem = n - (uint32_t)m.ps;
   m.la = (uint32_t)min((uint64_t)rem, R);
   m.lb = rem - m.la < R ? rem - m.la : (uint32_t)R;
@@ -1003,7 +1064,7 @@ __global__ __launch_bounds__(NT) void k_partition(Ws w, int cls, int level, Tile
 struct TileIO {
   size_t apos, bpos, ob;
   int na, cnt;
-  bool final;
+  int final;   // nonzero on the segment's last level
 };
 __device__ inline TileIO tile_io(const TileRec& r, uint32_t next_split, uint64_t R, uint32_t P, uint32_t Tc,
                                  int level) {
@@ -1015,7 +1076,7 @@ __device__ inline TileIO tile_io(const TileRec& r, uint32_t next_split, uint64_t
   io.ob = (size_t)r.base + m.o0;
   io.na = (int)(a1 - r.split);
   io.cnt = (int)(m.d1 - m.d0);
-  io.final = levels_for(r.n, Tc) == (uint32_t)level + 1;
+  io.final = levels_pow2(r.n, (uint32_t)__ffs(Tc) - 1) == (uint32_t)level + 1;
   return io;
 }
 
@@ -1045,7 +1106,8 @@ __device__ inline void load_tile_regs(const KeyBuf& src, const TileIO& io, Key<N
 template <int NL, int NT, int E, int MM>
 __global__ __launch_bounds__(NT) void k_merge(Ws w, int cls, int level, TileWork tw) {
   constexpr int P = NT * E;
-  __shared__ LdsTile<NL, P> tile;
+  // inputs with the two sentinels, plus the slots a finished thread may read
+  __shared__ LdsTile<NL, P + 2 * E> tile;
   Header* h = w.h;
   if (h->abort) return;
   const uint32_t Tc = w.T[cls];
@@ -1075,7 +1137,11 @@ __global__ __launch_bounds__(NT) void k_merge(Ws w, int cls, int level, TileWork
 #pragma unroll
     for (int r = 0; r < E; ++r) {
       const int i = threadIdx.x + r * NT;
-      if (i < cur.cnt) tile.put(i, pf[r]);
+      if (i < cur.cnt) tile.put(i < cur.na ? i : i + 1, pf[r]);
+    }
+    if (threadIdx.x == 0) {
+      tile.put(cur.na, key_sentinel<NL>());
+      tile.put(cur.cnt + 1, key_sentinel<NL>());
     }
     __syncthreads();
     // the next tile's inputs and the record of the one after
@@ -1093,8 +1159,8 @@ __global__ __launch_bounds__(NT) void k_merge(Ws w, int cls, int level, TileWork
     const int diag = threadIdx.x * E;
     Key<NL> e[E];
     if (diag < cnt) {
-      const int sa = lds_merge_path(tile, 0, na, na, nb, diag);
-      lds_register_merge<E, MM>(tile, 0, na, na, nb, sa, diag - sa, e);
+      const int sa = padded_merge_path(tile, na, nb, diag);
+      padded_register_merge<E, MM>(tile, na, nb, sa, diag - sa, e);
     }
     __syncthreads();
     if (diag < cnt) {
