@@ -262,6 +262,19 @@ __device__ inline void gstore<0>(const KeyBuf& b, size_t p, const Key<0>& v) {
   b.k[0][p] = v.k;
 }
 
+// Streaming stores (nontemporal hint) for outputs that the next kernel reads
+// only after the whole level has been written.
+template <int NL>
+__device__ inline void gstore_nt(const KeyBuf& b, size_t p, const Key<NL>& v) {
+#pragma unroll
+  for (int q = 0; q < NL; ++q) __builtin_nontemporal_store(v.k[q], b.k[q] + p);
+  __builtin_nontemporal_store(v.idx, b.idx + p);
+}
+template <>
+__device__ inline void gstore_nt<0>(const KeyBuf& b, size_t p, const Key<0>& v) {
+  __builtin_nontemporal_store(v.k, b.k[0] + p);
+}
+
 template <int NL>
 __device__ inline Key<NL> key_select(bool c, const Key<NL>& x, const Key<NL>& y) {
   Key<NL> r;

@@ -1174,9 +1174,9 @@ __global__ __launch_bounds__(NT) void k_merge(Ws w, int cls, int level, TileWork
       if (o < cnt) {
         const Key<NL> v = tile.get(o);
         if (cur.final)
-          out_perm[cur.ob + o] = key_index<NL>(v);
+          __builtin_nontemporal_store(key_index<NL>(v), out_perm + cur.ob + o);
         else
-          gstore<NL>(dst, cur.ob + o, v);
+          gstore_nt<NL>(dst, cur.ob + o, v);
       }
     }
     __syncthreads();

@@ -81,20 +81,23 @@ struct V {
 };
 
 // The last template argument picks the register merge: 0 serial, 1 bitonic.
-constexpr int kMaxVariants = 6;
+constexpr int kMaxVariants = 8;
 const Variant* variants(int c, int* count) {
   static const Variant v0[] = {V<0, 256, 16, 256, 16, 0>::get(), V<0, 256, 8, 256, 8, 0>::get(),
                                V<0, 512, 16, 256, 16, 0>::get(), V<0, 512, 16, 256, 8, 0>::get(),
-                               V<0, 512, 16, 256, 16, 1>::get(), V<0, 512, 16, 256, 8, 1>::get()};
+                               V<0, 512, 16, 256, 16, 1>::get(), V<0, 512, 16, 256, 8, 1>::get(),
+                               V<0, 1024, 16, 256, 16, 0>::get()};
   static const Variant v1[] = {V<1, 256, 16, 256, 16, 0>::get(), V<1, 256, 8, 256, 8, 0>::get(),
                                V<1, 512, 16, 256, 8, 0>::get(), V<1, 512, 16, 256, 16, 0>::get(),
-                               V<1, 512, 16, 256, 8, 1>::get(), V<1, 256, 8, 256, 8, 1>::get()};
+                               V<1, 512, 16, 256, 8, 1>::get(), V<1, 256, 8, 256, 8, 1>::get(),
+                               V<1, 1024, 8, 256, 16, 0>::get()};
   static const Variant v2[] = {V<2, 256, 16, 256, 16, 0>::get(), V<2, 256, 8, 256, 8, 0>::get(),
-                               V<2, 256, 8, 256, 16, 0>::get(), V<2, 256, 8, 256, 8, 1>::get()};
+                               V<2, 256, 8, 256, 16, 0>::get(), V<2, 256, 8, 256, 8, 1>::get(),
+                               V<2, 512, 8, 256, 8, 1>::get(), V<2, 512, 8, 256, 16, 0>::get()};
   static const Variant v3[] = {V<4, 256, 16, 256, 16, 0>::get(), V<4, 256, 8, 256, 8, 0>::get(),
                                V<4, 128, 16, 128, 16, 0>::get()};
   static const Variant* all[] = {v0, v1, v2, v3};
-  static const int counts[] = {6, 6, 4, 3};
+  static const int counts[] = {7, 7, 6, 3};
   *count = counts[c];
   return all[c];
 }

@@ -55,7 +55,7 @@ def _same(got, exp, what):
     assert np.array_equal(gb, eb), "%s: bucket offsets differ" % what
 
 
-@pytest.mark.parametrize("variant", [0, 1, 2, 3, 4, 5])
+@pytest.mark.parametrize("variant", [0, 1, 2, 3, 4, 5, 6])
 def test_long_segments_every_variant(gpu, oracle_mod, default_config, variant):
     # 1.5M words over few lengths: many merge levels and many tiles per workgroup
     wl = wordgen.single(1_500_000, 40_000, 1.1, 20, seed=5)
@@ -79,7 +79,7 @@ def test_config2_chunk1024_bit_exact(gpu, oracle_mod, default_config):
 
 
 @pytest.mark.parametrize("chunk", [16, 32, 64, 128, 256, 512, 1024])
-@pytest.mark.parametrize("variant", [0, 1, 2, 3, 4, 5])
+@pytest.mark.parametrize("variant", [0, 1, 2, 3, 4, 5, 6])
 def test_chunk_and_variant_sweep(gpu, oracle_mod, default_config, chunk, variant):
     # several tiles, merge levels and a ragged tail in every class
     wl = wordgen.single(41_000, 3000, 1.0, 32, seed=77)
