@@ -386,15 +386,16 @@ __device__ inline void load_be_lanes(const uint8_t* p, uint32_t L, uint64_t (&la
 }
 
 // Big-endian lanes of an L-byte word whose first byte is byte `pos` of a
-// dword array held in LDS (pos counts from the array's first byte).
+// dword array held in LDS (pos counts from the array's first byte).  The
+// 2*NQ+1 dwords from the word's first one are read whatever L is: the array
+// must extend that far (bytes past the word are masked off below).
 template <int NQ>
 __device__ inline void lds_be_lanes(const uint32_t* dw, uint32_t pos, uint32_t L, uint64_t (&lane)[NQ]) {
   const uint32_t s = pos & 3;
   const uint32_t* base = dw + (pos >> 2);
-  const uint32_t nd = L ? (s + L + 3) >> 2 : 0u;
   uint32_t wv[2 * NQ + 1];
 #pragma unroll
-  for (int j = 0; j < 2 * NQ + 1; ++j) wv[j] = (uint32_t)j < nd ? __builtin_bswap32(base[j]) : 0u;
+  for (int j = 0; j < 2 * NQ + 1; ++j) wv[j] = __builtin_bswap32(base[j]);
 #pragma unroll
   for (int q = 0; q < NQ; ++q) {
     const uint64_t hi = ((uint64_t)wv[2 * q] << 32) | wv[2 * q + 1];
@@ -422,7 +423,7 @@ __global__ __launch_bounds__(NT) void k_scatter_pack(Ws w) {
   constexpr uint32_t PER_WAVE = kWordsPerBlock / NW;
   constexpr int IT = PER_WAVE / 64;
   __shared__ uint32_t s_off[kWordsPerBlock + 1];
-  __shared__ uint32_t s_chr[kScatterChars / 4];
+  __shared__ uint32_t s_chr[kScatterChars / 4 + 9];   // + the dwords lds_be_lanes<4> may read past the end
   __shared__ uint32_t s_run[NW][kNB];
   __shared__ uint32_t s_bstart[kNB + 1];
   __shared__ uint32_t s_gbase[kNB];
@@ -520,21 +521,39 @@ __global__ __launch_bounds__(NT) void k_scatter_pack(Ws w) {
       const uint32_t L = min(s_off[i + 1] - a, (uint32_t)kMaxLen);
       const uint32_t dest = s_gbase[L] + (p - s_bstart[L]);
       const uint32_t idx = r.ws + i - doc0;
-      uint64_t ln[4];
-      if (staged)
-        lds_be_lanes<4>(s_chr, lead + (a - c0), L, ln);
-      else
-        load_be_lanes<4>(chars + a, L, ln);
+      const uint32_t pos = lead + (a - c0);
+      // only the lanes of the word's class are built (a wave's slots mostly
+      // share one length, so the branch rarely diverges)
       const int c = class_of_len(L);
-      if (c == 0) {
-        w.a.k[0][dest] = (ln[0] & 0xFFFFFFFF00000000ull) | idx;
-      } else {
-        w.a.k[0][dest] = ln[0];
-        if (c >= 2) w.a.k[1][dest] = ln[1];
-        if (c >= 3) {
-          w.a.k[2][dest] = ln[2];
-          w.a.k[3][dest] = ln[3];
+      if (c <= 1) {
+        uint64_t ln[1];
+        if (staged)
+          lds_be_lanes<1>(s_chr, pos, L, ln);
+        else
+          load_be_lanes<1>(chars + a, L, ln);
+        if (c == 0) {
+          w.a.k[0][dest] = (ln[0] & 0xFFFFFFFF00000000ull) | idx;
+        } else {
+          w.a.k[0][dest] = ln[0];
+          w.a.idx[dest] = idx;
         }
+      } else if (c == 2) {
+        uint64_t ln[2];
+        if (staged)
+          lds_be_lanes<2>(s_chr, pos, L, ln);
+        else
+          load_be_lanes<2>(chars + a, L, ln);
+        w.a.k[0][dest] = ln[0];
+        w.a.k[1][dest] = ln[1];
+        w.a.idx[dest] = idx;
+      } else {
+        uint64_t ln[4];
+        if (staged)
+          lds_be_lanes<4>(s_chr, pos, L, ln);
+        else
+          load_be_lanes<4>(chars + a, L, ln);
+#pragma unroll
+        for (int q = 0; q < 4; ++q) w.a.k[q][dest] = ln[q];
         w.a.idx[dest] = idx;
       }
     }

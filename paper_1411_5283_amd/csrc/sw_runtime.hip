@@ -431,8 +431,14 @@ int enqueue_body(const Ws& w, const Grids& g, hipStream_t s, bool capture, bool 
     for (int c = 1; c < sw::kNClass; ++c) HIP_TRY(hipStreamWaitEvent(fork->side[c], fork->fork, 0));
   }
   const TileWork none{0, 0, 0, 0};
+  // Each class keeps its own order on its own stream; across classes the work
+  // is enqueued stage by stage (all chunk sorts, then merge level 0 of every
+  // class, level 1, ...), so that a runtime which maps the parallel chains
+  // onto fewer hardware queues still finds every class's next kernel early.
+  auto cstream = [&](int c) { return (par && c > 0) ? fork->side[c] : s; };
+  int max_levels = 0;
   for (int c = 0; c < sw::kNClass; ++c) {
-    hipStream_t cs = (par && c > 0) ? fork->side[c] : s;
+    hipStream_t cs = cstream(c);
     {
       ProfScope p(K_SORT0 + c, cs, capture);
       g.var[c]->sort(w, c, none, g.sort[c], cs);
@@ -441,7 +447,12 @@ int enqueue_body(const Ws& w, const Grids& g, hipStream_t s, bool capture, bool 
       ProfScope p(K_PACK0 + c, cs, capture);
       g.var[c]->packed(w, c, g.packed, cs);
     }
-    for (int l = 0; l < g.levels[c]; ++l) {
+    max_levels = std::max(max_levels, g.levels[c]);
+  }
+  for (int l = 0; l < max_levels; ++l) {
+    for (int c = 0; c < sw::kNClass; ++c) {
+      if (l >= g.levels[c]) continue;
+      hipStream_t cs = cstream(c);
       {
         ProfScope p(K_PART0 + c, cs, capture);
         g.var[c]->partition(w, c, l, none, g.part[c], cs);
