@@ -741,20 +741,46 @@ __device__ inline void padded_register_merge(const Tile& t, int la, int lb, int 
 // thread t holds items t*E..t*E+E-1 of the tile): odd-even transposition on
 // chunks of C, then merge-path rounds through LDS until one run covers the
 // tile's cnt real items (the rest of the tile is sentinels, already in place).
+// In the round that merges runs of R, item i sits in slot i + i/R: every run
+// is followed by a sentinel slot, so the serial merge reads one slot per
+// output without a bounds test (its positions only stop at the run's
+// sentinel).  The tile must hold T + T/E slots.
 template <int NT, int E, int MM, class Tile>
 __device__ inline void sort_tile_core(Tile& tile, typename Tile::value_type (&e)[E], uint32_t C, uint32_t cnt) {
+  using K = typename Tile::value_type;
   constexpr int T = NT * E;
   oddeven_chunks(e, C);
   for (uint32_t R = C; R < (uint32_t)T && R < cnt; R <<= 1) {
+    const int lr = __ffs((int)R) - 1;   // R is a power of two, at least E
+    const int o = threadIdx.x * E;
+    const int g = o + (o >> lr);        // a thread's E items lie inside one run
     __syncthreads();
 #pragma unroll
-    for (int r = 0; r < E; ++r) tile.put(threadIdx.x * E + r, e[r]);
+    for (int r = 0; r < E; ++r) tile.put(g + r, e[r]);
+    if (((o + E) & (int)(R - 1)) == 0) tile.put(g + E, e_sentinel<K>());
     __syncthreads();
-    const int o = threadIdx.x * E;
     const int p0 = o & ~(int)(2 * R - 1);
     const int d = o - p0;
-    const int a = lds_merge_path(tile, p0, (int)R, p0 + (int)R, (int)R, d);
-    lds_register_merge<E, MM>(tile, p0, (int)R, p0 + (int)R, (int)R, a, d - a, e);
+    const int sa = p0 + (p0 >> lr), sb = sa + (int)R + 1;
+    const int a = lds_merge_path(tile, sa, (int)R, sb, (int)R, d);
+    if (MM == 0) {
+      // after a run's last item its position stays on the run's sentinel
+      int pa = sa + a, pb = sb + (d - a);
+      const int ea = sa + (int)R, eb = sb + (int)R;
+      K ha = tile.get(pa), hb = tile.get(pb);
+#pragma unroll
+      for (int j = 0; j < E; ++j) {
+        const bool takeB = e_less(hb, ha);
+        e[j] = e_select(takeB, hb, ha);
+        pa = takeB ? pa : min(pa + 1, ea);
+        pb = takeB ? min(pb + 1, eb) : pb;
+        const K nv = tile.get(takeB ? pb : pa);
+        ha = e_select(takeB, ha, nv);
+        hb = e_select(takeB, nv, hb);
+      }
+    } else {
+      run_bitonic_merge(LinRun<Tile>{tile, sa}, (int)R, LinRun<Tile>{tile, sb}, (int)R, a, d - a, e);
+    }
   }
 }
 
@@ -848,7 +874,7 @@ __device__ inline TileSeg find_tile(const Ws& w, const uint32_t* prefix, uint32_
 template <int NL, int NT, int E, int MM>
 __global__ __launch_bounds__(NT) void k_sort_tiles(Ws w, int cls, TileWork tw) {
   constexpr int T = NT * E;
-  __shared__ LdsTile<NL, T> tile;
+  __shared__ LdsTile<NL, T + T / E> tile;
   Header* h = w.h;
   if (h->abort) return;
   uint32_t C = w.chunk[cls];
@@ -919,7 +945,7 @@ template <int NL, int E, int MM>
 __global__ __launch_bounds__(kPackTile / E) void k_sort_packed(Ws w, int cls) {
   constexpr int NT = kPackTile / E;
   constexpr uint32_t H = kPackMax;
-  __shared__ TLdsTile<NL, kPackTile> tile;
+  __shared__ TLdsTile<NL, kPackTile + kPackTile / E> tile;
   __shared__ uint32_t s_start[kPackMax + 1];   // segment starts inside the tile
   __shared__ uint32_t s_base[kPackMax];        // segment first output positions
   __shared__ uint32_t s_rng[3];

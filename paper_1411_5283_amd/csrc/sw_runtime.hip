@@ -94,8 +94,8 @@ const Variant* variants(int c, int* count) {
   static const Variant v2[] = {V<2, 256, 16, 256, 16, 0>::get(), V<2, 256, 8, 256, 8, 0>::get(),
                                V<2, 256, 8, 256, 16, 0>::get(), V<2, 256, 8, 256, 8, 1>::get(),
                                V<2, 512, 8, 256, 8, 1>::get(), V<2, 512, 8, 256, 16, 0>::get()};
-  static const Variant v3[] = {V<4, 256, 16, 256, 16, 0>::get(), V<4, 256, 8, 256, 8, 0>::get(),
-                               V<4, 128, 16, 128, 16, 0>::get()};
+  static const Variant v3[] = {V<4, 256, 8, 256, 8, 0>::get(), V<4, 128, 16, 128, 16, 0>::get(),
+                               V<4, 128, 16, 256, 8, 0>::get()};
   static const Variant* all[] = {v0, v1, v2, v3};
   static const int counts[] = {7, 7, 6, 3};
   *count = counts[c];
@@ -529,7 +529,7 @@ Cache g_cache[64];
 extern "C" {
 
 const char* sort_words_last_error(void) { return g_err.c_str(); }
-const char* sort_words_version(void) { return "sortwords-gfx950 0.5"; }
+const char* sort_words_version(void) { return "sortwords-gfx950 0.6"; }
 
 size_t sort_words_workspace_size(uint32_t max_words, uint32_t max_docs) {
   Layout L;
