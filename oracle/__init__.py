@@ -18,6 +18,11 @@ Functions (host numpy arrays in, numpy arrays out):
   outputs of inputs too large to sort on the CPU).
 * ``paper_chunk_size`` -- chunk size = array size / number of processors
   (section 5, Results), rounded up so that the chunks cover the array.
+* ``oracle_tokenize`` -- the first pre-processing phase (section 3): raw text
+  to the word list, special characters removed.  Plain C.
+* ``oracle_materialize`` -- the sorted words written out as text (section 4:
+  the merged chunks are printed).  Plain C; ``oracle_materialize_batch`` runs
+  it per document.
 
 Parity: pinned by brute force over all permutations of tiny inputs, by
 invariants, closed forms and Python's stable ``sorted`` (tests/test_oracle.py).
@@ -37,7 +42,8 @@ _LIB = os.path.join(_HERE, "liboracle.so")
 MAX_LEN = 32
 N_OFFSETS = MAX_LEN + 2
 
-OK, INVALID_ARG, WORD_TOO_LONG, OOM = 0, -1, -2, -4
+OK, INVALID_ARG, WORD_TOO_LONG, CAPACITY, OOM = 0, -1, -2, -3, -4
+TOK_LOWER = 1
 
 _lib = None
 
@@ -70,6 +76,11 @@ def _load():
         lib.oracle_rank.restype = ctypes.c_uint64
         lib.oracle_length_counts.argtypes = [u32p, ctypes.c_uint32, u64p]
         lib.oracle_length_counts.restype = None
+        lib.oracle_tokenize.argtypes = [u8p, ctypes.c_uint64, ctypes.c_uint32, u8p, u32p,
+                                        ctypes.c_uint32, u32p]
+        lib.oracle_tokenize.restype = ctypes.c_int
+        lib.oracle_materialize.argtypes = [u8p, u32p, ctypes.c_uint32, u32p, ctypes.c_int, u8p]
+        lib.oracle_materialize.restype = ctypes.c_int
         _lib = lib
     return _lib
 
@@ -200,3 +211,51 @@ def paper_chunk_size(array_size: int, processors: int) -> int:
     if processors <= 0:
         raise ValueError("processors must be positive")
     return -(-int(array_size) // int(processors))
+
+
+def oracle_tokenize(text, flags: int = 0, max_words=None):
+    """(chars, offsets) of the words of raw text: runs between ASCII whitespace,
+    letters only, other bytes removed (flags & TOK_LOWER: lower case)."""
+    t = np.frombuffer(bytes(text), np.uint8) if not isinstance(text, np.ndarray) else \
+        np.ascontiguousarray(text, dtype=np.uint8)
+    n = t.shape[0]
+    cap = (n + 1) // 2 if max_words is None else int(max_words)
+    buf = t if n else np.zeros(1, np.uint8)
+    chars = np.zeros(max(n, 1), np.uint8)
+    offs = np.zeros(cap + 1, np.uint32)
+    nw = np.zeros(1, np.uint32)
+    rc = _load().oracle_tokenize(_p(buf, ctypes.c_uint8), n, int(flags), _p(chars, ctypes.c_uint8),
+                                 _p(offs, ctypes.c_uint32), cap, _p(nw, ctypes.c_uint32))
+    if rc != OK:
+        raise OracleError(rc)
+    k = int(nw[0])
+    return chars[:int(offs[k])].copy(), offs[:k + 1].copy()
+
+
+def oracle_materialize(chars, offsets, perm, sep: int = 10) -> bytes:
+    """Word perm[k] for k = 0..n-1, each followed by byte ``sep`` (none if sep < 0)."""
+    chars, offsets = _prep(chars, offsets)
+    n = offsets.shape[0] - 1
+    perm = np.ascontiguousarray(perm, dtype=np.uint32)
+    if perm.shape[0] != n:
+        raise OracleError(INVALID_ARG)
+    size = int(offsets[-1]) - int(offsets[0]) + (n if sep >= 0 else 0) if n else 0
+    out = np.zeros(max(size, 1), np.uint8)
+    pp = perm if n else np.zeros(1, np.uint32)
+    rc = _load().oracle_materialize(_p(chars, ctypes.c_uint8), _p(offsets, ctypes.c_uint32), n,
+                                    _p(pp, ctypes.c_uint32), int(sep), _p(out, ctypes.c_uint8))
+    if rc != OK:
+        raise OracleError(rc)
+    return out[:size].tobytes()
+
+
+def oracle_materialize_batch(chars, offsets, doc_offsets, perm, sep: int = 10) -> bytes:
+    """Per document (doc-local perm), documents back to back."""
+    chars, offsets = _prep(chars, offsets)
+    doc_offsets = np.asarray(doc_offsets, dtype=np.int64)
+    perm = np.asarray(perm, dtype=np.uint32)
+    parts = []
+    for d in range(doc_offsets.shape[0] - 1):
+        lo, hi = int(doc_offsets[d]), int(doc_offsets[d + 1])
+        parts.append(oracle_materialize(chars, offsets[lo:hi + 1], perm[lo:hi], sep))
+    return b"".join(parts)

@@ -32,7 +32,12 @@
  *
  * Every entry point takes host pointers.  Return codes: 0 ok, -1 invalid
  * argument (a null pointer, or offsets that decrease), -2 a word longer than
- * 32 bytes, -4 out of host memory.
+ * 32 bytes, -3 more words than the caller's output holds, -4 out of host
+ * memory.
+ *
+ * Around the sort: oracle_tokenize is the first pre-processing phase (raw
+ * text to the word list) and oracle_materialize writes the sorted words out
+ * as text (section 4: the master merges the chunks and prints the result).
  */
 #define _GNU_SOURCE
 #include <stdint.h>
@@ -42,7 +47,7 @@
 #define ORC_MAX_LEN 32
 #define ORC_NBUCKET (ORC_MAX_LEN + 1)
 
-enum { ORC_OK = 0, ORC_INVALID = -1, ORC_TOO_LONG = -2, ORC_OOM = -4 };
+enum { ORC_OK = 0, ORC_INVALID = -1, ORC_TOO_LONG = -2, ORC_CAPACITY = -3, ORC_OOM = -4 };
 
 /* Phase-1 check shared by every entry point: offsets non-decreasing, every
  * length at most ORC_MAX_LEN.  A decreasing offset outranks a long word. */
@@ -262,4 +267,80 @@ void oracle_length_counts(const uint32_t *offsets, uint32_t n, uint64_t *counts)
         uint32_t L = word_len(offsets, i);
         counts[L > ORC_MAX_LEN ? ORC_MAX_LEN : L] += 1;
     }
+}
+
+/* ---------------------------------------------------------------- phase 1
+ * First phase of "Pre-processing" (section 3): the special characters of the
+ * text are removed.  Reading: words are the runs of bytes between ASCII
+ * whitespace (tab, line feed, vertical tab, form feed, carriage return,
+ * space); inside a run only the ASCII letters are kept, in order, and every
+ * other byte (digit, punctuation, control, non-ASCII) is dropped without
+ * splitting the run; a run left without letters is no word.  With flag bit 0
+ * set, capitals become lower case.
+ * Output: chars = the kept letters of all words back to back; offsets =
+ * n_words+1 entries from 0 (out_offsets must hold max_words+1).  Returns 0,
+ * or -3 when the text has more than max_words words. */
+static int is_space(uint8_t c) { return c == ' ' || (c >= 9 && c <= 13); }
+static int is_letter(uint8_t c) { return (c >= 'a' && c <= 'z') || (c >= 'A' && c <= 'Z'); }
+
+int oracle_tokenize(const uint8_t *text, uint64_t n_bytes, uint32_t flags, uint8_t *out_chars,
+                    uint32_t *out_offsets, uint32_t max_words, uint32_t *n_words)
+{
+    uint32_t nw = 0, nc = 0;
+    int started = 0;   /* the current run already holds a letter */
+    for (uint64_t i = 0; i < n_bytes; ++i) {
+        const uint8_t c = text[i];
+        if (is_space(c)) {
+            started = 0;
+            continue;
+        }
+        if (!is_letter(c))
+            continue;   /* a special character: removed */
+        if (!started) {
+            if (nw == max_words)
+                return ORC_CAPACITY;
+            out_offsets[nw++] = nc;
+            started = 1;
+        }
+        out_chars[nc++] = (flags & 1u) && c <= 'Z' ? (uint8_t)(c + 32) : c;
+    }
+    out_offsets[nw] = nc;
+    *n_words = nw;
+    return ORC_OK;
+}
+
+/* ---------------------------------------------------------------- output
+ * The sorted text (section 4: the merged result is printed): word perm[k]
+ * for k = 0..n-1, each followed by the byte sep when 0 <= sep <= 255, back to
+ * back when sep < 0.  out holds offsets[n]-offsets[0] bytes, plus n with a
+ * separator.  perm must be a permutation of 0..n-1 and offsets must not
+ * decrease; otherwise -1. */
+int oracle_materialize(const uint8_t *chars, const uint32_t *offsets, uint32_t n,
+                       const uint32_t *perm, int sep, uint8_t *out)
+{
+    if (n && (!offsets || !perm))
+        return ORC_INVALID;
+    for (uint32_t i = 0; i < n; ++i)
+        if (offsets[i + 1] < offsets[i])
+            return ORC_INVALID;
+    uint8_t *seen = calloc(n ? n : 1, 1);
+    if (!seen)
+        return ORC_OOM;
+    size_t pos = 0;
+    int rc = ORC_OK;
+    for (uint32_t k = 0; k < n; ++k) {
+        const uint32_t i = perm[k];
+        if (i >= n || seen[i]) {
+            rc = ORC_INVALID;
+            break;
+        }
+        seen[i] = 1;
+        const uint32_t L = offsets[i + 1] - offsets[i];
+        memcpy(out + pos, chars + offsets[i], L);
+        pos += L;
+        if (sep >= 0 && sep <= 255)
+            out[pos++] = (uint8_t)sep;
+    }
+    free(seen);
+    return rc;
 }
