@@ -37,7 +37,7 @@ WORKLOADS = {
               "20k-word Zipf(1.0) vocabulary, lengths 1-20, 8 GiB HBM budget"),
 }
 CSRC = [os.path.join(ROOT, "paper_1411_5283_amd", "csrc", f)
-        for f in ("sw_device.hpp", "sw_kernels.hpp", "sw_runtime.hip")]
+        for f in ("sw_device.hpp", "sw_kernels.hpp", "sw_text.hpp", "sw_runtime.hip")]
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "hbm_traffic.json")
 
 
@@ -267,6 +267,87 @@ def serve_bench(args, sw, wordgen, torch):
 
 
 # ------------------------------------------------------------------ main
+def text_bench(args, sw, wordgen, torch, wl, chars, offs, docs, perm, boff, perm_h, boff_h, stream):
+    """The steps around the sort on the same workload: the word list written as
+    raw text (capitals, punctuation, line breaks) is tokenized back on the GPU
+    (lower-case folding), and the sorted result is written out as text with a
+    line break after every word.  Both are timed with HIP events on the bench
+    stream and checked (the tokenized list must equal the word list; sampled
+    words of the sorted text must equal the words perm names)."""
+    n, nd = wl.n, wl.n_docs
+    dev = chars.device
+    t0 = time.perf_counter()
+    raw = wordgen.render_text(wl, 14115283)
+    log("rendered %d bytes of text in %.1f s" % (raw.size, time.perf_counter() - t0))
+    reps = 5
+    text = torch.from_numpy(raw).to(dev)
+    nb = raw.size
+    tchars = torch.empty(max(nb, 1), dtype=torch.uint8, device=dev)
+    toffs = torch.empty(n + 2, dtype=torch.int32, device=dev)
+    tnw = torch.zeros(1, dtype=torch.int32, device=dev)
+    tws = torch.empty(sw.tokenize_workspace_size(nb), dtype=torch.uint8, device=dev)
+    run_tok = lambda: sw.tokenize(text, nb, sw.TOK_LOWER, tchars, toffs, n + 1, tnw, tws, stream)
+    run_tok()
+    sw.sort_words_status(tws, stream)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(reps):
+        run_tok()
+    e1.record(stream)
+    torch.cuda.synchronize()
+    sw.sort_words_status(tws, stream)
+    tok_ms = e0.elapsed_time(e1) / reps
+    nw = int(tnw.cpu()[0])
+    letters = int(offs[n].item()) - int(offs[0].item()) if n else 0
+    tok_ok = nw == n and bool(torch.equal(toffs[:n + 1], offs[:n + 1] - offs[0])) and \
+        bool(torch.equal(tchars[:letters], chars[:letters]))
+    tok_bytes = 2 * nb + letters + 4 * (nw + 1)      # text read twice, letters and offsets written
+    log("tokenize: %.3f ms, %d words, same=%s" % (tok_ms, nw, tok_ok))
+    del text, tchars, toffs, tws
+
+    size = letters + n
+    out = torch.empty(max(size, 1), dtype=torch.uint8, device=dev)
+    st = torch.zeros(1, dtype=torch.int32, device=dev)
+    run_mat = lambda: sw.materialize(chars, offs, docs, nd, n, perm, boff, 10, out, st, stream)
+    run_mat()
+    torch.cuda.synchronize()
+    e0.record(stream)
+    for _ in range(reps):
+        run_mat()
+    e1.record(stream)
+    torch.cuda.synchronize()
+    mat_ms = e0.elapsed_time(e1) / reps
+    status = int(st.cpu()[0])
+    # sampled check: the text of a few hundred sorted positions
+    rng = np.random.default_rng(5)
+    ks = rng.integers(0, n, 300) if n else []
+    out_h = out.cpu().numpy()
+    doc_h = wl.doc_offsets if wl.doc_offsets is not None else np.array([0, n], np.uint32)
+    bo = boff_h[:nd * 34].reshape(nd, 34).astype(np.int64)
+    mat_ok = status == 0
+    for k in ks:
+        d = int(np.searchsorted(doc_h, k, side="right") - 1)
+        kl = int(k) - int(doc_h[d])
+        L = int(np.searchsorted(bo[d], kl, side="right") - 1)
+        cnt = np.diff(bo[d])
+        pos = int(wl.offsets[doc_h[d]]) - int(wl.offsets[0]) + int(doc_h[d])
+        pos += int(sum(int(cnt[l]) * (l + 1) for l in range(L))) + (kl - int(bo[d][L])) * (L + 1)
+        i = int(doc_h[d]) + int(perm_h[k])
+        w = wl.chars[wl.offsets[i]:wl.offsets[i + 1]].tobytes()
+        mat_ok &= out_h[pos:pos + L + 1].tobytes() == w + b"\n"
+    mat_bytes = 4 * n + 8 * n + letters + size       # perm, offsets, characters, text
+    log("materialize: %.3f ms, status=%d, sampled check=%s" % (mat_ms, status, mat_ok))
+    del out
+    return {
+        "tokenize": {"ms": tok_ms, "text_bytes": nb, "words": nw, "Mwords_per_s": nw / (tok_ms / 1e3) / 1e6,
+                     "algorithmic_GBs": tok_bytes / (tok_ms / 1e3) / 1e9, "same_as_word_list": tok_ok,
+                     "input": "the word list rendered as text: capitals, punctuation, line breaks, digits"},
+        "materialize": {"ms": mat_ms, "text_bytes": size, "Mwords_per_s": n / (mat_ms / 1e3) / 1e6,
+                        "algorithmic_GBs": mat_bytes / (mat_ms / 1e3) / 1e9, "status": status,
+                        "sampled_check": bool(mat_ok), "separator": "line feed"},
+    }
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -279,6 +360,8 @@ def main():
     ap.add_argument("--no-check", action="store_true")
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--untuned", action="store_true", help="ignore the autotuner cache")
+    ap.add_argument("--no-text", action="store_true",
+                    help="skip the tokenizer and sorted-text measurements around the sort")
     ap.add_argument("--serial", action="store_true",
                     help="run the key classes one after another (for per-kernel profiling)")
     ap.add_argument("--serve-warmup", type=int, default=200)
@@ -435,6 +518,8 @@ def main():
             "whole_pass_GBs_at_plan_time": total_bytes / (ms_step / 1e3) / 1e9,
             "eager_kernel_sum_ms": tsum}
 
+    text = None if args.no_text else text_bench(args, sw, wordgen, torch, wl, chars, offs, docs, perm, boff,
+                                                   perm_h, boff_h, stream)
     cpu = None if args.no_cpu_baseline else cpu_baseline(wl)
     out = {
         "metric": METRIC, "value": value, "unit": "Mwords/s", "n_gpus": 1, "steps": args.steps,
@@ -449,6 +534,7 @@ def main():
         "batched_over_plain": (value / plain["value"]) if plain else None,
         "check": check,
         "roofline": roof,
+        "around_the_sort": text,
         "cpu_baseline": cpu,
         "kernel_source": kernel_source_hash(),
     }

@@ -179,6 +179,50 @@ int sw_profile_enable(int on);
 int sw_profile_reset(void);
 int sw_profile_read(int max_entries, const char **names, uint32_t *launches, double *ms);
 
+/* ------------------------------------------------------------ around the sort
+ * Tokenizer: the first pre-processing phase of section 3 (special characters
+ * removed from the text before the words are listed).  A word is a run of
+ * bytes between ASCII whitespace (tab, line feed, vertical tab, form feed,
+ * carriage return, space); inside a run the ASCII letters are kept in order
+ * and every other byte is dropped without ending the run; a run left without
+ * letters is no word.  With SW_TOK_LOWER capitals become lower case.
+ *   text         device, n_bytes bytes (n_bytes < 2^32; any pointer alignment)
+ *   out_chars    device, n_bytes bytes of capacity: the kept letters
+ *   out_offsets  device, max_words+1 entries: word w is
+ *                out_chars[out_offsets[w] .. out_offsets[w+1]), out_offsets[0] = 0
+ *   out_n_words  device, 1 word: the number of words
+ *   workspace    device, sort_words_tokenize_workspace_size(n_bytes) bytes
+ * The result is the word list sort_words* take.  Asynchronous on `stream`;
+ * more words than max_words is SW_ERR_WORKSPACE, read with
+ * sort_words_status(workspace, stream) (outputs then unspecified). */
+#define SW_TOK_LOWER 1u
+size_t sort_words_tokenize_workspace_size(uint64_t n_bytes);
+int sort_words_tokenize(const uint8_t *text, uint64_t n_bytes, uint32_t flags,
+                        uint8_t *out_chars, uint32_t *out_offsets, uint32_t max_words,
+                        uint32_t *out_n_words, void *workspace, size_t workspace_bytes,
+                        void *stream);
+
+/* Sorted text: section 4 prints the merged result.  Writes the words in
+ * sorted order, each followed by the byte `sep` (0..255), or back to back
+ * when sep < 0.
+ *   chars, offsets, doc_offsets, n_docs  the word list given to the sort
+ *                (doc_offsets NULL with n_docs = 1: one document)
+ *   n_words      total words N
+ *   perm, bucket_offsets  the sort's outputs (document-local indices,
+ *                n_docs * SW_NUM_OFFSETS offsets)
+ *   out_text     device, (offsets[N] - offsets[0]) + (sep >= 0 ? N : 0) bytes;
+ *                document d's text starts at byte
+ *                (offsets[doc_offsets[d]] - offsets[0]) + (sep >= 0 ? doc_offsets[d] : 0)
+ *   out_status   device, 1 word: set to 0, then nonzero if a word fails a
+ *                check (index outside its document, offsets outside the word
+ *                list, length unlike its bucket's, bytes past the output); such
+ *                a word is not written and no byte outside out_text ever is.
+ * Asynchronous on `stream`; host-side argument errors are returned. */
+int sort_words_materialize(const uint8_t *chars, const uint32_t *offsets,
+                           const uint32_t *doc_offsets, uint32_t n_docs, uint32_t n_words,
+                           const uint32_t *perm, const uint32_t *bucket_offsets, int sep,
+                           uint8_t *out_text, uint32_t *out_status, void *stream);
+
 const char *sort_words_last_error(void);
 const char *sort_words_version(void);
 

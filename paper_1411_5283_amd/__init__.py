@@ -78,6 +78,9 @@ def lib() -> ctypes.CDLL:
         "sw_profile_reset": ([], i32),
         "sw_profile_read": ([i32, ctypes.POINTER(ctypes.c_char_p), ctypes.POINTER(u32),
                              ctypes.POINTER(ctypes.c_double)], i32),
+        "sort_words_tokenize_workspace_size": ([ctypes.c_uint64], sz),
+        "sort_words_tokenize": ([vp, ctypes.c_uint64, u32, vp, vp, u32, vp, vp, sz, vp], i32),
+        "sort_words_materialize": ([vp, vp, vp, u32, u32, vp, vp, i32, vp, vp, vp], i32),
         "sort_words_last_error": ([], ctypes.c_char_p),
         "sort_words_version": ([], ctypes.c_char_p),
     }
@@ -94,7 +97,8 @@ EXPORTED = ("sort_words", "sort_words_workspace_size", "sort_words_ex", "sort_wo
             "sort_words_decode_status", "sw_plan_create", "sw_plan_run",
             "sw_plan_status", "sw_plan_status_async", "sw_plan_destroy", "sw_get_config", "sw_set_config",
             "sw_num_variants", "sw_variant_tiles", "sw_profile_enable", "sw_profile_reset",
-            "sw_profile_read", "sort_words_last_error", "sort_words_version")
+            "sw_profile_read", "sort_words_tokenize_workspace_size", "sort_words_tokenize",
+            "sort_words_materialize", "sort_words_last_error", "sort_words_version")
 
 
 def _check(rc: int) -> int:
@@ -256,6 +260,35 @@ def profile_read() -> dict:
 
 def version() -> str:
     return lib().sort_words_version().decode()
+
+
+# ------------------------------------------------------------------ around the sort
+TOK_LOWER = 1
+
+
+def tokenize_workspace_size(n_bytes: int) -> int:
+    return int(lib().sort_words_tokenize_workspace_size(int(n_bytes)))
+
+
+def tokenize(text, n_bytes, flags, out_chars, out_offsets, max_words, out_n_words, workspace, stream=None):
+    """sort_words_tokenize on device tensors (asynchronous; errors via sort_words_status(workspace))."""
+    return _check(lib().sort_words_tokenize(_ptr(text), int(n_bytes), int(flags), _ptr(out_chars),
+                                            _ptr(out_offsets), int(max_words), _ptr(out_n_words),
+                                            _ptr(workspace), workspace.numel(), _stream(stream)))
+
+
+def materialize(chars, offsets, doc_offsets, n_docs, n_words, perm, bucket_offsets, sep, out_text,
+                out_status, stream=None):
+    """sort_words_materialize on device tensors (asynchronous; out_status nonzero = a check failed)."""
+    return _check(lib().sort_words_materialize(_ptr(chars), _ptr(offsets), _ptr(doc_offsets), int(n_docs),
+                                               int(n_words), _ptr(perm), _ptr(bucket_offsets), int(sep),
+                                               _ptr(out_text), _ptr(out_status), _stream(stream)))
+
+
+def text_size(wl, sep: int) -> int:
+    """Bytes of the sorted text of a word list (one separator per word when sep >= 0)."""
+    n = wl.n
+    return int(wl.offsets[n]) - int(wl.offsets[0]) + (n if sep >= 0 else 0) if n else 0
 
 
 # ------------------------------------------------------------------ host helpers

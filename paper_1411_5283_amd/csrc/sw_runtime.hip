@@ -13,6 +13,7 @@
 
 #include "sort_words.h"
 #include "sw_kernels.hpp"
+#include "sw_text.hpp"
 
 namespace {
 
@@ -851,6 +852,61 @@ int sw_profile_read(int max_entries, const char** names, uint32_t* launches, dou
     if (ms) ms[n] = g_prof_ms[k];
   }
   return n;
+}
+
+// ------------------------------------------------------------------ around the sort
+static uint64_t tok_blocks(uint64_t n_bytes) { return (n_bytes + sw::kTokBlock - 1) / sw::kTokBlock; }
+static size_t tok_header_bytes() { return (sizeof(Header) + 255) & ~(size_t)255; }
+
+size_t sort_words_tokenize_workspace_size(uint64_t n_bytes) {
+  if (n_bytes >= (1ull << 32)) return 0;
+  return tok_header_bytes() + 2 * tok_blocks(n_bytes) * sizeof(uint4) + 256;
+}
+
+int sort_words_tokenize(const uint8_t* text, uint64_t n_bytes, uint32_t flags, uint8_t* out_chars,
+                        uint32_t* out_offsets, uint32_t max_words, uint32_t* out_n_words, void* workspace,
+                        size_t workspace_bytes, void* stream) {
+  if (!out_offsets || !out_n_words || !workspace || (n_bytes && (!text || !out_chars)))
+    return fail(SW_ERR_INVALID_ARG, "sort_words_tokenize: null pointer argument");
+  if (n_bytes >= (1ull << 32)) return fail(SW_ERR_INVALID_ARG, "sort_words_tokenize: text of 2^32 bytes or more");
+  if (flags & ~SW_TOK_LOWER) return fail(SW_ERR_INVALID_ARG, "sort_words_tokenize: unknown flags 0x%x", flags);
+  if (workspace_bytes < sort_words_tokenize_workspace_size(n_bytes))
+    return fail(SW_ERR_WORKSPACE, "sort_words_tokenize: workspace too small");
+  hipStream_t s = (hipStream_t)stream;
+  Header* h = (Header*)workspace;
+  const uint32_t nblk = (uint32_t)tok_blocks(n_bytes);
+  uint4* sums = (uint4*)((char*)workspace + tok_header_bytes());
+  uint4* pre = sums + nblk;
+  sw::k_tok_begin<<<1, 64, 0, s>>>(h);
+  if (nblk) sw::k_tok_sum<<<nblk, sw::kTokNT, 0, s>>>(text, n_bytes, sums);
+  sw::k_tok_scan<1024><<<1, 1024, 0, s>>>(h, sums, pre, nblk, max_words, out_offsets, out_n_words);
+  if (nblk) sw::k_tok_write<<<nblk, sw::kTokNT, 0, s>>>(h, text, n_bytes, pre, flags, out_chars, out_offsets);
+  HIP_TRY(hipGetLastError());
+  return SW_OK;
+}
+
+int sort_words_materialize(const uint8_t* chars, const uint32_t* offsets, const uint32_t* doc_offsets,
+                           uint32_t n_docs, uint32_t n_words, const uint32_t* perm, const uint32_t* bucket_offsets,
+                           int sep, uint8_t* out_text, uint32_t* out_status, void* stream) {
+  if (!offsets || !bucket_offsets || !out_status || (n_words && (!chars || !perm || !out_text)))
+    return fail(SW_ERR_INVALID_ARG, "sort_words_materialize: null pointer argument");
+  if (sep > 255) return fail(SW_ERR_INVALID_ARG, "sort_words_materialize: separator %d is not a byte", sep);
+  if (doc_offsets ? n_docs == 0 : n_docs != 1)
+    return fail(SW_ERR_INVALID_ARG, "sort_words_materialize: n_docs must be 1 without doc_offsets, >= 1 with");
+  hipStream_t s = (hipStream_t)stream;
+  sw::k_mat_begin<<<1, 64, 0, s>>>(out_status);
+  if (n_words) {
+    DevInfo* d;
+    int rc = device_info(&d);
+    if (rc) return rc;
+    constexpr int NT = 256;
+    const unsigned grid =
+        (unsigned)std::max<uint64_t>(1, std::min<uint64_t>((n_words + NT - 1) / NT, (uint64_t)d->cus * 8));
+    sw::k_materialize<NT><<<grid, NT, 0, s>>>(chars, offsets, doc_offsets, n_docs, n_words, perm, bucket_offsets,
+                                              sep, out_text, out_status);
+  }
+  HIP_TRY(hipGetLastError());
+  return SW_OK;
 }
 
 }  // extern "C"

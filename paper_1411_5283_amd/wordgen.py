@@ -207,3 +207,55 @@ def concat_docs(lists) -> WordList:
         doc.append(doc[-1] + w.n)
     offsets = np.concatenate(offs)
     return WordList(chars, offsets.astype(np.uint32), np.asarray(doc, np.uint32))
+
+
+# Raw text for the tokenizer: a word list written out as prose.  Only bytes
+# that carry no letters are added (spaces, line breaks, punctuation, digits in
+# place of some separators), and some first letters are made capitals, so
+# tokenizing with lower-case folding gives the word list back.
+_PUNCT = np.frombuffer(b",.;:!?\")", np.uint8)
+_OPEN = np.frombuffer(b"(\"", np.uint8)
+
+
+def render_text(wl: WordList, seed: int) -> np.ndarray:
+    """The whole word list as text (in pieces of _CHUNK words, each seeded on its own)."""
+    parts = []
+    for j, lo in enumerate(range(0, max(wl.n, 1), _CHUNK)):
+        hi = min(wl.n, lo + _CHUNK)
+        offs = wl.offsets[lo:hi + 1]
+        parts.append(_render(wl.chars, offs, seed + j))
+    return np.concatenate(parts) if len(parts) > 1 else parts[0]
+
+
+def _render(chars: np.ndarray, offsets: np.ndarray, seed: int) -> np.ndarray:
+    rng = np.random.Generator(np.random.PCG64(seed))
+    n = offsets.shape[0] - 1
+    offs = offsets.astype(np.int64)
+    L = np.diff(offs)
+    pre = (rng.random(n) < 0.02).astype(np.int64)           # opening bracket or quote
+    suf = (rng.random(n) < 0.15).astype(np.int64)           # trailing punctuation
+    sep_kind = rng.random(n)
+    sep = np.where(sep_kind < 0.02, 2, 1).astype(np.int64)  # some separators are a space and a digit
+    size = pre + L + suf + sep
+    start = np.zeros(n + 1, np.int64)
+    np.cumsum(size, out=start[1:])
+    out = np.full(int(start[-1]), ord(" "), np.uint8)
+    if n == 0:
+        return out
+    # letters, with some first letters made capitals
+    first = start[:-1] + pre
+    dst = np.repeat(first - offs[:-1], L) + np.arange(int(offs[-1] - offs[0]), dtype=np.int64) + offs[0]
+    out[dst] = chars[offs[0]:offs[-1]]
+    cap = (rng.random(n) < 0.1) & (L > 0)
+    out[first[cap]] -= 32
+    out[start[:-1][pre == 1]] = _OPEN[rng.integers(0, _OPEN.size, int(pre.sum()))]
+    after = first + L
+    out[after[suf == 1]] = _PUNCT[rng.integers(0, _PUNCT.size, int(suf.sum()))]
+    # separators: mostly a space, sometimes a line break, sometimes a space
+    # followed by a digit (dropped from the run it starts)
+    sp = after + suf
+    line = sep_kind > 0.93
+    out[sp[line]] = ord("\n")
+    two = sep == 2
+    out[sp[two] + 1] = ord("0") + rng.integers(0, 10, int(two.sum())).astype(np.uint8)
+    return out

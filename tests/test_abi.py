@@ -61,3 +61,21 @@ def test_host_side_calls_without_gpu():
     assert sw.num_variants(0) >= 1 and sw.num_variants(7) == 0
     t, p = sw.variant_tiles(0, 0)
     assert t >= 1024 and p >= 1024 and (t & (t - 1)) == 0
+
+
+def test_text_entry_points_validate_on_host():
+    """Argument errors of the tokenizer and the text writer are found before any GPU call."""
+    import paper_1411_5283_amd as sw
+    L = sw.lib()
+    assert L.sort_words_tokenize_workspace_size(1 << 32) == 0
+    assert L.sort_words_tokenize_workspace_size(0) > 0
+    # null outputs, a text of 2^32 bytes, unknown flags
+    assert L.sort_words_tokenize(None, 10, 0, None, None, 4, None, None, 0, None) == sw.ERR_INVALID_ARG
+    assert L.sort_words_tokenize(1, 1 << 32, 0, 1, 1, 4, 1, 1, 1 << 20, None) == sw.ERR_INVALID_ARG
+    assert L.sort_words_tokenize(1, 10, 6, 1, 1, 4, 1, 1, 1 << 20, None) == sw.ERR_INVALID_ARG
+    assert L.sort_words_tokenize(1, 10, 0, 1, 1, 4, 1, 1, 8, None) == sw.ERR_WORKSPACE
+    # the text writer: null pointers, a separator above 255, n_docs without doc_offsets
+    assert L.sort_words_materialize(None, None, None, 1, 0, None, None, 10, None, None, None) == sw.ERR_INVALID_ARG
+    assert L.sort_words_materialize(1, 1, None, 1, 5, 1, 1, 256, 1, 1, None) == sw.ERR_INVALID_ARG
+    assert L.sort_words_materialize(1, 1, None, 2, 5, 1, 1, 10, 1, 1, None) == sw.ERR_INVALID_ARG
+    assert L.sort_words_materialize(1, 1, 1, 0, 5, 1, 1, 10, 1, 1, None) == sw.ERR_INVALID_ARG
