@@ -209,12 +209,32 @@ __global__ __launch_bounds__(NT) void k_tok_scan(Header* h, const uint4* sums, u
   }
 }
 
-// Pass 3: every thread rescans its bytes and writes its letters and the
-// offsets of the words that start among them.
+// Bytes [0, len) of an LDS buffer to global memory at dst (any alignment):
+// the head up to a 4-byte boundary and the tail byte by byte, the middle as
+// whole dwords, consecutive threads on consecutive dwords.
+template <int NT>
+__device__ inline void lds_bytes_to_global(const uint8_t* src, uint32_t len, uint8_t* dst) {
+  const uint32_t head = min(len, (uint32_t)((4u - ((uintptr_t)dst & 3u)) & 3u));
+  const uint32_t body = (len - head) >> 2;
+  for (uint32_t i = threadIdx.x; i < head; i += NT) dst[i] = src[i];
+  uint32_t* d32 = (uint32_t*)(dst + head);
+  for (uint32_t j = threadIdx.x; j < body; j += NT) {
+    const uint8_t* q = src + head + 4 * j;
+    d32[j] = (uint32_t)q[0] | ((uint32_t)q[1] << 8) | ((uint32_t)q[2] << 16) | ((uint32_t)q[3] << 24);
+  }
+  for (uint32_t i = head + 4 * body + threadIdx.x; i < len; i += NT) dst[i] = src[i];
+}
+
+// Pass 3: every thread rescans its bytes; its letters and the offsets of the
+// words starting among them go to LDS at their places in the workgroup's
+// output (which is one contiguous stretch of chars and one of offsets), and
+// the workgroup stores both stretches whole.
 __global__ __launch_bounds__(kTokNT) void k_tok_write(Header* h, const uint8_t* text, uint64_t n, const uint4* pre,
                                                       uint32_t flags, uint8_t* out_chars, uint32_t* out_offsets) {
   __shared__ uint32_t s_last[kTokNT / 64];
   __shared__ uint32_t s_tmp[kTokNT / 64];
+  __shared__ uint8_t s_chr[kTokBlock];
+  __shared__ uint32_t s_off[kTokBlock / 2];
   if (h->abort) return;
   const uint64_t b = blockIdx.x;
   const uint64_t p = b * kTokBlock + (uint64_t)threadIdx.x * kTokBytes;
@@ -226,9 +246,9 @@ __global__ __launch_bounds__(kTokNT) void k_tok_write(Header* h, const uint8_t* 
   uint32_t carry = tok_carry_in_block<kTokNT>(s.last, s_last);
   if (carry == TS_NONE) carry = bp.z;
   const uint32_t starts = carry == TS_LETTER ? s.starts_letter : s.starts_space;
-  uint32_t tot;
-  uint32_t lpos = bp.x + block_excl_scan<kTokNT>(s.letters, s_tmp, tot);
-  uint32_t wpos = bp.y + block_excl_scan<kTokNT>(starts, s_tmp, tot);
+  uint32_t nl, nwd;
+  uint32_t lpos = block_excl_scan<kTokNT>(s.letters, s_tmp, nl);   // inside the workgroup
+  uint32_t wpos = block_excl_scan<kTokNT>(starts, s_tmp, nwd);
   const uint32_t fold = (flags & kTokFlagLower) ? 32u : 0u;
   uint32_t cur = carry;
   for (uint32_t i = 0; i < cnt; ++i) {
@@ -236,11 +256,14 @@ __global__ __launch_bounds__(kTokNT) void k_tok_write(Header* h, const uint8_t* 
     if (tok_space(c)) {
       cur = TS_SPACE;
     } else if (tok_letter(c)) {
-      if (cur != TS_LETTER) out_offsets[wpos++] = lpos;
-      out_chars[lpos++] = (uint8_t)(c | (c < 97u ? fold : 0u));
+      if (cur != TS_LETTER) s_off[wpos++] = bp.x + lpos;
+      s_chr[lpos++] = (uint8_t)(c | (c < 97u ? fold : 0u));
       cur = TS_LETTER;
     }
   }
+  __syncthreads();
+  lds_bytes_to_global<kTokNT>(s_chr, nl, out_chars + bp.x);
+  for (uint32_t j = threadIdx.x; j < nwd; j += kTokNT) out_offsets[bp.y + j] = s_off[j];
 }
 
 // ---------------------------------------------------------------- sorted text
@@ -258,58 +281,140 @@ __global__ void k_mat_begin(uint32_t* status) {
   if (threadIdx.x == 0) *status = 0u;
 }
 
+// Document of output position k: the last d with doc_offsets[d] <= k.
+__device__ inline uint32_t mat_doc(const uint32_t* doc_offsets, uint32_t n_docs, uint32_t k) {
+  uint32_t lo = 0, hi = n_docs;
+  while (hi - lo > 1) {
+    const uint32_t mid = (lo + hi) >> 1;
+    if (doc_offsets[mid] <= k)
+      lo = mid;
+    else
+      hi = mid;
+  }
+  return lo;
+}
+
+// The bucket of a document-local position: the last L with bo[L] <= kl.
+template <class BO>
+__device__ inline uint32_t mat_bucket(const BO& bo, uint32_t kl) {
+  uint32_t L = 0;
+#pragma unroll
+  for (uint32_t step = 32; step >= 1; step >>= 1)
+    if (L + step <= (uint32_t)kMaxLen && bo[L + step] <= kl) L += step;
+  return L;
+}
+
+// A workgroup takes NT consecutive output positions.  The bucket table of the
+// document of its first position sits in LDS (words of later documents read
+// theirs from memory).  When every word of the workgroup passes its checks
+// and the words' places follow each other, they are assembled in LDS and
+// stored as one stretch; otherwise each good word is written on its own.
 template <int NT>
 __global__ __launch_bounds__(NT) void k_materialize(const uint8_t* chars, const uint32_t* offsets,
                                                     const uint32_t* doc_offsets, uint32_t n_docs, uint32_t N,
                                                     const uint32_t* perm, const uint32_t* boff, int sep,
                                                     uint8_t* out, uint32_t* status) {
+  __shared__ uint8_t s_txt[NT * (kMaxLen + 1)];
+  __shared__ uint64_t s_base[kNB];
+  __shared__ uint32_t s_bo[kNOff];
+  __shared__ uint32_t s_doc[3];
+  __shared__ uint32_t s_tmp[NT / 64];
+  __shared__ uint64_t s_pos0;
   const uint32_t s = sep >= 0 ? 1u : 0u;
   const uint32_t o0 = offsets[0], oN = offsets[N];
   const uint64_t out_size = (uint64_t)(oN - o0) + (uint64_t)s * N;
-  for (uint32_t k = blockIdx.x * NT + threadIdx.x; k < N; k += gridDim.x * NT) {
-    // document of output position k: last d with doc_offsets[d] <= k
-    uint32_t d = 0, dend = N;
-    if (doc_offsets) {
-      uint32_t lo = 0, hi = n_docs;
-      while (hi - lo > 1) {
-        const uint32_t mid = (lo + hi) >> 1;
-        if (doc_offsets[mid] <= k)
-          lo = mid;
-        else
-          hi = mid;
+  for (uint32_t k0 = blockIdx.x * NT; k0 < N; k0 += gridDim.x * NT) {
+    if (threadIdx.x == 0) {
+      const uint32_t d = doc_offsets ? mat_doc(doc_offsets, n_docs, k0) : 0u;
+      s_doc[0] = d;
+      s_doc[1] = doc_offsets ? doc_offsets[d] : 0u;
+      s_doc[2] = doc_offsets ? doc_offsets[d + 1] : N;
+    }
+    __syncthreads();
+    const uint32_t d0 = s_doc[0], ds0 = s_doc[1], de0 = s_doc[2];
+    if (threadIdx.x < (uint32_t)kNOff) s_bo[threadIdx.x] = boff[(size_t)d0 * kNOff + threadIdx.x];
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      // text position of each bucket of document d0 (only meaningful if its
+      // offsets are in range; every word is checked below anyway)
+      uint64_t pos = ds0 <= N ? (uint64_t)(offsets[ds0] - o0) + (uint64_t)s * ds0 : 0u;
+      for (int L = 0; L < kNB; ++L) {
+        s_base[L] = pos;
+        pos += (uint64_t)(s_bo[L + 1] - s_bo[L]) * (L + s);
       }
-      d = lo;
-      dend = doc_offsets[d + 1];
     }
-    const uint32_t dstart = doc_offsets ? doc_offsets[d] : 0u;
-    if (dstart > k || k >= dend || dend > N) {
-      atomicOr(status, 1u);
-      continue;
+    __syncthreads();
+    const uint32_t k = k0 + threadIdx.x;
+    bool ok = false;
+    uint64_t pos = 0;
+    uint32_t L = 0, a = 0;
+    if (k < N) {
+      uint32_t d = d0, dstart = ds0, dend = de0;
+      if (doc_offsets && !(k >= ds0 && k < de0)) {
+        d = mat_doc(doc_offsets, n_docs, k);
+        dstart = doc_offsets[d];
+        dend = doc_offsets[d + 1];
+      }
+      if (dstart <= k && k < dend && dend <= N) {
+        const uint32_t kl = k - dstart;
+        uint32_t bL;
+        if (d == d0) {
+          L = mat_bucket(s_bo, kl);
+          bL = s_bo[L];
+          pos = s_base[L];
+        } else {
+          const uint32_t* bo = boff + (size_t)d * kNOff;
+          L = mat_bucket(bo, kl);
+          bL = bo[L];
+          pos = (uint64_t)(offsets[dstart] - o0) + (uint64_t)s * dstart;
+          for (uint32_t l = 0; l < L; ++l) pos += (uint64_t)(bo[l + 1] - bo[l]) * (l + s);
+        }
+        pos += (uint64_t)(kl - bL) * (L + s);
+        const uint32_t i = perm[k];
+        ok = i < dend - dstart && kl >= bL && pos + L + s <= out_size;
+        if (ok) {
+          a = offsets[dstart + i];
+          const uint32_t e = offsets[dstart + i + 1];
+          ok = a >= o0 && e <= oN && e >= a && e - a == L;
+        }
+      }
+      if (!ok) atomicOr(status, 1u);
     }
-    const uint32_t* bo = boff + (size_t)d * kNOff;
-    const uint32_t kl = k - dstart;
-    // bucket of the document-local position: last L with bo[L] <= kl
-    uint32_t L = 0;
-#pragma unroll
-    for (uint32_t step = 32; step >= 1; step >>= 1)
-      if (L + step <= (uint32_t)kMaxLen && bo[L + step] <= kl) L += step;
-    uint64_t pos = (uint64_t)(offsets[dstart] - o0) + (uint64_t)s * dstart;
-    for (uint32_t l = 0; l < L; ++l) pos += (uint64_t)(bo[l + 1] - bo[l]) * (l + s);
-    pos += (uint64_t)(kl - bo[L]) * (L + s);
-    const uint32_t i = perm[k];
-    bool ok = i < dend - dstart && kl >= bo[L] && pos + L + s <= out_size;
-    uint32_t a = 0;
+    // the word's bytes: the aligned dwords covering [a, a + L); a dword that
+    // holds one of the word's bytes lies in the same page, so reading it whole
+    // stays inside mapped memory
+    uint32_t wv[9];
     if (ok) {
-      a = offsets[dstart + i];
-      const uint32_t e = offsets[dstart + i + 1];
-      ok = a >= o0 && e <= oN && e >= a && e - a == L;
+      const uint32_t* src = (const uint32_t*)((uintptr_t)(chars + a) & ~(uintptr_t)3);
+      const uint32_t nd = L ? (((uintptr_t)(chars + a) & 3u) + L + 3) >> 2 : 0u;
+#pragma unroll
+      for (int j = 0; j < 9; ++j) wv[j] = (uint32_t)j < nd ? src[j] : 0u;
     }
-    if (!ok) {
-      atomicOr(status, 1u);
-      continue;
+    const uint32_t sh = (uint32_t)((uintptr_t)(chars + a) & 3u);
+    const uint32_t size = ok ? L + s : 0u;
+    uint32_t total;
+    const uint32_t rel = block_excl_scan<NT>(size, s_tmp, total);
+    if (threadIdx.x == 0) s_pos0 = pos;
+    __syncthreads();
+    const bool fits = k >= N || (ok && pos == s_pos0 + rel);
+    if (__syncthreads_and(fits)) {
+      if (ok) {
+        for (uint32_t j = 0; j < L; ++j) {
+          const uint32_t b = sh + j;
+          s_txt[rel + j] = (uint8_t)(wv[b >> 2] >> (8 * (b & 3)));
+        }
+        if (s) s_txt[rel + L] = (uint8_t)sep;
+      }
+      __syncthreads();
+      lds_bytes_to_global<NT>(s_txt, total, out + s_pos0);
+    } else if (ok) {
+      for (uint32_t j = 0; j < L; ++j) {
+        const uint32_t b = sh + j;
+        out[pos + j] = (uint8_t)(wv[b >> 2] >> (8 * (b & 3)));
+      }
+      if (s) out[pos + L] = (uint8_t)sep;
     }
-    for (uint32_t j = 0; j < L; ++j) out[pos + j] = chars[a + j];
-    if (s) out[pos + L] = (uint8_t)sep;
+    __syncthreads();
   }
 }
 
