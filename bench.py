@@ -459,6 +459,31 @@ def main():
         log("plain: %.3f ms/step, %.1f Mwords/s, same=%s" % (pms, plain["value"], same))
         del perm2
 
+    # ---- baseline without length lists (one key per word, length first; single document)
+    unb = None
+    if docs is None and not args.no_plain:
+        perm3 = torch.empty_like(perm)
+        boff3 = torch.empty(34, dtype=torch.int32, device=dev)
+        try:
+            sw.sort_words_unbucketed(chars, offs, n, perm3, boff3, ws, stream)
+            sw.sort_words_status(ws, stream)
+            ev0.record(stream)
+            for _ in range(args.plain_steps):
+                sw.sort_words_unbucketed(chars, offs, n, perm3, boff3, ws, stream)
+            ev1.record(stream)
+            torch.cuda.synchronize()
+            sw.sort_words_status(ws, stream)
+            ums = ev0.elapsed_time(ev1) / args.plain_steps
+            same = bool(torch.equal(perm3, perm))
+            unb = {"value": n / (ums / 1e3) / 1e6, "unit": "Mwords/s", "ms_per_step": ums,
+                   "same_result_as_batched": same,
+                   "form": "sort_words_unbucketed: one 32-byte key per word (length first), the whole "
+                           "list chunk-sorted and merged as one sequence"}
+            log("unbucketed: %.3f ms/step, %.1f Mwords/s, same=%s" % (ums, unb["value"], same))
+        except sw.SortWordsError as e:
+            unb = {"error": str(e)}
+        del perm3, boff3
+
     # ---- the same pass launched eagerly (no graph), classes forked onto side streams
     def eager():
         if docs is None:
@@ -532,6 +557,8 @@ def main():
         "eager_ms_per_step": eager_ms,
         "per_bucket_launch": plain,
         "batched_over_plain": (value / plain["value"]) if plain else None,
+        "unbucketed": unb,
+        "batched_over_unbucketed": (value / unb["value"]) if unb and "value" in unb else None,
         "check": check,
         "roofline": roof,
         "around_the_sort": text,

@@ -116,6 +116,16 @@ int sort_words_plain(const uint8_t *chars, const uint32_t *offsets,
                      uint32_t *out_perm, uint32_t *out_bucket_offsets,
                      void *workspace, size_t workspace_bytes, void *stream);
 
+/* Baseline without length lists (the whole-file sorts of Table 2): every word
+ * becomes one 32-byte key (its length in the top byte, then its bytes) and
+ * the whole list is chunk-sorted and merged as one sequence.  The order is the
+ * same total order, so the result equals sort_words'.  Words of at most 31
+ * bytes (a 32-byte word is SW_ERR_WORD_TOO_LONG here).  Arguments as
+ * sort_words_ex; asynchronous, device errors via sort_words_status(). */
+int sort_words_unbucketed(const uint8_t *chars, const uint32_t *offsets, uint32_t n,
+                          uint32_t *out_perm, uint32_t *out_bucket_offsets,
+                          void *workspace, size_t workspace_bytes, void *stream);
+
 /* Waits for `stream`, then returns the status the device recorded in
  * `workspace` for the last call enqueued with it (SW_OK or an error). */
 int sort_words_status(const void *workspace, void *stream);

@@ -62,6 +62,7 @@ def lib() -> ctypes.CDLL:
         "sort_words_ex": ([vp, vp, u32, vp, vp, vp, sz, vp], i32),
         "sort_words_batch": ([vp, vp, vp, u32, vp, vp, vp, sz, vp], i32),
         "sort_words_plain": ([vp, vp, vp, u32, vp, vp, vp, sz, vp], i32),
+        "sort_words_unbucketed": ([vp, vp, u32, vp, vp, vp, sz, vp], i32),
         "sort_words_status": ([vp, vp], i32),
         "sw_plan_create": ([u32, u32, vp, ctypes.POINTER(vp)], i32),
         "sw_plan_run": ([vp, vp, vp, vp, u32, u32, vp, vp], i32),
@@ -93,7 +94,7 @@ def lib() -> ctypes.CDLL:
 
 
 EXPORTED = ("sort_words", "sort_words_workspace_size", "sort_words_ex", "sort_words_batch",
-            "sort_words_plain", "sort_words_status", "sort_words_status_async",
+            "sort_words_plain", "sort_words_unbucketed", "sort_words_status", "sort_words_status_async",
             "sort_words_decode_status", "sw_plan_create", "sw_plan_run",
             "sw_plan_status", "sw_plan_status_async", "sw_plan_destroy", "sw_get_config", "sw_set_config",
             "sw_num_variants", "sw_variant_tiles", "sw_profile_enable", "sw_profile_reset",
@@ -154,6 +155,13 @@ def sort_words_plain(chars, offsets, doc_offsets, n_docs, out_perm, out_bucket_o
                                          _ptr(out_perm), _ptr(out_bucket_offsets), _ptr(workspace),
                                          workspace.numel() * workspace.element_size(),
                                          _stream(stream)))
+
+
+def sort_words_unbucketed(chars, offsets, n, out_perm, out_bucket_offsets, workspace, stream=None) -> int:
+    """The baseline without length lists (asynchronous; errors via sort_words_status)."""
+    return _check(lib().sort_words_unbucketed(_ptr(chars), _ptr(offsets), int(n), _ptr(out_perm),
+                                              _ptr(out_bucket_offsets), _ptr(workspace),
+                                              workspace.numel() * workspace.element_size(), _stream(stream)))
 
 
 def sort_words_status(workspace, stream=None) -> int:

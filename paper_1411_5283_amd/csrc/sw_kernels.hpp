@@ -561,6 +561,44 @@ __global__ __launch_bounds__(NT) void k_scatter_pack(Ws w) {
   }
 }
 
+// ---------------------------------------------------------------- k_pack_full
+// Baseline without length lists: every word of the (single) document becomes
+// one 32-byte key, its length in the top byte followed by up to 31 of its
+// bytes, written at its input position; the whole list is then sorted as one
+// segment.  Comparing such keys (then the index) is the same total order as
+// the bucketed sort's, so the result is identical.  A word longer than 31
+// bytes does not fit the key and is reported as too long.
+template <int NT>
+__global__ __launch_bounds__(NT) void k_pack_full(Ws w) {
+  Header* h = w.h;
+  if (h->abort) return;
+  const uint32_t N = h->n_words;
+  const uint32_t* off = h->d.offsets;
+  const uint8_t* chars = h->d.chars;
+  uint32_t bad = 0;
+  for (uint32_t i = blockIdx.x * NT + threadIdx.x; i < N; i += gridDim.x * NT) {
+    const uint32_t a = off[i], L = off[i + 1] - a;
+    if (L > (uint32_t)kMaxLen - 1) {
+      bad = 1;
+      continue;
+    }
+    uint64_t ln[4];
+    load_be_lanes<4>(chars + a, L, ln);
+    const uint64_t top = (uint64_t)L << 56;
+    w.a.k[3][i] = (ln[2] << 56) | (ln[3] >> 8);
+    w.a.k[2][i] = (ln[1] << 56) | (ln[2] >> 8);
+    w.a.k[1][i] = (ln[0] << 56) | (ln[1] >> 8);
+    w.a.k[0][i] = top | (ln[0] >> 8);
+    w.a.idx[i] = i;
+  }
+  if (__any(bad)) {
+    if (__lane_id() == 0) {
+      atomicOr(&h->status, ST_TOO_LONG);
+      atomicOr(&h->abort, 1u);
+    }
+  }
+}
+
 // ---------------------------------------------------------------- chunk sort
 // Odd-even transposition (the parallel form of bubble sort's adjacent
 // compare-exchanges, section 2) on chunks of C consecutive items.  Thread t of

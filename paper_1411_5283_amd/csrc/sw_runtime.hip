@@ -659,6 +659,48 @@ int sort_words_plain(const uint8_t* chars, const uint32_t* offsets, const uint32
   return read_status(workspace, s);
 }
 
+int sort_words_unbucketed(const uint8_t* chars, const uint32_t* offsets, uint32_t n, uint32_t* out_perm,
+                          uint32_t* out_bucket_offsets, void* workspace, size_t workspace_bytes, void* stream) {
+  if (!offsets || !out_bucket_offsets || !workspace || (n && !out_perm))
+    return fail(SW_ERR_INVALID_ARG, "sort_words_unbucketed: null pointer argument");
+  Layout L;
+  if (!make_layout(capacity_for(workspace_bytes, 1), 1, L) || L.total > workspace_bytes || n > L.Nmax)
+    return fail(SW_ERR_WORKSPACE, "sort_words_unbucketed: workspace too small for %u words", n);
+  hipStream_t s = (hipStream_t)stream;
+  const sw_config cfg = current_config();
+  const Ws w = make_ws(workspace, L, cfg);
+  Grids g;
+  int rc = make_grids(w, cfg, g);
+  if (rc) return rc;
+  DevInfo* di;
+  if ((rc = device_info(&di))) return rc;
+  RunDesc d{chars, offsets, nullptr, out_perm, out_bucket_offsets, n, 1};
+  if ((rc = enqueue_begin(w, d, s))) return rc;
+  // the pre-pass of the bucketed sort: validation, length counts, bucket offsets
+  sw::k_doc_plan<1024><<<1, 1024, 0, s>>>(w);
+  sw::k_hist<kNT><<<g.words, kNT, 0, s>>>(w);
+  sw::k_scan_rows<1024, 4><<<sw::kNB, 1024, 0, s>>>(w, w.cnt, sw::kNB, w.Bmax + 1, 0);
+  sw::k_segments<kNT><<<g.docs, kNT, 0, s>>>(w);
+  if (n) {
+    const unsigned pgrid = (unsigned)std::min<uint64_t>((n + kNT - 1) / kNT, (uint64_t)di->cus * 8);
+    sw::k_pack_full<kNT><<<pgrid, kNT, 0, s>>>(w);
+    // one segment of n four-lane keys: chunk sort, then every merge level
+    constexpr int c = sw::kNClass - 1;
+    const Variant& v = *g.var[c];
+    const uint32_t m = sw::levels_for(n, v.T);
+    const TileWork tw{1, 0, n, m};
+    v.sort(w, c, tw, (n + v.T - 1) / v.T, s);
+    const uint32_t mtiles = (n + v.P - 1) / v.P;
+    const uint32_t tiles_per_wg = (kPartNT / 64) * (64 / sw::kPartLanes);
+    for (uint32_t l = 0; l < m; ++l) {
+      v.partition(w, c, (int)l, tw, (mtiles + tiles_per_wg - 1) / tiles_per_wg, s);
+      v.merge(w, c, (int)l, tw, std::min<uint32_t>(mtiles, (uint32_t)(di->cus * di->occ_merge[c][cfg.variant[c]])), s);
+    }
+  }
+  HIP_TRY(hipGetLastError());
+  return SW_OK;
+}
+
 // ------------------------------------------------------------------ plans
 struct sw_plan {
   void* ws = nullptr;

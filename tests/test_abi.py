@@ -79,3 +79,11 @@ def test_text_entry_points_validate_on_host():
     assert L.sort_words_materialize(1, 1, None, 1, 5, 1, 1, 256, 1, 1, None) == sw.ERR_INVALID_ARG
     assert L.sort_words_materialize(1, 1, None, 2, 5, 1, 1, 10, 1, 1, None) == sw.ERR_INVALID_ARG
     assert L.sort_words_materialize(1, 1, 1, 0, 5, 1, 1, 10, 1, 1, None) == sw.ERR_INVALID_ARG
+
+
+def test_unbucketed_validates_on_host():
+    import paper_1411_5283_amd as sw
+    L = sw.lib()
+    assert L.sort_words_unbucketed(None, None, 0, None, None, None, 0, None) == sw.ERR_INVALID_ARG
+    assert L.sort_words_unbucketed(1, 1, 5, None, 1, 1, 1 << 20, None) == sw.ERR_INVALID_ARG
+    assert L.sort_words_unbucketed(1, 1, 5, 1, 1, 1, 16, None) == sw.ERR_WORKSPACE
