@@ -185,55 +185,21 @@ def hbm_traffic(dominant_kernel: str):
 
 # ------------------------------------------------------------------ serving
 def serve_bench(args, sw, wordgen, torch):
-    """Continuous batching under Poisson arrivals (see paper_1411_5283_amd/serve.py)."""
-    from paper_1411_5283_amd.serve import GpuExecutor, SortServer
+    """Continuous batching under Poisson arrivals: the library's native serving
+    loop (sw_server_*), or with --serve-python the Python scheduler of
+    paper_1411_5283_amd/serve.py."""
     n_warm, n_meas = args.serve_warmup, args.serve_requests
     log("generating %d requests" % (n_warm + n_meas))
     reqs = list(wordgen.serving_requests(n_warm + n_meas))
     warm, meas = reqs[:n_warm], reqs[n_warm:]
-    ex = GpuExecutor(slots=args.serve_slots, max_batch_words=args.serve_batch_words,
-                     max_batch_docs=args.serve_batch_docs, max_batch_chars=args.serve_batch_words * 8)
-    budget = (8 << 30) - ex.fixed_bytes()
-
-    def run(rset, rate):
-        srv = SortServer(ex, budget_bytes=budget, max_batch_words=args.serve_batch_words,
-                         max_batch_docs=args.serve_batch_docs, min_batch_words=args.serve_min_words,
-                         max_wait_s=args.serve_max_wait_ms * 1e-3)
-        srv.start()
-        rng = np.random.default_rng(1)
-        t0 = time.perf_counter()
-        futs = []
-        if rate is None:                      # closed burst: everything arrives at once
-            futs = [srv.submit(r.chars, r.offsets) for r in rset]
-        else:
-            t = t0
-            for r in rset:
-                t += rng.exponential(1.0 / rate)
-                wait = t - time.perf_counter()
-                if wait > 0:
-                    time.sleep(wait)          # sleeping releases the interpreter to the server thread
-                futs.append(srv.submit(r.chars, r.offsets))
-        for f in futs:
-            f.result(timeout=300)
-        t1 = time.perf_counter()
-        srv.stop()
-        words = sum(r.n for r in rset)
-        return {"requests": len(rset), "words": words, "seconds": t1 - t0,
-                "mwords_s": words / (t1 - t0) / 1e6, "p50_ms": srv.stats.percentile(50) * 1e3,
-                "p99_ms": srv.stats.percentile(99) * 1e3, "batches": srv.stats.batches,
-                "max_bytes_in_use": srv.stats.max_bytes_in_use}
-
-    sat = run(warm, None)
-    log("saturation (closed burst): %s" % sat)
-    sat_rate = sat["requests"] / sat["seconds"]
-    points = []
-    for frac in (0.5, 0.8, 1.0):
-        r = run(meas, frac * sat_rate)
-        r["lambda_req_s"] = frac * sat_rate
-        r["lambda_frac"] = frac
-        points.append(r)
-        log("lambda %.1f x saturation: %s" % (frac, r))
-    ex.close()
+    if args.serve_python:
+        out, ex = serve_python(args, sw, reqs, warm, meas)
+        loop = "python scheduler (serve.py) over graph-captured plans"
+    else:
+        out, ex = serve_native(args, sw, reqs, warm, meas)
+        loop = "native serving loop (sw_server_*: C++ scheduler thread, pinned staging, %d copy threads)" % \
+            args.serve_copy_threads
+    sat, points, budget = out
     main_pt = points[1]
     cpu = None
     if not args.no_cpu_baseline:
@@ -260,13 +226,95 @@ def serve_bench(args, sw, wordgen, torch):
                    "request_mean": float(sizes.mean()), "slots": args.serve_slots,
                    "max_batch_words": args.serve_batch_words, "budget_bytes": budget,
                    "min_batch_words": args.serve_min_words, "max_wait_ms": args.serve_max_wait_ms,
-                   "value_at": "lambda = 0.8 x closed-burst saturation rate"},
+                   "loop": loop, "value_at": "lambda = 0.8 x closed-burst saturation rate"},
         "serving": {"saturation": sat, "points": points},
         "roofline": None, "cpu_baseline": cpu, "kernel_source": kernel_source_hash(),
     }
 
 
-# ------------------------------------------------------------------ main
+def _arrivals(rset, rate, submit):
+    """Submit every request at Poisson times (rate None: all at once); returns the start time."""
+    rng = np.random.default_rng(1)
+    t0 = time.perf_counter()
+    if rate is None:
+        return t0, [submit(r) for r in rset]
+    t = t0
+    out = []
+    for r in rset:
+        t += rng.exponential(1.0 / rate)
+        wait = t - time.perf_counter()
+        if wait > 0:
+            time.sleep(wait)
+        out.append(submit(r))
+    return t0, out
+
+
+def _serve_points(run, warm, meas):
+    sat = run(warm, None)
+    log("saturation (closed burst): %s" % sat)
+    sat_rate = sat["requests"] / sat["seconds"]
+    points = []
+    for frac in (0.5, 0.8, 1.0):
+        r = run(meas, frac * sat_rate)
+        r["lambda_req_s"] = frac * sat_rate
+        r["lambda_frac"] = frac
+        points.append(r)
+        log("lambda %.1f x saturation: %s" % (frac, r))
+    return sat, points
+
+
+def serve_native(args, sw, reqs, warm, meas):
+    cfg = dict(slots=args.serve_slots, max_batch_words=args.serve_batch_words,
+               max_batch_docs=args.serve_batch_docs, max_batch_chars=args.serve_batch_words * 8,
+               min_batch_words=args.serve_min_words, max_wait_us=int(args.serve_max_wait_ms * 1e3),
+               copy_threads=args.serve_copy_threads)
+    probe = sw.NativeServer(budget_bytes=1 << 30, **cfg)
+    budget = (8 << 30) - probe.fixed_bytes()
+    probe.close()
+
+    def run(rset, rate):
+        srv = sw.NativeServer(budget_bytes=budget, **cfg)
+        t0, tickets = _arrivals(rset, rate, lambda r: srv.submit(r.chars, r.offsets))
+        lats = [srv.wait(t)[2] for t in tickets]
+        t1 = time.perf_counter()
+        st = srv.stats()
+        srv.close()
+        words = sum(r.n for r in rset)
+        return {"requests": len(rset), "words": words, "seconds": t1 - t0,
+                "mwords_s": words / (t1 - t0) / 1e6, "p50_ms": float(np.percentile(lats, 50)) * 1e3,
+                "p99_ms": float(np.percentile(lats, 99)) * 1e3, "batches": st["batches"],
+                "max_bytes_in_use": st["max_bytes_in_use"]}
+
+    return (*_serve_points(run, warm, meas), budget), None
+
+
+def serve_python(args, sw, reqs, warm, meas):
+    from paper_1411_5283_amd.serve import GpuExecutor, SortServer
+    ex = GpuExecutor(slots=args.serve_slots, max_batch_words=args.serve_batch_words,
+                     max_batch_docs=args.serve_batch_docs, max_batch_chars=args.serve_batch_words * 8)
+    budget = (8 << 30) - ex.fixed_bytes()
+
+    def run(rset, rate):
+        srv = SortServer(ex, budget_bytes=budget, max_batch_words=args.serve_batch_words,
+                         max_batch_docs=args.serve_batch_docs, min_batch_words=args.serve_min_words,
+                         max_wait_s=args.serve_max_wait_ms * 1e-3)
+        srv.start()
+        t0, futs = _arrivals(rset, rate, lambda r: srv.submit(r.chars, r.offsets))
+        for f in futs:
+            f.result(timeout=300)
+        t1 = time.perf_counter()
+        srv.stop()
+        words = sum(r.n for r in rset)
+        return {"requests": len(rset), "words": words, "seconds": t1 - t0,
+                "mwords_s": words / (t1 - t0) / 1e6, "p50_ms": srv.stats.percentile(50) * 1e3,
+                "p99_ms": srv.stats.percentile(99) * 1e3, "batches": srv.stats.batches,
+                "max_bytes_in_use": srv.stats.max_bytes_in_use}
+
+    out = (*_serve_points(run, warm, meas), budget)
+    ex.close()
+    return out, None
+
+
 def text_bench(args, sw, wordgen, torch, wl, chars, offs, docs, perm, boff, perm_h, boff_h, stream):
     """The steps around the sort on the same workload: the word list written as
     raw text (capitals, punctuation, line breaks) is tokenized back on the GPU
@@ -348,6 +396,7 @@ def text_bench(args, sw, wordgen, torch, wl, chars, offs, docs, perm, boff, perm
     }
 
 
+# ------------------------------------------------------------------ main
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -371,6 +420,8 @@ def main():
     ap.add_argument("--serve-batch-docs", type=int, default=256)
     ap.add_argument("--serve-min-words", type=int, default=1 << 20)
     ap.add_argument("--serve-max-wait-ms", type=float, default=1.0)
+    ap.add_argument("--serve-copy-threads", type=int, default=4)
+    ap.add_argument("--serve-python", action="store_true", help="the Python scheduler instead of the native loop")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py: this build runs on one GPU only; --gpus %d is not supported "

@@ -233,6 +233,51 @@ int sort_words_materialize(const uint8_t *chars, const uint32_t *offsets,
                            const uint32_t *perm, const uint32_t *bucket_offsets, int sep,
                            uint8_t *out_text, uint32_t *out_status, void *stream);
 
+/* ------------------------------------------------------------ serving
+ * Continuous batching of sort requests (not in the paper; the serving form of
+ * the batched sort).  A host thread admits requests in arrival order while
+ * the device bytes of all admitted requests (characters, offsets,
+ * permutation, bucket offsets) stay within budget_bytes, packs every admitted
+ * request that is not running into one batch (up to the batch limits), and
+ * runs it as one sw_plan_run on a free slot (each slot: its own stream, plan
+ * and pinned staging), so batches on different slots overlap on the device.
+ * While a batch runs, the next one starts once it holds min_batch_words
+ * words or max_batch_docs requests, or its oldest request has waited
+ * max_wait_us.  copy_threads extra host threads help pack requests and copy
+ * results out.  Device memory taken by the server itself (plans and staging)
+ * is sw_server_fixed_bytes(cfg), outside the budget. */
+typedef struct sw_server sw_server;
+typedef struct {
+    uint32_t slots;             /* 1..8 concurrent batches */
+    uint32_t max_batch_words;
+    uint32_t max_batch_docs;
+    uint32_t copy_threads;      /* 0..64 */
+    uint64_t max_batch_chars;   /* < 2^32 */
+    uint64_t budget_bytes;
+    uint32_t min_batch_words;
+    uint32_t max_wait_us;
+} sw_server_config;
+typedef struct {
+    uint64_t completed, failed, words, batches, bytes_in_use, max_bytes_in_use;
+} sw_server_counts;
+int sw_server_create(const sw_server_config *cfg, sw_server **out);
+/* One request (one document), HOST pointers: chars/offsets (n_words+1
+ * entries, any first offset) must stay valid, and out_perm (n_words) /
+ * out_bucket_offsets (SW_NUM_OFFSETS) untouched, until sw_server_wait
+ * returns for its ticket.  A malformed request (SW_ERR_INVALID_ARG,
+ * SW_ERR_WORD_TOO_LONG) or one that can never fit the budget or a batch
+ * (SW_ERR_WORKSPACE) is refused here, alone, and gets no ticket. */
+int sw_server_submit(sw_server *srv, const uint8_t *chars, const uint32_t *offsets, uint32_t n_words,
+                     uint32_t *out_perm, uint32_t *out_bucket_offsets, uint64_t *out_ticket);
+/* Blocks until the request completes; returns its status (a batch that failed
+ * on the device fails all its requests) and its latency from submission to
+ * the completion seen by the server thread.  A ticket is waited for once. */
+int sw_server_wait(sw_server *srv, uint64_t ticket, double *latency_s);
+int sw_server_stats(sw_server *srv, sw_server_counts *out);
+size_t sw_server_fixed_bytes(const sw_server_config *cfg);
+/* Finishes every submitted request, then frees the server. */
+void sw_server_destroy(sw_server *srv);
+
 const char *sort_words_last_error(void);
 const char *sort_words_version(void);
 

@@ -43,6 +43,18 @@ class sw_config(ctypes.Structure):
                 ("flags", ctypes.c_uint32)]
 
 
+class sw_server_config(ctypes.Structure):
+    _fields_ = [("slots", ctypes.c_uint32), ("max_batch_words", ctypes.c_uint32),
+                ("max_batch_docs", ctypes.c_uint32), ("copy_threads", ctypes.c_uint32),
+                ("max_batch_chars", ctypes.c_uint64), ("budget_bytes", ctypes.c_uint64),
+                ("min_batch_words", ctypes.c_uint32), ("max_wait_us", ctypes.c_uint32)]
+
+
+class sw_server_counts(ctypes.Structure):
+    _fields_ = [(k, ctypes.c_uint64) for k in ("completed", "failed", "words", "batches", "bytes_in_use",
+                                               "max_bytes_in_use")]
+
+
 _lib = None
 
 
@@ -82,6 +94,12 @@ def lib() -> ctypes.CDLL:
         "sort_words_tokenize_workspace_size": ([ctypes.c_uint64], sz),
         "sort_words_tokenize": ([vp, ctypes.c_uint64, u32, vp, vp, u32, vp, vp, sz, vp], i32),
         "sort_words_materialize": ([vp, vp, vp, u32, u32, vp, vp, i32, vp, vp, vp], i32),
+        "sw_server_create": ([ctypes.POINTER(sw_server_config), ctypes.POINTER(vp)], i32),
+        "sw_server_submit": ([vp, vp, vp, u32, vp, vp, ctypes.POINTER(ctypes.c_uint64)], i32),
+        "sw_server_wait": ([vp, ctypes.c_uint64, ctypes.POINTER(ctypes.c_double)], i32),
+        "sw_server_stats": ([vp, ctypes.POINTER(sw_server_counts)], i32),
+        "sw_server_fixed_bytes": ([ctypes.POINTER(sw_server_config)], sz),
+        "sw_server_destroy": ([vp], None),
         "sort_words_last_error": ([], ctypes.c_char_p),
         "sort_words_version": ([], ctypes.c_char_p),
     }
@@ -99,7 +117,9 @@ EXPORTED = ("sort_words", "sort_words_workspace_size", "sort_words_ex", "sort_wo
             "sw_plan_status", "sw_plan_status_async", "sw_plan_destroy", "sw_get_config", "sw_set_config",
             "sw_num_variants", "sw_variant_tiles", "sw_profile_enable", "sw_profile_reset",
             "sw_profile_read", "sort_words_tokenize_workspace_size", "sort_words_tokenize",
-            "sort_words_materialize", "sort_words_last_error", "sort_words_version")
+            "sort_words_materialize", "sw_server_create", "sw_server_submit", "sw_server_wait",
+            "sw_server_stats", "sw_server_fixed_bytes", "sw_server_destroy", "sort_words_last_error",
+            "sort_words_version")
 
 
 def _check(rc: int) -> int:
@@ -297,6 +317,68 @@ def text_size(wl, sep: int) -> int:
     """Bytes of the sorted text of a word list (one separator per word when sep >= 0)."""
     n = wl.n
     return int(wl.offsets[n]) - int(wl.offsets[0]) + (n if sep >= 0 else 0) if n else 0
+
+
+# ------------------------------------------------------------------ serving (native loop)
+class NativeServer:
+    """The library's serving loop (sw_server_*): requests are host arrays;
+    results come back as host arrays.  A request's arrays are kept alive here
+    until it has been waited for."""
+
+    def __init__(self, slots: int = 2, max_batch_words: int = 1 << 22, max_batch_docs: int = 256,
+                 max_batch_chars: int | None = None, budget_bytes: int = 8 << 30, min_batch_words: int = 0,
+                 max_wait_us: int = 0, copy_threads: int = 4):
+        self.cfg = sw_server_config(int(slots), int(max_batch_words), int(max_batch_docs), int(copy_threads),
+                                    int(max_batch_chars or max_batch_words * 8), int(budget_bytes),
+                                    int(min_batch_words), int(max_wait_us))
+        h = ctypes.c_void_p()
+        _check(lib().sw_server_create(ctypes.byref(self.cfg), ctypes.byref(h)))
+        self._h = h
+        self._live = {}
+
+    def fixed_bytes(self) -> int:
+        return int(lib().sw_server_fixed_bytes(ctypes.byref(self.cfg)))
+
+    def submit(self, chars, offsets) -> int:
+        """Queue one request; returns its ticket (raises at once if it is refused)."""
+        chars = np.ascontiguousarray(chars, dtype=np.uint8)
+        offsets = np.ascontiguousarray(offsets, dtype=np.uint32)
+        n = offsets.shape[0] - 1
+        if n < 0:
+            raise SortWordsError(ERR_INVALID_ARG, "offsets must hold n+1 entries")
+        perm = np.empty(max(n, 1), np.uint32)
+        boff = np.empty(NUM_OFFSETS, np.uint32)
+        t = ctypes.c_uint64()
+        cp = chars.ctypes.data if chars.size else None
+        _check(lib().sw_server_submit(self._h, cp, offsets.ctypes.data, n, perm.ctypes.data,
+                                      boff.ctypes.data, ctypes.byref(t)))
+        self._live[t.value] = (chars, offsets, perm, boff, n)
+        return t.value
+
+    def wait(self, ticket: int):
+        """(perm, bucket_offsets, latency_s) of a request; raises if its batch failed."""
+        lat = ctypes.c_double()
+        rc = lib().sw_server_wait(self._h, int(ticket), ctypes.byref(lat))
+        chars, offsets, perm, boff, n = self._live.pop(int(ticket))
+        _check(rc)
+        return perm[:n], boff, float(lat.value)
+
+    def stats(self) -> dict:
+        c = sw_server_counts()
+        _check(lib().sw_server_stats(self._h, ctypes.byref(c)))
+        return {k: int(getattr(c, k)) for k, _ in c._fields_}
+
+    def close(self):
+        if self._h:
+            lib().sw_server_destroy(self._h)
+            self._h = None
+            self._live.clear()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 # ------------------------------------------------------------------ host helpers

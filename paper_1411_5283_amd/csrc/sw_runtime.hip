@@ -4,16 +4,23 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
+#include <chrono>
+#include <condition_variable>
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <functional>
 #include <mutex>
 #include <string>
+#include <thread>
+#include <unordered_map>
 #include <vector>
 
 #include "sort_words.h"
 #include "sw_kernels.hpp"
 #include "sw_text.hpp"
+#include "sw_sched.hpp"
 
 namespace {
 
@@ -949,6 +956,380 @@ int sort_words_materialize(const uint8_t* chars, const uint32_t* offsets, const 
   }
   HIP_TRY(hipGetLastError());
   return SW_OK;
+}
+
+}  // extern "C"
+
+// ------------------------------------------------------------------ serving
+// The serving loop (continuous batching): the scheduling rules are in
+// sw_sched.hpp; here are the GPU executor (one stream, one graph-captured
+// plan and pinned staging per slot), the host threads that pack requests
+// into staging and copy results out, and the scheduler thread.
+namespace {
+
+// A few host threads for the copies of a batch; the calling thread takes the
+// first part.
+class CopyPool {
+ public:
+  explicit CopyPool(unsigned n) {
+    for (unsigned i = 0; i < n; ++i) th_.emplace_back([this] { loop(); });
+  }
+  ~CopyPool() {
+    {
+      std::lock_guard<std::mutex> lk(mu_);
+      stop_ = true;
+    }
+    cv_.notify_all();
+    for (auto& t : th_) t.join();
+  }
+  unsigned threads() const { return (unsigned)th_.size() + 1; }
+  // fn(part) for part = 0..parts-1, spread over the pool and the caller
+  void run(unsigned parts, const std::function<void(unsigned)>& fn) {
+    if (parts <= 1 || th_.empty()) {
+      for (unsigned i = 0; i < parts; ++i) fn(i);
+      return;
+    }
+    {
+      std::lock_guard<std::mutex> lk(mu_);
+      fn_ = &fn;
+      next_ = 1;
+      parts_ = parts;
+      left_ = parts - 1;
+      ++gen_;
+    }
+    cv_.notify_all();
+    fn(0);
+    std::unique_lock<std::mutex> lk(mu_);
+    done_cv_.wait(lk, [this] { return left_ == 0; });
+    fn_ = nullptr;
+  }
+
+ private:
+  void loop() {
+    uint64_t seen = 0;
+    std::unique_lock<std::mutex> lk(mu_);
+    for (;;) {
+      cv_.wait(lk, [&] { return stop_ || (gen_ != seen && next_ < parts_); });
+      if (stop_) return;
+      seen = gen_;
+      while (next_ < parts_) {
+        const unsigned part = next_++;
+        const std::function<void(unsigned)>* f = fn_;
+        lk.unlock();
+        (*f)(part);
+        lk.lock();
+        if (--left_ == 0) done_cv_.notify_all();
+      }
+    }
+  }
+  std::vector<std::thread> th_;
+  std::mutex mu_;
+  std::condition_variable cv_, done_cv_;
+  const std::function<void(unsigned)>* fn_ = nullptr;
+  unsigned next_ = 0, parts_ = 0, left_ = 0;
+  uint64_t gen_ = 0;
+  bool stop_ = false;
+};
+
+struct SrvSlot {
+  hipStream_t s = nullptr;
+  sw_plan* plan = nullptr;
+  uint8_t* d_chars = nullptr;
+  uint32_t *d_offsets = nullptr, *d_docs = nullptr, *d_perm = nullptr, *d_boff = nullptr;
+  uint8_t* h_chars = nullptr;
+  uint32_t *h_offsets = nullptr, *h_docs = nullptr, *h_perm = nullptr, *h_boff = nullptr, *h_status = nullptr;
+  hipEvent_t ev = nullptr;
+  std::vector<uint64_t> wpos, cpos;   // per request: first word and first char in the batch
+};
+
+class HipExec {
+ public:
+  uint64_t max_words = 0, max_docs = 0, max_chars = 0;
+  std::vector<SrvSlot> slot;
+  CopyPool* pool = nullptr;
+
+  uint32_t slots() const { return (uint32_t)slot.size(); }
+  bool capacity(uint64_t words, uint64_t docs, uint64_t chars) const {
+    return words <= max_words && docs <= max_docs && chars <= max_chars;
+  }
+
+  // On an error the slot's stream is drained first, so the slot's staging is
+  // free again when the batch is closed.
+  int launch(swsrv::Batch& b) {
+    const int rc = enqueue(b);
+    if (rc) (void)hipStreamSynchronize(slot[(size_t)b.slot].s);
+    return rc;
+  }
+
+  int enqueue(swsrv::Batch& b) {
+    SrvSlot& sl = slot[(size_t)b.slot];
+    const size_t nr = b.reqs.size();
+    sl.wpos.resize(nr + 1);
+    sl.cpos.resize(nr + 1);
+    sl.wpos[0] = sl.cpos[0] = 0;
+    for (size_t i = 0; i < nr; ++i) {
+      sl.wpos[i + 1] = sl.wpos[i] + b.reqs[i]->n;
+      sl.cpos[i + 1] = sl.cpos[i] + b.reqs[i]->nchars;
+    }
+    const uint64_t W = sl.wpos[nr], C = sl.cpos[nr];
+    // pack: characters back to back, offsets rebased onto the batch, document starts
+    sl.h_offsets[0] = 0;
+    sl.h_docs[0] = 0;
+    const unsigned parts = std::min<unsigned>(pool->threads(), (unsigned)nr);
+    auto pack = [&](unsigned part) {
+      const size_t lo = nr * part / parts, hi = nr * (part + 1) / parts;
+      for (size_t i = lo; i < hi; ++i) {
+        const swsrv::Request* r = b.reqs[i];
+        const uint32_t o0 = r->offsets[0];
+        if (r->nchars) memcpy(sl.h_chars + sl.cpos[i], r->chars + o0, r->nchars);
+        uint32_t* dst = sl.h_offsets + sl.wpos[i] + 1;
+        const uint32_t base = (uint32_t)sl.cpos[i];
+        for (uint32_t k = 0; k < r->n; ++k) dst[k] = r->offsets[k + 1] - o0 + base;
+        sl.h_docs[i + 1] = (uint32_t)sl.wpos[i + 1];
+      }
+    };
+    pool->run(parts, pack);
+    HIP_TRY(hipMemcpyAsync(sl.d_chars, sl.h_chars, std::max<uint64_t>(C, 1), hipMemcpyHostToDevice, sl.s));
+    HIP_TRY(hipMemcpyAsync(sl.d_offsets, sl.h_offsets, 4 * (W + 1), hipMemcpyHostToDevice, sl.s));
+    HIP_TRY(hipMemcpyAsync(sl.d_docs, sl.h_docs, 4 * (nr + 1), hipMemcpyHostToDevice, sl.s));
+    int rc = sw_plan_run(sl.plan, sl.d_chars, sl.d_offsets, sl.d_docs, (uint32_t)nr, (uint32_t)W, sl.d_perm,
+                         sl.d_boff);
+    if (rc) return rc;
+    if (W) HIP_TRY(hipMemcpyAsync(sl.h_perm, sl.d_perm, 4 * W, hipMemcpyDeviceToHost, sl.s));
+    HIP_TRY(hipMemcpyAsync(sl.h_boff, sl.d_boff, 4 * nr * SW_NUM_OFFSETS, hipMemcpyDeviceToHost, sl.s));
+    if ((rc = sw_plan_status_async(sl.plan, sl.h_status))) return rc;
+    HIP_TRY(hipEventRecord(sl.ev, sl.s));
+    return SW_OK;
+  }
+
+  bool poll(const swsrv::Batch& b) { return hipEventQuery(slot[(size_t)b.slot].ev) != hipErrorNotReady; }
+
+  int finish(swsrv::Batch& b) {
+    SrvSlot& sl = slot[(size_t)b.slot];
+    HIP_TRY(hipEventSynchronize(sl.ev));
+    const int st = sort_words_decode_status(*sl.h_status);
+    if (st) return st;
+    const size_t nr = b.reqs.size();
+    const unsigned parts = std::min<unsigned>(pool->threads(), (unsigned)nr);
+    auto out = [&](unsigned part) {
+      const size_t lo = nr * part / parts, hi = nr * (part + 1) / parts;
+      for (size_t i = lo; i < hi; ++i) {
+        swsrv::Request* r = b.reqs[i];
+        if (r->n) memcpy(r->out_perm, sl.h_perm + sl.wpos[i], 4 * (size_t)r->n);
+        memcpy(r->out_boff, sl.h_boff + i * SW_NUM_OFFSETS, 4 * SW_NUM_OFFSETS);
+      }
+    };
+    pool->run(parts, out);
+    return SW_OK;
+  }
+};
+
+double srv_now() {
+  using namespace std::chrono;
+  return duration<double>(steady_clock::now().time_since_epoch()).count();
+}
+
+}  // namespace
+
+struct sw_server {
+  int device = 0;
+  HipExec ex;
+  std::unique_ptr<CopyPool> pool;
+  std::unique_ptr<swsrv::Scheduler<HipExec>> sched;
+  swsrv::Limits lim;
+  std::thread th;
+  std::mutex mu;
+  std::condition_variable cv_in, cv_done;
+  std::deque<swsrv::Request*> intake;
+  std::unordered_map<uint64_t, swsrv::Request*> live;
+  swsrv::Counters counters;
+  uint64_t next_ticket = 1;
+  bool stop = false;
+  int thread_error = 0;
+};
+
+static void server_loop(sw_server* sv) {
+  (void)hipSetDevice(sv->device);
+  std::vector<swsrv::Request*> done;
+  for (;;) {
+    {
+      std::unique_lock<std::mutex> lk(sv->mu);
+      if (!sv->sched->busy() && sv->intake.empty()) {
+        if (sv->stop) return;
+        sv->cv_in.wait(lk, [sv] { return sv->stop || !sv->intake.empty(); });
+        if (sv->stop && sv->intake.empty()) return;
+      }
+      while (!sv->intake.empty()) {
+        sv->sched->enqueue(sv->intake.front());
+        sv->intake.pop_front();
+      }
+    }
+    done.clear();
+    const uint64_t batches0 = sv->sched->counters().batches;
+    sv->sched->step(srv_now(), done);
+    const bool launched = sv->sched->counters().batches != batches0;
+    if (!done.empty() || launched) {
+      std::lock_guard<std::mutex> lk(sv->mu);
+      sv->counters = sv->sched->counters();
+      for (swsrv::Request* r : done) r->finished = true;
+      if (!done.empty()) sv->cv_done.notify_all();
+    }
+    if (done.empty() && !launched && sv->sched->running()) {
+      // batches on the device and nothing to do: look again shortly
+      std::unique_lock<std::mutex> lk(sv->mu);
+      sv->cv_in.wait_for(lk, std::chrono::microseconds(20), [sv] { return !sv->intake.empty(); });
+    }
+  }
+}
+
+static void server_free(sw_server* sv) {
+  if (!sv) return;
+  (void)hipSetDevice(sv->device);
+  for (SrvSlot& sl : sv->ex.slot) {
+    if (sl.s) (void)hipStreamSynchronize(sl.s);
+    if (sl.plan) sw_plan_destroy(sl.plan);
+    if (sl.ev) (void)hipEventDestroy(sl.ev);
+    for (void* d : {(void*)sl.d_chars, (void*)sl.d_offsets, (void*)sl.d_docs, (void*)sl.d_perm, (void*)sl.d_boff})
+      if (d) (void)hipFree(d);
+    for (void* h : {(void*)sl.h_chars, (void*)sl.h_offsets, (void*)sl.h_docs, (void*)sl.h_perm, (void*)sl.h_boff,
+                    (void*)sl.h_status})
+      if (h) (void)hipHostFree(h);
+    if (sl.s) (void)hipStreamDestroy(sl.s);
+  }
+  for (auto& kv : sv->live) delete kv.second;
+  delete sv;
+}
+
+extern "C" {
+
+int sw_server_create(const sw_server_config* cfg, sw_server** out) {
+  if (!cfg || !out) return fail(SW_ERR_INVALID_ARG, "sw_server_create: null argument");
+  *out = nullptr;
+  if (cfg->slots < 1 || cfg->slots > 8 || cfg->max_batch_words < 1 || cfg->max_batch_docs < 1 ||
+      cfg->max_batch_chars < 1 || cfg->copy_threads > 64)
+    return fail(SW_ERR_INVALID_ARG, "sw_server_create: slots 1..8, batch limits >= 1, copy_threads <= 64");
+  if (cfg->max_batch_chars >= (1ull << 32))
+    return fail(SW_ERR_INVALID_ARG, "sw_server_create: a batch's characters must stay below 2^32");
+  int device = 0;
+  HIP_TRY(hipGetDevice(&device));
+  sw_server* sv = new sw_server();
+  sv->device = device;
+  sv->lim.budget_bytes = cfg->budget_bytes;
+  sv->lim.max_batch_words = cfg->max_batch_words;
+  sv->lim.max_batch_docs = cfg->max_batch_docs;
+  sv->lim.max_batch_chars = cfg->max_batch_chars;
+  sv->lim.min_batch_words = cfg->min_batch_words;
+  sv->lim.max_wait_s = cfg->max_wait_us * 1e-6;
+  HipExec& ex = sv->ex;
+  ex.max_words = cfg->max_batch_words;
+  ex.max_docs = cfg->max_batch_docs;
+  ex.max_chars = cfg->max_batch_chars;
+  sv->pool.reset(new CopyPool(cfg->copy_threads));
+  ex.pool = sv->pool.get();
+  ex.slot.resize(cfg->slots);
+  const uint64_t W = cfg->max_batch_words, D = cfg->max_batch_docs, C = cfg->max_batch_chars;
+  auto cleanup = [&](int rc) {
+    server_free(sv);
+    return rc;
+  };
+  for (SrvSlot& sl : ex.slot) {
+    if (hipStreamCreateWithFlags(&sl.s, hipStreamNonBlocking) != hipSuccess ||
+        hipEventCreateWithFlags(&sl.ev, hipEventDisableTiming) != hipSuccess)
+      return cleanup(fail(SW_ERR_HIP, "sw_server_create: stream or event creation failed"));
+    int rc = sw_plan_create((uint32_t)W, (uint32_t)D, sl.s, &sl.plan);
+    if (rc) return cleanup(rc);
+    if (hipMalloc(&sl.d_chars, C) != hipSuccess || hipMalloc(&sl.d_offsets, 4 * (W + 1)) != hipSuccess ||
+        hipMalloc(&sl.d_docs, 4 * (D + 1)) != hipSuccess || hipMalloc(&sl.d_perm, 4 * W) != hipSuccess ||
+        hipMalloc(&sl.d_boff, 4 * D * SW_NUM_OFFSETS) != hipSuccess)
+      return cleanup(fail(SW_ERR_OOM, "sw_server_create: device buffers"));
+    if (hipHostMalloc(&sl.h_chars, C, 0) != hipSuccess || hipHostMalloc(&sl.h_offsets, 4 * (W + 1), 0) != hipSuccess ||
+        hipHostMalloc(&sl.h_docs, 4 * (D + 1), 0) != hipSuccess || hipHostMalloc(&sl.h_perm, 4 * W, 0) != hipSuccess ||
+        hipHostMalloc(&sl.h_boff, 4 * D * SW_NUM_OFFSETS, 0) != hipSuccess ||
+        hipHostMalloc(&sl.h_status, 4, 0) != hipSuccess)
+      return cleanup(fail(SW_ERR_OOM, "sw_server_create: pinned staging"));
+  }
+  sv->sched.reset(new swsrv::Scheduler<HipExec>(ex, sv->lim));
+  sv->th = std::thread(server_loop, sv);
+  *out = sv;
+  return SW_OK;
+}
+
+int sw_server_submit(sw_server* sv, const uint8_t* chars, const uint32_t* offsets, uint32_t n_words,
+                     uint32_t* out_perm, uint32_t* out_bucket_offsets, uint64_t* out_ticket) {
+  if (!sv || !offsets || !out_bucket_offsets || !out_ticket || (n_words && !out_perm))
+    return fail(SW_ERR_INVALID_ARG, "sw_server_submit: null argument");
+  const int chk = swsrv::check_request(offsets, n_words, SW_MAX_LEN);
+  if (chk) return fail(chk, "sw_server_submit: %s", chk == SW_ERR_INVALID_ARG ? "offsets decrease" : "a word is too long");
+  const uint64_t nchars = (uint64_t)offsets[n_words] - offsets[0];
+  if (nchars && !chars) return fail(SW_ERR_INVALID_ARG, "sw_server_submit: null characters");
+  swsrv::Request* r = new swsrv::Request();
+  r->chars = chars;
+  r->offsets = offsets;
+  r->n = n_words;
+  r->nchars = nchars;
+  r->bytes = swsrv::footprint(n_words, nchars);
+  r->out_perm = out_perm;
+  r->out_boff = out_bucket_offsets;
+  r->status = 1;   // pending
+  if (!sv->sched->acceptable(*r)) {
+    delete r;
+    return fail(SW_ERR_WORKSPACE, "sw_server_submit: a request of %u words can never fit", n_words);
+  }
+  {
+    std::lock_guard<std::mutex> lk(sv->mu);
+    r->ticket = sv->next_ticket++;
+    r->arrival = srv_now();
+    sv->live[r->ticket] = r;
+    sv->intake.push_back(r);
+    *out_ticket = r->ticket;
+  }
+  sv->cv_in.notify_one();
+  return SW_OK;
+}
+
+int sw_server_wait(sw_server* sv, uint64_t ticket, double* latency_s) {
+  if (!sv) return fail(SW_ERR_INVALID_ARG, "sw_server_wait: null server");
+  std::unique_lock<std::mutex> lk(sv->mu);
+  auto it = sv->live.find(ticket);
+  if (it == sv->live.end()) return fail(SW_ERR_INVALID_ARG, "sw_server_wait: unknown ticket %llu",
+                                        (unsigned long long)ticket);
+  swsrv::Request* r = it->second;
+  sv->cv_done.wait(lk, [r] { return r->finished; });
+  const int st = r->status;
+  if (latency_s) *latency_s = r->done - r->arrival;
+  sv->live.erase(it);
+  delete r;
+  return st ? fail(st, "sw_server_wait: the request's batch failed") : SW_OK;
+}
+
+int sw_server_stats(sw_server* sv, sw_server_counts* out) {
+  if (!sv || !out) return fail(SW_ERR_INVALID_ARG, "sw_server_stats: null argument");
+  std::lock_guard<std::mutex> lk(sv->mu);
+  out->completed = sv->counters.completed;
+  out->failed = sv->counters.failed;
+  out->words = sv->counters.words;
+  out->batches = sv->counters.batches;
+  out->bytes_in_use = sv->counters.in_use;
+  out->max_bytes_in_use = sv->counters.max_in_use;
+  return SW_OK;
+}
+
+size_t sw_server_fixed_bytes(const sw_server_config* cfg) {
+  if (!cfg) return 0;
+  const uint64_t W = cfg->max_batch_words, D = cfg->max_batch_docs;
+  return (size_t)cfg->slots * (sort_words_workspace_size((uint32_t)W, (uint32_t)D) + cfg->max_batch_chars +
+                               8 * (W + 1) + 4 * (D + 1) + 4 * D * SW_NUM_OFFSETS);
+}
+
+void sw_server_destroy(sw_server* sv) {
+  if (!sv) return;
+  {
+    std::lock_guard<std::mutex> lk(sv->mu);
+    sv->stop = true;
+  }
+  sv->cv_in.notify_all();
+  if (sv->th.joinable()) sv->th.join();
+  server_free(sv);
 }
 
 }  // extern "C"

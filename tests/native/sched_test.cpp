@@ -1,0 +1,186 @@
+// CPU test of the serving scheduler's rules (sw_sched.hpp) with a stand-in
+// executor and a simulated clock.  Prints "OK" and exits 0, or names the
+// broken rule and exits 1.
+#include <cstdio>
+#include <cstdlib>
+#include <set>
+#include <vector>
+
+#include "sw_sched.hpp"
+
+using swsrv::Batch;
+using swsrv::Request;
+
+#define CHECK(cond, ...)                                 \
+  do {                                                   \
+    if (!(cond)) {                                       \
+      std::printf("FAIL line %d: ", __LINE__);           \
+      std::printf(__VA_ARGS__);                          \
+      std::printf("\n");                                 \
+      std::exit(1);                                      \
+    }                                                    \
+  } while (0)
+
+struct FakeExec {
+  uint32_t nslots = 2;
+  uint64_t max_words = 1000, max_docs = 8, max_chars = 1 << 20;
+  double* clock = nullptr;
+  double per_word = 1e-6;                 // simulated device time
+  uint64_t poison = ~0ull;                // a batch holding this ticket fails on the "device"
+  std::vector<std::vector<uint64_t>> launched;   // tickets of every batch, in launch order
+  std::vector<double> finish_at;
+  std::vector<int> running_per_launch;
+  int running = 0, max_running = 0;
+
+  uint32_t slots() const { return nslots; }
+  bool capacity(uint64_t w, uint64_t d, uint64_t c) const { return w <= max_words && d <= max_docs && c <= max_chars; }
+  int launch(Batch& b) {
+    std::vector<uint64_t> t;
+    for (Request* r : b.reqs) t.push_back(r->ticket);
+    launched.push_back(t);
+    finish_at.resize((size_t)b.slot + 1 > finish_at.size() ? (size_t)b.slot + 1 : finish_at.size());
+    finish_at[(size_t)b.slot] = *clock + 1e-5 + per_word * (double)b.words;
+    ++running;
+    if (running > max_running) max_running = running;
+    return 0;
+  }
+  bool poll(const Batch& b) { return *clock >= finish_at[(size_t)b.slot]; }
+  int finish(Batch& b) {
+    --running;
+    for (Request* r : b.reqs)
+      if (r->ticket == poison) return -5;
+    for (Request* r : b.reqs)
+      for (uint32_t i = 0; i < r->n; ++i) r->out_perm[i] = i;
+    return 0;
+  }
+};
+
+static Request* make(uint64_t ticket, uint32_t n, double t, std::vector<uint32_t>& store) {
+  Request* r = new Request();
+  r->ticket = ticket;
+  r->n = n;
+  r->nchars = 4ull * n;
+  r->bytes = swsrv::footprint(n, r->nchars);
+  r->arrival = t;
+  store.assign(n ? n : 1, 0xFFFFFFFFu);
+  r->out_perm = store.data();
+  return r;
+}
+
+int main() {
+  // 1. FIFO admission under the budget: a large head request is not overtaken
+  {
+    double clock = 0;
+    FakeExec ex;
+    ex.clock = &clock;
+    swsrv::Limits lim;
+    lim.budget_bytes = swsrv::footprint(600, 2400) + swsrv::footprint(100, 400);
+    lim.max_batch_words = 1000;
+    lim.max_batch_docs = 8;
+    swsrv::Scheduler<FakeExec> s(ex, lim);
+    std::vector<std::vector<uint32_t>> store(4);
+    std::vector<Request*> reqs = {make(1, 600, 0, store[0]), make(2, 500, 0, store[1]), make(3, 50, 0, store[2]),
+                                  make(4, 100, 0, store[3])};
+    for (Request* r : reqs) {
+      CHECK(s.acceptable(*r), "request %llu refused", (unsigned long long)r->ticket);
+      s.enqueue(r);
+    }
+    std::vector<Request*> done;
+    std::set<uint64_t> seen;
+    for (int it = 0; it < 100000 && s.busy(); ++it) {
+      s.step(clock, done);
+      CHECK(s.counters().in_use <= lim.budget_bytes, "budget exceeded: %llu", (unsigned long long)s.counters().in_use);
+      clock += 1e-5;
+    }
+    CHECK(!s.busy(), "did not drain");
+    for (Request* r : done) {
+      CHECK(seen.insert(r->ticket).second, "request %llu finished twice", (unsigned long long)r->ticket);
+      CHECK(r->status == 0 && r->out_perm[0] == 0, "request %llu has no result", (unsigned long long)r->ticket);
+    }
+    CHECK(seen.size() == 4, "%zu of 4 finished", seen.size());
+    // request 1 (600 words) fits alone; 2 (500) does not fit beside it, and 3
+    // and 4 must not overtake 2: the first batch is {1}, the second starts
+    // with 2
+    CHECK(ex.launched[0].size() == 1 && ex.launched[0][0] == 1, "first batch is not {1}");
+    CHECK(ex.launched[1][0] == 2, "request 2 was overtaken");
+    CHECK(s.counters().max_in_use <= lim.budget_bytes, "max in use above budget");
+    for (Request* r : reqs) delete r;
+  }
+  // 2. batch limits and order; slots overlap; min batch words while busy
+  {
+    double clock = 0;
+    FakeExec ex;
+    ex.clock = &clock;
+    ex.per_word = 2e-6;
+    swsrv::Limits lim;
+    lim.max_batch_words = 1000;
+    lim.max_batch_docs = 4;
+    lim.min_batch_words = 300;
+    lim.max_wait_s = 1e-3;
+    swsrv::Scheduler<FakeExec> s(ex, lim);
+    const int N = 60;
+    std::vector<std::vector<uint32_t>> store(N);
+    std::vector<Request*> reqs;
+    std::vector<Request*> done;
+    for (int i = 0; i < N; ++i) {
+      reqs.push_back(make((uint64_t)i + 1, (uint32_t)(20 + (i * 37) % 200), clock, store[(size_t)i]));
+      s.enqueue(reqs.back());
+      s.step(clock, done);
+      clock += 2e-5;
+    }
+    for (int it = 0; it < 1000000 && s.busy(); ++it) {
+      s.step(clock, done);
+      clock += 1e-5;
+    }
+    CHECK(!s.busy() && done.size() == (size_t)N, "did not drain (%zu of %d)", done.size(), N);
+    uint64_t expect = 1;
+    for (size_t b = 0; b < ex.launched.size(); ++b) {
+      uint64_t words = 0;
+      for (uint64_t t : ex.launched[b]) {
+        CHECK(t == expect, "batch %zu takes request %llu out of order", b, (unsigned long long)t);
+        ++expect;
+        words += reqs[(size_t)t - 1]->n;
+      }
+      CHECK(ex.launched[b].size() <= lim.max_batch_docs && words <= lim.max_batch_words, "batch %zu over limits", b);
+    }
+    CHECK(ex.max_running == 2, "the two slots never overlapped (max running %d)", ex.max_running);
+    CHECK(ex.launched.size() < (size_t)N, "no batching happened");
+    for (Request* r : reqs) delete r;
+  }
+  // 3. a batch that fails on the device fails its requests only
+  {
+    double clock = 0;
+    FakeExec ex;
+    ex.clock = &clock;
+    ex.nslots = 1;
+    ex.poison = 2;
+    swsrv::Limits lim;
+    lim.max_batch_docs = 1;
+    swsrv::Scheduler<FakeExec> s(ex, lim);
+    std::vector<std::vector<uint32_t>> store(3);
+    std::vector<Request*> reqs = {make(1, 10, 0, store[0]), make(2, 10, 0, store[1]), make(3, 10, 0, store[2])};
+    for (Request* r : reqs) s.enqueue(r);
+    std::vector<Request*> done;
+    for (int it = 0; it < 10000 && s.busy(); ++it) {
+      s.step(clock, done);
+      clock += 1e-4;
+    }
+    CHECK(done.size() == 3, "not all finished");
+    CHECK(reqs[0]->status == 0 && reqs[1]->status == -5 && reqs[2]->status == 0, "failure not isolated");
+    CHECK(s.counters().failed == 1 && s.counters().completed == 2, "counters wrong");
+    CHECK(s.counters().in_use == 0, "bytes not released");
+    for (Request* r : reqs) delete r;
+  }
+  // 4. intake checks
+  {
+    uint32_t ok[] = {0, 3, 3, 35};
+    uint32_t dec[] = {0, 3, 2};
+    uint32_t lng[] = {5, 10, 43};
+    CHECK(swsrv::check_request(ok, 3, 32) == 0, "good request refused");
+    CHECK(swsrv::check_request(dec, 2, 32) == -1, "decreasing offsets accepted");
+    CHECK(swsrv::check_request(lng, 2, 32) == -2, "33-byte word accepted");
+    CHECK(swsrv::check_request(ok, 0, 32) == 0, "empty request refused");
+  }
+  std::printf("OK\n");
+  return 0;
+}

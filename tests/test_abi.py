@@ -87,3 +87,22 @@ def test_unbucketed_validates_on_host():
     assert L.sort_words_unbucketed(None, None, 0, None, None, None, 0, None) == sw.ERR_INVALID_ARG
     assert L.sort_words_unbucketed(1, 1, 5, None, 1, 1, 1 << 20, None) == sw.ERR_INVALID_ARG
     assert L.sort_words_unbucketed(1, 1, 5, 1, 1, 1, 16, None) == sw.ERR_WORKSPACE
+
+
+def test_server_validates_on_host():
+    import ctypes
+    import paper_1411_5283_amd as sw
+    L = sw.lib()
+    h = ctypes.c_void_p()
+    bad = [sw.sw_server_config(0, 1000, 8, 0, 1 << 20, 1 << 30, 0, 0),        # no slot
+           sw.sw_server_config(9, 1000, 8, 0, 1 << 20, 1 << 30, 0, 0),        # too many slots
+           sw.sw_server_config(2, 0, 8, 0, 1 << 20, 1 << 30, 0, 0),           # empty batches
+           sw.sw_server_config(2, 1000, 8, 65, 1 << 20, 1 << 30, 0, 0),       # too many copy threads
+           sw.sw_server_config(2, 1000, 8, 0, 1 << 32, 1 << 30, 0, 0)]        # 2^32 characters
+    for cfg in bad:
+        assert L.sw_server_create(ctypes.byref(cfg), ctypes.byref(h)) == sw.ERR_INVALID_ARG
+    assert L.sw_server_create(None, ctypes.byref(h)) == sw.ERR_INVALID_ARG
+    t = ctypes.c_uint64()
+    assert L.sw_server_submit(None, None, None, 0, None, None, ctypes.byref(t)) == sw.ERR_INVALID_ARG
+    assert L.sw_server_wait(None, 1, None) == sw.ERR_INVALID_ARG
+    assert L.sw_server_fixed_bytes(None) == 0
