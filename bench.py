@@ -243,8 +243,10 @@ def _arrivals(rset, rate, submit):
     for r in rset:
         t += rng.exponential(1.0 / rate)
         wait = t - time.perf_counter()
-        if wait > 0:
-            time.sleep(wait)
+        if wait > 3e-4:                 # sleep most of a long gap, spin the rest (sleep is coarse)
+            time.sleep(wait - 2e-4)
+        while time.perf_counter() < t:
+            pass
         out.append(submit(r))
     return t0, out
 
@@ -264,6 +266,9 @@ def _serve_points(run, warm, meas):
 
 
 def serve_native(args, sw, reqs, warm, meas):
+    """One server for the whole measurement: the warm-up requests go first
+    (a closed burst, not measured), then the saturation rate is a closed burst
+    of the measured requests, then Poisson arrivals at fractions of it."""
     cfg = dict(slots=args.serve_slots, max_batch_words=args.serve_batch_words,
                max_batch_docs=args.serve_batch_docs, max_batch_chars=args.serve_batch_words * 8,
                min_batch_words=args.serve_min_words, max_wait_us=int(args.serve_max_wait_ms * 1e3),
@@ -271,21 +276,35 @@ def serve_native(args, sw, reqs, warm, meas):
     probe = sw.NativeServer(budget_bytes=1 << 30, **cfg)
     budget = (8 << 30) - probe.fixed_bytes()
     probe.close()
+    srv = sw.NativeServer(budget_bytes=budget, **cfg)
 
     def run(rset, rate):
-        srv = sw.NativeServer(budget_bytes=budget, **cfg)
+        s0 = srv.stats()
         t0, tickets = _arrivals(rset, rate, lambda r: srv.submit(r.chars, r.offsets))
         lats = [srv.wait(t)[2] for t in tickets]
         t1 = time.perf_counter()
-        st = srv.stats()
-        srv.close()
+        s1 = srv.stats()
         words = sum(r.n for r in rset)
         return {"requests": len(rset), "words": words, "seconds": t1 - t0,
                 "mwords_s": words / (t1 - t0) / 1e6, "p50_ms": float(np.percentile(lats, 50)) * 1e3,
-                "p99_ms": float(np.percentile(lats, 99)) * 1e3, "batches": st["batches"],
-                "max_bytes_in_use": st["max_bytes_in_use"]}
+                "p99_ms": float(np.percentile(lats, 99)) * 1e3, "batches": s1["batches"] - s0["batches"],
+                "max_bytes_in_use": s1["max_bytes_in_use"]}
 
-    return (*_serve_points(run, warm, meas), budget), None
+    run(warm, None)
+    sat = run(meas, None)
+    log("saturation (closed burst of the measured requests): %s" % sat)
+    sat_rate = sat["requests"] / sat["seconds"]
+    points = []
+    for frac in (0.5, 0.8, 1.0):
+        r = run(meas, frac * sat_rate)
+        r["lambda_req_s"] = frac * sat_rate
+        r["lambda_frac"] = frac
+        points.append(r)
+        log("lambda %.1f x saturation: %s" % (frac, r))
+    st = srv.stats()
+    srv.close()
+    assert st["max_bytes_in_use"] <= budget
+    return (sat, points, budget), None
 
 
 def serve_python(args, sw, reqs, warm, meas):
@@ -416,11 +435,11 @@ def main():
     ap.add_argument("--serve-warmup", type=int, default=200)
     ap.add_argument("--serve-requests", type=int, default=1000)
     ap.add_argument("--serve-slots", type=int, default=2)
-    ap.add_argument("--serve-batch-words", type=int, default=1 << 22)
-    ap.add_argument("--serve-batch-docs", type=int, default=256)
-    ap.add_argument("--serve-min-words", type=int, default=1 << 20)
+    ap.add_argument("--serve-batch-words", type=int, default=1 << 21)
+    ap.add_argument("--serve-batch-docs", type=int, default=64)
+    ap.add_argument("--serve-min-words", type=int, default=1 << 18)
     ap.add_argument("--serve-max-wait-ms", type=float, default=1.0)
-    ap.add_argument("--serve-copy-threads", type=int, default=4)
+    ap.add_argument("--serve-copy-threads", type=int, default=10)
     ap.add_argument("--serve-python", action="store_true", help="the Python scheduler instead of the native loop")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
