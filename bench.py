@@ -170,8 +170,8 @@ def cpu_baseline(wl, budget_s: float = 12.0) -> dict:
 
 
 def hbm_traffic(dominant_kernel: str):
-    """HBM bytes per launch of the dominant kernel from the committed
-    rocprofv3 counter summary, if it was taken on the current kernel source."""
+    """HBM bytes per launch of a kernel family from the committed rocprofv3
+    counter summary, if it was taken on the current kernel source."""
     try:
         with open(TRAFFIC_FILE) as f:
             t = json.load(f)
@@ -408,9 +408,11 @@ def text_bench(args, sw, wordgen, torch, wl, chars, offs, docs, perm, boff, perm
     return {
         "tokenize": {"ms": tok_ms, "text_bytes": nb, "words": nw, "Mwords_per_s": nw / (tok_ms / 1e3) / 1e6,
                      "algorithmic_GBs": tok_bytes / (tok_ms / 1e3) / 1e9, "same_as_word_list": tok_ok,
+                     "traffic_bytes": {k: hbm_traffic(k) for k in ("tok_sum", "tok_scan", "tok_write")},
                      "input": "the word list rendered as text: capitals, punctuation, line breaks, digits"},
         "materialize": {"ms": mat_ms, "text_bytes": size, "Mwords_per_s": n / (mat_ms / 1e3) / 1e6,
                         "algorithmic_GBs": mat_bytes / (mat_ms / 1e3) / 1e9, "status": status,
+                        "traffic_bytes": hbm_traffic("materialize"),
                         "sampled_check": bool(mat_ok), "separator": "line feed"},
     }
 

@@ -225,17 +225,18 @@ __device__ inline void lds_bytes_to_global(const uint8_t* src, uint32_t len, uin
   for (uint32_t i = head + 4 * body + threadIdx.x; i < len; i += NT) dst[i] = src[i];
 }
 
-// Pass 3: every thread rescans its bytes; its letters and the offsets of the
-// words starting among them go to LDS at their places in the workgroup's
-// output (which is one contiguous stretch of chars and one of offsets), and
-// the workgroup stores both stretches whole.
+// Pass 3: every thread rescans its bytes.  Its letters go to LDS at their
+// places in the workgroup's stretch of chars (laid out on the output's dword
+// grid, so that the stretch is stored as whole dwords); the offsets of the
+// words that start among them go straight to memory (a thread's words are
+// consecutive there).
 __global__ __launch_bounds__(kTokNT) void k_tok_write(Header* h, const uint8_t* text, uint64_t n, const uint4* pre,
                                                       uint32_t flags, uint8_t* out_chars, uint32_t* out_offsets) {
   __shared__ uint32_t s_last[kTokNT / 64];
   __shared__ uint32_t s_tmp[kTokNT / 64];
-  __shared__ uint8_t s_chr[kTokBlock];
-  __shared__ uint32_t s_off[kTokBlock / 2];
+  __shared__ uint32_t s_chr32[kTokBlock / 4 + 2];
   if (h->abort) return;
+  uint8_t* s_chr = (uint8_t*)s_chr32;
   const uint64_t b = blockIdx.x;
   const uint64_t p = b * kTokBlock + (uint64_t)threadIdx.x * kTokBytes;
   const uint32_t cnt = p < n ? (uint32_t)min<uint64_t>(kTokBytes, n - p) : 0u;
@@ -247,23 +248,36 @@ __global__ __launch_bounds__(kTokNT) void k_tok_write(Header* h, const uint8_t* 
   if (carry == TS_NONE) carry = bp.z;
   const uint32_t starts = carry == TS_LETTER ? s.starts_letter : s.starts_space;
   uint32_t nl, nwd;
-  uint32_t lpos = block_excl_scan<kTokNT>(s.letters, s_tmp, nl);   // inside the workgroup
-  uint32_t wpos = block_excl_scan<kTokNT>(starts, s_tmp, nwd);
+  const uint32_t lrel = block_excl_scan<kTokNT>(s.letters, s_tmp, nl);   // inside the workgroup
+  uint32_t wpos = bp.y + block_excl_scan<kTokNT>(starts, s_tmp, nwd);
+  const uint32_t head = (uint32_t)((uintptr_t)(out_chars + bp.x) & 3u);   // LDS byte of the stretch's first letter
   const uint32_t fold = (flags & kTokFlagLower) ? 32u : 0u;
+  uint32_t lpos = lrel;
   uint32_t cur = carry;
   for (uint32_t i = 0; i < cnt; ++i) {
     const uint32_t c = (w[i >> 2] >> (8 * (i & 3))) & 0xFFu;
     if (tok_space(c)) {
       cur = TS_SPACE;
     } else if (tok_letter(c)) {
-      if (cur != TS_LETTER) s_off[wpos++] = bp.x + lpos;
-      s_chr[lpos++] = (uint8_t)(c | (c < 97u ? fold : 0u));
+      if (cur != TS_LETTER) out_offsets[wpos++] = bp.x + lpos;
+      s_chr[head + lpos++] = (uint8_t)(c | (c < 97u ? fold : 0u));
       cur = TS_LETTER;
     }
   }
   __syncthreads();
-  lds_bytes_to_global<kTokNT>(s_chr, nl, out_chars + bp.x);
-  for (uint32_t j = threadIdx.x; j < nwd; j += kTokNT) out_offsets[bp.y + j] = s_off[j];
+  // the stretch [head, head + nl) of LDS to out_chars + bp.x: edge bytes one
+  // by one, whole dwords in between (LDS dword k is output dword k)
+  uint8_t* dst = out_chars + bp.x - head;
+  const uint32_t end = head + nl;
+  const uint32_t d0 = (head + 3) >> 2, d1 = end >> 2;   // whole dwords [d0, d1)
+  if (d0 > d1) {
+    for (uint32_t i = head + threadIdx.x; i < end; i += kTokNT) dst[i] = s_chr[i];
+  } else {
+    for (uint32_t i = head + threadIdx.x; i < 4 * d0; i += kTokNT) dst[i] = s_chr[i];
+    uint32_t* dst32 = (uint32_t*)dst;
+    for (uint32_t k = d0 + threadIdx.x; k < d1; k += kTokNT) dst32[k] = s_chr32[k];
+    for (uint32_t i = 4 * d1 + threadIdx.x; i < end; i += kTokNT) dst[i] = s_chr[i];
+  }
 }
 
 // ---------------------------------------------------------------- sorted text
