@@ -27,7 +27,6 @@ constexpr int kNClass = 4;
 constexpr int kMaxLev = 24;             // merge levels a segment may need
 constexpr uint32_t kWordsPerBlock = 4096;
 constexpr uint32_t kSegsPerBlock = 4096;
-constexpr uint32_t kMinMergeTile = 512;      // smallest merge tile of any variant
 // Short segments (at most kPackMax words) are sorted several to a tile of
 // kPackTile items by k_sort_packed.
 constexpr uint32_t kPackTile = 2048;
@@ -110,8 +109,6 @@ struct Ws {
   uint32_t* st;         // [Smax+kNClass]  chunk-sort tile prefix per class
   uint32_t* mt;         // [Smax+kNClass]  merge tile prefix per class
   uint32_t* vpre;       // [Smax+kNClass]  prefix of short-segment sizes per class
-  uint4* rec;           // [kNClass][rec_stride]  record of each merge tile (k_partition)
-  uint32_t rec_stride;  // Nmax/kMinMergeTile + Smax + 2
   KeyBuf a;             // key buffer 0 (scatter output, chunk sort in place)
   KeyBuf b;             // key buffer 1 (ping-pong for merge levels)
   uint32_t Nmax, Dmax, Bmax, Smax, SBmax;

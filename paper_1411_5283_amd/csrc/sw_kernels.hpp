@@ -16,8 +16,11 @@
 //                  big-endian key lanes + index (the sub-arrays of phase 2)
 //   k_sort_tiles   per tile: odd-even transposition on chunks (bubble sort's
 //                  parallel form), then merge-path merges in LDS up to the tile
-//   k_merge        one merge-path level over HBM; the last level of a segment
-//                  writes the output permutation
+//   k_merge        one merge-path level over HBM (each workgroup places its
+//                  own tiles); the last level of a segment writes the output
+//                  permutation
+//   k_pack_full    the same words as one sequence of full keys (baseline
+//                  without length lists)
 // Every kernel after k_begin reads the run from the workspace, so the same
 // sequence runs eagerly or as one captured HIP graph.
 #pragma once
@@ -1076,83 +1079,29 @@ __device__ inline MergeTile merge_tile(uint32_t n, uint32_t j, uint64_t R, uint3
   return m;
 }
 
-// Per merge tile record written by k_partition: the tile's segment (first
-// position, size), its index in the segment, and the merge-path split at its
-// first output (A items before it).
+// Placement of a merge tile: its segment (first position, size), its index in
+// the segment, and the merge-path split at its first output (A items before
+// it).
 struct TileRec {
   uint32_t base, n, j, split;
 };
 
-// k_partition: the record of every tile of one merge level.  Groups of
-// kPartLanes lanes each place one tile (kPartLanes probes per round), so a
-// wave places 64/kPartLanes tiles; merge workgroups then need a single
-// 16-byte load to place a tile.
+// Merge tiles are placed by groups of kPartLanes lanes (kPartLanes probes per
+// round of the merge-path search): fewer lanes touch fewer cache lines per
+// round, more lanes need fewer rounds.
 constexpr int kPartLanes = 16;
-template <int NL, int NT>
-__global__ __launch_bounds__(NT) void k_partition(Ws w, int cls, int level, TileWork tw, uint32_t P) {
-  constexpr int TPW = 64 / kPartLanes;   // tiles per wave
-  Header* h = w.h;
-  if (h->abort) return;
-  const uint64_t R = (uint64_t)w.T[cls] << level;
-  uint32_t ntiles, cstart = 0, cact = 0;
-  const uint32_t* mt = nullptr;
-  if (tw.direct) {
-    if ((uint32_t)level >= tw.m) return;
-    ntiles = (tw.n + P - 1) / P;
-  } else {
-    cstart = h->cls_start[cls];
-    cact = h->active[cls][level];
-    mt = w.mt + cstart + cls;
-    ntiles = cact ? mt[cact] : 0u;
-  }
-  const KeyBuf src = (level & 1) ? w.b : w.a;
-  TileRec* rec = (TileRec*)w.rec + (size_t)cls * w.rec_stride;
-  const uint32_t lane = __lane_id();
-  const uint32_t nw = gridDim.x * (NT / 64);
-  for (uint32_t t0 = (blockIdx.x * (NT / 64) + (threadIdx.x >> 6)) * TPW; t0 < ntiles; t0 += nw * TPW) {
-    const uint32_t t = t0 + lane / kPartLanes;
-    const bool active = t < ntiles;
-    TileSeg g{0, 0, 0};
-    if (active) {
-      if (tw.direct) {
-        g.base = tw.base;
-        g.n = tw.n;
-        g.j = t;
-      } else {
-        // the group's tile: its segment by a plain search (per lane, same answer in the group)
-        uint32_t lo = 0, hi = cact;   // largest k with mt[k] <= t
-        while (hi - lo > 1) {
-          const uint32_t mid = (lo + hi) >> 1;
-          if (mt[mid] <= t)
-            lo = mid;
-          else
-            hi = mid;
-        }
-        const uint32_t s = w.sorted[cstart + lo];
-        g.base = w.seg_base[s];
-        g.n = w.seg_n[s];
-        g.j = t - mt[lo];
-      }
-    }
-    MergeTile m{};
-    if (active) m = merge_tile(g.n, g.j, R, P);
-    const size_t abase = (size_t)g.base + m.ps;
-    const uint32_t sp = group_merge_path<NL, kPartLanes>(src, abase, m.la, abase + m.la, m.lb, m.d0, active);
-    if (active && lane % kPartLanes == 0) rec[t] = TileRec{g.base, g.n, g.j, sp};
-  }
-}
 
-// Where a merge tile reads and writes, from its record and the split of the
-// next tile.
+// Where a merge tile reads and writes, from its placement and the split at
+// its last output.
 struct TileIO {
   size_t apos, bpos, ob;
   int na, cnt;
   int final;   // nonzero on the segment's last level
 };
-__device__ inline TileIO tile_io(const TileRec& r, uint32_t next_split, uint64_t R, uint32_t P, uint32_t Tc,
+__device__ inline TileIO tile_io(const TileRec& r, uint32_t end_split, uint64_t R, uint32_t P, uint32_t Tc,
                                  int level) {
   const MergeTile m = merge_tile(r.n, r.j, R, P);
-  const uint32_t a1 = m.d1 == m.la + m.lb ? m.la : next_split;
+  const uint32_t a1 = m.d1 == m.la + m.lb ? m.la : end_split;
   TileIO io;
   io.apos = (size_t)r.base + m.ps + r.split;
   io.bpos = (size_t)r.base + m.ps + m.la + (m.d0 - r.split);
@@ -1178,19 +1127,82 @@ __device__ inline void load_tile_regs(const KeyBuf& src, const TileIO& io, Key<N
 // ---------------------------------------------------------------- k_merge
 // One merge level of class cls: every segment still merging has runs of
 // R = T << level sorted items; pairs of runs are merged into runs of 2R.
-// Work is cut into tiles of P = NT*E outputs placed by k_partition.  Each
-// workgroup walks its tiles (grid stride) as a pipeline: while it merges tile
-// t, the inputs of its next tile are already on their way into registers and
-// the record of the tile after that is being fetched.  A tile's inputs are
-// staged in LDS, each thread finds its diagonal by merge path and merges E
-// outputs in registers (method MM), the outputs are staged back in LDS and
-// stored in order.  The segment's last level writes indices to the output
-// permutation.
+// Work is cut into tiles of P = NT*E outputs.  A workgroup takes tiles
+// t = blockIdx.x + k*gridDim.x and places them itself, TB at a time: groups
+// of kPartLanes lanes find each tile's segment and the merge-path splits at
+// its first and last output, into LDS.  Tiles then run as a pipeline: while
+// tile k merges, the inputs of tile k+1 are already on their way into
+// registers.  A tile's two input ranges are staged in LDS as A, sentinel, B,
+// sentinel; each thread finds its diagonal by merge path and merges E outputs
+// in registers (method MM); the outputs are staged back in LDS and stored in
+// order with the nontemporal hint.  The segment's last level writes indices
+// to the output permutation.
+template <int NL, int NT>
+__device__ inline void place_tiles(const Ws& w, int cls, int level, const TileWork& tw, uint32_t P, uint32_t ntiles,
+                                   uint32_t k0, TileRec* s_rec, uint32_t* s_end) {
+  static_assert(NT / kPartLanes >= 2 && NT / kPartLanes <= 16, "two searches per tile, at most 8 tiles");
+  Header* h = w.h;
+  const uint64_t R = (uint64_t)w.T[cls] << level;
+  const uint32_t lane = __lane_id();
+  const uint32_t g = threadIdx.x / kPartLanes;
+  const uint32_t t = blockIdx.x + (k0 + g / 2) * gridDim.x;
+  const bool active = t < ntiles;
+  TileSeg sg{0, 0, 0};
+  if (active) {
+    if (tw.direct) {
+      sg.base = tw.base;
+      sg.n = tw.n;
+      sg.j = t;
+    }
+  }
+  if (!tw.direct) {
+    // the tile's segment: the last k with mt[k] <= t, kPartLanes probes per
+    // round (every lane of the group takes part, active or not)
+    const uint32_t cstart = h->cls_start[cls];
+    const uint32_t cact = h->active[cls][level];
+    const uint32_t* mt = w.mt + cstart + cls;
+    const uint32_t gl = lane % kPartLanes;
+    const uint64_t gmask = (((1ull << kPartLanes) - 1) << (lane - gl));
+    uint32_t lo = 0, hi = active ? cact : 1u;
+    while (__any(hi - lo > 1)) {
+      const uint32_t step = (hi - lo + kPartLanes - 1) / kPartLanes;
+      const uint32_t k = lo + gl * step;
+      const bool p = hi - lo > 1 && k < hi && mt[k] <= t;
+      const uint32_t c = __popcll(__ballot(p) & gmask);
+      if (hi - lo > 1) {
+        const uint32_t nlo = lo + (c - 1) * step;   // mt[lo] <= t, so c >= 1
+        hi = min(nlo + step, hi);
+        lo = nlo;
+      }
+    }
+    if (active) {
+      const uint32_t s = w.sorted[cstart + lo];
+      sg.base = w.seg_base[s];
+      sg.n = w.seg_n[s];
+      sg.j = t - mt[lo];
+    }
+  }
+  MergeTile m{};
+  if (active) m = merge_tile(sg.n, sg.j, R, P);
+  const KeyBuf src = (level & 1) ? w.b : w.a;
+  const size_t abase = (size_t)sg.base + m.ps;
+  const uint32_t d = (g & 1) ? m.d1 : m.d0;
+  const uint32_t sp = group_merge_path<NL, kPartLanes>(src, abase, m.la, abase + m.la, m.lb, d, active);
+  if (active && lane % kPartLanes == 0) {
+    if (g & 1)
+      s_end[g / 2] = sp;
+    else
+      s_rec[g / 2] = TileRec{sg.base, sg.n, sg.j, sp};
+  }
+}
+
 template <int NL, int NT, int E, int MM>
 __global__ __launch_bounds__(NT) void k_merge(Ws w, int cls, int level, TileWork tw) {
   constexpr int P = NT * E;
-  // inputs with the two sentinels, plus the slots a finished thread may read
+  constexpr uint32_t TB = NT / kPartLanes / 2;   // tiles placed per batch
   __shared__ LdsTile<NL, P + 2 * E> tile;
+  __shared__ TileRec s_rec[TB];
+  __shared__ uint32_t s_end[TB];
   Header* h = w.h;
   if (h->abort) return;
   const uint32_t Tc = w.T[cls];
@@ -1204,19 +1216,18 @@ __global__ __launch_bounds__(NT) void k_merge(Ws w, int cls, int level, TileWork
     ntiles = cact ? (w.mt + h->cls_start[cls] + cls)[cact] : 0u;
   }
   const uint32_t G = gridDim.x;
-  uint32_t t = blockIdx.x;
-  if (t >= ntiles) return;
+  if (blockIdx.x >= ntiles) return;
+  const uint32_t nb = (ntiles - blockIdx.x + G - 1) / G;   // tiles of this workgroup
   const KeyBuf src = (level & 1) ? w.b : w.a;
   const KeyBuf dst = (level & 1) ? w.a : w.b;
-  const TileRec* rec = (const TileRec*)w.rec + (size_t)cls * w.rec_stride;
   uint32_t* out_perm = h->d.out_perm;
 
-  TileIO cur = tile_io(rec[t], rec[t + 1].split, R, P, Tc, level);
+  place_tiles<NL, NT>(w, cls, level, tw, P, ntiles, 0, s_rec, s_end);
+  __syncthreads();
+  TileIO cur = tile_io(s_rec[0], s_end[0], R, P, Tc, level);
   Key<NL> pf[E];
   load_tile_regs<NL, NT, E>(src, cur, pf);
-  TileRec rn = rec[t + G < ntiles ? t + G : t];
-  uint32_t rn1 = rec[t + G < ntiles ? t + G + 1 : t].split;
-  for (; t < ntiles; t += G) {
+  for (uint32_t k = 0; k < nb; ++k) {
 #pragma unroll
     for (int r = 0; r < E; ++r) {
       const int i = threadIdx.x + r * NT;
@@ -1226,24 +1237,20 @@ __global__ __launch_bounds__(NT) void k_merge(Ws w, int cls, int level, TileWork
       tile.put(cur.na, key_sentinel<NL>());
       tile.put(cur.cnt + 1, key_sentinel<NL>());
     }
+    const bool has_next = k + 1 < nb;
+    if (has_next && (k + 1) % TB == 0) place_tiles<NL, NT>(w, cls, level, tw, P, ntiles, k + 1, s_rec, s_end);
     __syncthreads();
-    // the next tile's inputs and the record of the one after
-    const bool has_next = t + G < ntiles;
     TileIO nxt = cur;
     if (has_next) {
-      nxt = tile_io(rn, rn1, R, P, Tc, level);
+      nxt = tile_io(s_rec[(k + 1) % TB], s_end[(k + 1) % TB], R, P, Tc, level);
       load_tile_regs<NL, NT, E>(src, nxt, pf);
-      if (t + 2 * G < ntiles) {
-        rn = rec[t + 2 * G];
-        rn1 = rec[t + 2 * G + 1].split;
-      }
     }
-    const int cnt = cur.cnt, na = cur.na, nb = cnt - na;
+    const int cnt = cur.cnt, na = cur.na, nb2 = cnt - na;
     const int diag = threadIdx.x * E;
     Key<NL> e[E];
     if (diag < cnt) {
-      const int sa = padded_merge_path(tile, na, nb, diag);
-      padded_register_merge<E, MM>(tile, na, nb, sa, diag - sa, e);
+      const int sa = padded_merge_path(tile, na, nb2, diag);
+      padded_register_merge<E, MM>(tile, na, nb2, sa, diag - sa, e);
     }
     __syncthreads();
     if (diag < cnt) {

@@ -56,7 +56,6 @@ constexpr int kScatterNT = 512;  // threads per workgroup of k_scatter_pack
 struct Variant {
   void (*sort)(const Ws&, int, TileWork, unsigned, hipStream_t);
   void (*packed)(const Ws&, int, unsigned, hipStream_t);
-  void (*partition)(const Ws&, int, int, TileWork, unsigned, hipStream_t);
   void (*merge)(const Ws&, int, int, TileWork, unsigned, hipStream_t);
   const void* sort_fn;
   const void* merge_fn;
@@ -64,7 +63,6 @@ struct Variant {
   int nts, ntm;
 };
 
-constexpr int kPartNT = 256;
 
 template <int NL, int NTS, int ES, int NTM, int EM, int MM = 0>
 struct V {
@@ -74,16 +72,12 @@ struct V {
   static void packed(const Ws& w, int c, unsigned grid, hipStream_t s) {
     sw::k_sort_packed<NL, 8, 0><<<grid, sw::kPackTile / 8, 0, s>>>(w, c);
   }
-  static void partition(const Ws& w, int c, int l, TileWork tw, unsigned grid, hipStream_t s) {
-    sw::k_partition<NL, kPartNT><<<grid, kPartNT, 0, s>>>(w, c, l, tw, (uint32_t)(NTM * EM));
-  }
   static void merge(const Ws& w, int c, int l, TileWork tw, unsigned grid, hipStream_t s) {
     sw::k_merge<NL, NTM, EM, MM><<<grid, NTM, 0, s>>>(w, c, l, tw);
   }
   static Variant get() {
-    static_assert(NTM * EM >= (int)sw::kMinMergeTile, "merge tile below the split-array sizing");
     static_assert(NTM * EM <= 2 * NTS * ES, "merge tile must divide a pair of sorted tiles");
-    return Variant{sort, packed, partition, merge, (const void*)sw::k_sort_tiles<NL, NTS, ES, MM>,
+    return Variant{sort, packed, merge, (const void*)sw::k_sort_tiles<NL, NTS, ES, MM>,
                    (const void*)sw::k_merge<NL, NTM, EM, MM>, (uint32_t)(NTS * ES), (uint32_t)(NTM * EM), NTS, NTM};
   }
 };
@@ -161,8 +155,8 @@ int device_info(DevInfo** out) {
 
 // ------------------------------------------------------------------ layout
 struct Layout {
-  uint64_t Nmax = 0, Dmax = 0, Bmax = 0, Smax = 0, SBmax = 0, rec_stride = 0;
-  size_t o_hdr, o_doc_off, o_doc_blk, o_cnt, o_seg_n, o_seg_base, o_segcnt, o_sorted, o_st, o_mt, o_vpre, o_rec;
+  uint64_t Nmax = 0, Dmax = 0, Bmax = 0, Smax = 0, SBmax = 0;
+  size_t o_hdr, o_doc_off, o_doc_blk, o_cnt, o_seg_n, o_seg_base, o_segcnt, o_sorted, o_st, o_mt, o_vpre;
   size_t o_a[4], o_ai, o_b[4], o_bi;
   size_t total = 0;
 };
@@ -193,8 +187,6 @@ bool make_layout(uint64_t Nmax, uint64_t Dmax, Layout& L) {
   L.o_st = take(4 * (L.Smax + sw::kNClass));
   L.o_mt = take(4 * (L.Smax + sw::kNClass));
   L.o_vpre = take(4 * (L.Smax + sw::kNClass));
-  L.rec_stride = Nmax / sw::kMinMergeTile + L.Smax + 2;
-  L.o_rec = take(16 * sw::kNClass * L.rec_stride);
   for (int q = 0; q < 4; ++q) L.o_a[q] = take(8 * N1);
   L.o_ai = take(4 * N1);
   for (int q = 0; q < 4; ++q) L.o_b[q] = take(8 * N1);
@@ -232,8 +224,6 @@ Ws make_ws(void* base, const Layout& L, const sw_config& cfg) {
   w.st = (uint32_t*)(p + L.o_st);
   w.mt = (uint32_t*)(p + L.o_mt);
   w.vpre = (uint32_t*)(p + L.o_vpre);
-  w.rec = (uint4*)(p + L.o_rec);
-  w.rec_stride = (uint32_t)L.rec_stride;
   for (int q = 0; q < 4; ++q) {
     w.a.k[q] = (uint64_t*)(p + L.o_a[q]);
     w.b.k[q] = (uint64_t*)(p + L.o_b[q]);
@@ -259,13 +249,12 @@ Ws make_ws(void* base, const Layout& L, const sw_config& cfg) {
 enum KernelId {
   K_BEGIN, K_DOC_PLAN, K_HIST, K_SCAN, K_SEGMENTS, K_SEG_COUNT, K_SEG_SCATTER, K_TILE_PREFIX, K_SCATTER,
   K_SORT0, K_SORT1, K_SORT2, K_SORT3, K_MERGE0, K_MERGE1, K_MERGE2, K_MERGE3,
-  K_PART0, K_PART1, K_PART2, K_PART3, K_PACK0, K_PACK1, K_PACK2, K_PACK3, K_COUNT
+  K_PACK0, K_PACK1, K_PACK2, K_PACK3, K_COUNT
 };
 const char* const kKernelNames[K_COUNT] = {
     "begin", "doc_plan", "hist", "scan_rows", "segments", "seg_count", "seg_scatter", "tile_prefix",
     "scatter_pack", "sort_tiles_c0", "sort_tiles_c1", "sort_tiles_c2", "sort_tiles_c3",
     "merge_c0", "merge_c1", "merge_c2", "merge_c3",
-    "partition_c0", "partition_c1", "partition_c2", "partition_c3",
     "sort_packed_c0", "sort_packed_c1", "sort_packed_c2", "sort_packed_c3"};
 
 struct ProfRec {
@@ -316,7 +305,7 @@ struct ProfScope {
 struct Grids {
   uint32_t flags;
   unsigned words, scatter, docs, segs;
-  unsigned sort[sw::kNClass], merge[sw::kNClass], part[sw::kNClass], packed;
+  unsigned sort[sw::kNClass], merge[sw::kNClass], packed;
   int levels[sw::kNClass];
   const Variant* var[sw::kNClass];
 };
@@ -342,8 +331,6 @@ int make_grids(const Ws& w, const sw_config& cfg, Grids& g) {
     const uint64_t maxtiles_m = (uint64_t)w.Nmax / vs[v].P + w.Smax;
     g.sort[c] = clampg(maxtiles_s, cus * (uint64_t)d->occ_sort[c][v]);
     g.merge[c] = clampg(maxtiles_m, cus * (uint64_t)d->occ_merge[c][v]);
-    const uint64_t tiles_per_wg = (uint64_t)(kPartNT / 64) * (64 / sw::kPartLanes);
-    g.part[c] = clampg((maxtiles_m + tiles_per_wg - 1) / tiles_per_wg, cus * 8);
     g.levels[c] = (int)sw::levels_for(w.Nmax, vs[v].T);
   }
   return SW_OK;
@@ -351,7 +338,7 @@ int make_grids(const Ws& w, const sw_config& cfg, Grids& g) {
 
 // Side streams and events for running the four key classes concurrently:
 // after the scatter the classes share nothing, so each class's chain (chunk
-// sort, then partition + merge per level) goes on its own stream, forked
+// sort, then one merge per level) goes on its own stream, forked
 // from and joined back into the caller's stream.  Under graph capture the
 // chains become parallel branches of the graph.
 struct Fork {
@@ -461,10 +448,6 @@ int enqueue_body(const Ws& w, const Grids& g, hipStream_t s, bool capture, bool 
     for (int c = 0; c < sw::kNClass; ++c) {
       if (l >= g.levels[c]) continue;
       hipStream_t cs = cstream(c);
-      {
-        ProfScope p(K_PART0 + c, cs, capture);
-        g.var[c]->partition(w, c, l, none, g.part[c], cs);
-      }
       ProfScope p(K_MERGE0 + c, cs, capture);
       g.var[c]->merge(w, c, l, none, g.merge[c], cs);
     }
@@ -537,7 +520,7 @@ Cache g_cache[64];
 extern "C" {
 
 const char* sort_words_last_error(void) { return g_err.c_str(); }
-const char* sort_words_version(void) { return "sortwords-gfx950 0.6"; }
+const char* sort_words_version(void) { return "sortwords-gfx950 0.7"; }
 
 size_t sort_words_workspace_size(uint32_t max_words, uint32_t max_docs) {
   Layout L;
@@ -653,11 +636,6 @@ int sort_words_plain(const uint8_t* chars, const uint32_t* offsets, const uint32
     }
     const uint32_t mtiles = (n + v.P - 1) / v.P;
     for (uint32_t l = 0; l < m; ++l) {
-      {
-        ProfScope p(K_PART0 + c, s, false);
-        const uint32_t tiles_per_wg = (kPartNT / 64) * (64 / sw::kPartLanes);
-        v.partition(w, c, (int)l, tw, (mtiles + tiles_per_wg - 1) / tiles_per_wg, s);
-      }
       ProfScope p(K_MERGE0 + c, s, false);
       v.merge(w, c, (int)l, tw, mtiles, s);
     }
@@ -698,11 +676,8 @@ int sort_words_unbucketed(const uint8_t* chars, const uint32_t* offsets, uint32_
     const TileWork tw{1, 0, n, m};
     v.sort(w, c, tw, (n + v.T - 1) / v.T, s);
     const uint32_t mtiles = (n + v.P - 1) / v.P;
-    const uint32_t tiles_per_wg = (kPartNT / 64) * (64 / sw::kPartLanes);
-    for (uint32_t l = 0; l < m; ++l) {
-      v.partition(w, c, (int)l, tw, (mtiles + tiles_per_wg - 1) / tiles_per_wg, s);
+    for (uint32_t l = 0; l < m; ++l)
       v.merge(w, c, (int)l, tw, std::min<uint32_t>(mtiles, (uint32_t)(di->cus * di->occ_merge[c][cfg.variant[c]])), s);
-    }
   }
   HIP_TRY(hipGetLastError());
   return SW_OK;

@@ -1,7 +1,7 @@
 """Autotuner for the chunk size and tile variant of each key class.
 
 For every key class it times each compiled tile variant with each chunk size
-on a real workload (kernel time of that class's chunk sort, partition and
+on a real workload (kernel time of that class's chunk sort and
 merge levels, from the library's HIP-event timing), checks that every
 candidate returns exactly the same permutation and bucket offsets as the
 first run, and keeps the fastest.  Results are cached in a JSON file keyed by
@@ -81,7 +81,7 @@ def tune(wl, name: str, reps: int = 2, chunks=CHUNKS, log=print) -> dict:
                 if not same:
                     raise RuntimeError("class %d variant %d chunk %d changed the result" % (c, v, C))
                 ms = sum(prof.get(k, (0, 0.0))[1] for k in
-                         ("sort_tiles_c%d" % c, "partition_c%d" % c, "merge_c%d" % c)) / reps
+                         ("sort_tiles_c%d" % c, "merge_c%d" % c)) / reps
                 trials.append({"class": c, "variant": v, "chunk": C, "ms": ms})
                 log("class %d variant %d chunk %4d: %.4f ms" % (c, v, C, ms))
                 if best_t is None or ms < best_t:
