@@ -1127,35 +1127,35 @@ __device__ inline void load_tile_regs(const KeyBuf& src, const TileIO& io, Key<N
 // ---------------------------------------------------------------- k_merge
 // One merge level of class cls: every segment still merging has runs of
 // R = T << level sorted items; pairs of runs are merged into runs of 2R.
-// Work is cut into tiles of P = NT*E outputs.  A workgroup takes tiles
-// t = blockIdx.x + k*gridDim.x and places them itself, TB at a time: groups
-// of kPartLanes lanes find each tile's segment and the merge-path splits at
-// its first and last output, into LDS.  Tiles then run as a pipeline: while
-// tile k merges, the inputs of tile k+1 are already on their way into
+// Work is cut into tiles of P = NT*E outputs; a workgroup takes a contiguous
+// range of tiles and places them itself, TB at a time: group g of
+// kPartLanes lanes finds the segment of tile t0+g (a kPartLanes-ary search
+// over the class's tile prefix) and the merge-path split at its first output,
+// so that the split at a tile's last output is the next tile's (NT/kPartLanes
+// searches place NT/kPartLanes - 1 tiles).  Tiles then run as a pipeline:
+// while tile k merges, the inputs of tile k+1 are already on their way into
 // registers.  A tile's two input ranges are staged in LDS as A, sentinel, B,
-// sentinel; each thread finds its diagonal by merge path and merges E outputs
-// in registers (method MM); the outputs are staged back in LDS and stored in
-// order with the nontemporal hint.  The segment's last level writes indices
-// to the output permutation.
+// sentinel; each thread finds its diagonal by merge path and merges E
+// outputs in registers (method MM); the outputs are staged back in LDS and
+// stored in order with the nontemporal hint.  The segment's last level writes
+// indices to the output permutation.
 template <int NL, int NT>
 __device__ inline void place_tiles(const Ws& w, int cls, int level, const TileWork& tw, uint32_t P, uint32_t ntiles,
-                                   uint32_t k0, TileRec* s_rec, uint32_t* s_end) {
-  static_assert(NT / kPartLanes >= 2 && NT / kPartLanes <= 16, "two searches per tile, at most 8 tiles");
+                                   uint32_t t0, TileRec* s_rec, uint32_t* s_split) {
+  constexpr int NG = NT / kPartLanes;
+  static_assert(NG >= 2 && NG <= 16, "groups of kPartLanes lanes");
   Header* h = w.h;
   const uint64_t R = (uint64_t)w.T[cls] << level;
   const uint32_t lane = __lane_id();
   const uint32_t g = threadIdx.x / kPartLanes;
-  const uint32_t t = blockIdx.x + (k0 + g / 2) * gridDim.x;
+  const uint32_t t = t0 + g;
   const bool active = t < ntiles;
   TileSeg sg{0, 0, 0};
-  if (active) {
-    if (tw.direct) {
-      sg.base = tw.base;
-      sg.n = tw.n;
-      sg.j = t;
-    }
-  }
-  if (!tw.direct) {
+  if (tw.direct) {
+    sg.base = tw.base;
+    sg.n = tw.n;
+    sg.j = t;
+  } else {
     // the tile's segment: the last k with mt[k] <= t, kPartLanes probes per
     // round (every lane of the group takes part, active or not)
     const uint32_t cstart = h->cls_start[cls];
@@ -1186,23 +1186,20 @@ __device__ inline void place_tiles(const Ws& w, int cls, int level, const TileWo
   if (active) m = merge_tile(sg.n, sg.j, R, P);
   const KeyBuf src = (level & 1) ? w.b : w.a;
   const size_t abase = (size_t)sg.base + m.ps;
-  const uint32_t d = (g & 1) ? m.d1 : m.d0;
-  const uint32_t sp = group_merge_path<NL, kPartLanes>(src, abase, m.la, abase + m.la, m.lb, d, active);
+  const uint32_t sp = group_merge_path<NL, kPartLanes>(src, abase, m.la, abase + m.la, m.lb, m.d0, active);
   if (active && lane % kPartLanes == 0) {
-    if (g & 1)
-      s_end[g / 2] = sp;
-    else
-      s_rec[g / 2] = TileRec{sg.base, sg.n, sg.j, sp};
+    s_split[g] = sp;
+    if (g + 1 < (uint32_t)NG) s_rec[g] = TileRec{sg.base, sg.n, sg.j, sp};
   }
 }
 
 template <int NL, int NT, int E, int MM>
 __global__ __launch_bounds__(NT) void k_merge(Ws w, int cls, int level, TileWork tw) {
   constexpr int P = NT * E;
-  constexpr uint32_t TB = NT / kPartLanes / 2;   // tiles placed per batch
+  constexpr uint32_t TB = NT / kPartLanes - 1;   // tiles placed per batch
   __shared__ LdsTile<NL, P + 2 * E> tile;
   __shared__ TileRec s_rec[TB];
-  __shared__ uint32_t s_end[TB];
+  __shared__ uint32_t s_split[TB + 1];
   Header* h = w.h;
   if (h->abort) return;
   const uint32_t Tc = w.T[cls];
@@ -1215,16 +1212,18 @@ __global__ __launch_bounds__(NT) void k_merge(Ws w, int cls, int level, TileWork
     const uint32_t cact = h->active[cls][level];
     ntiles = cact ? (w.mt + h->cls_start[cls] + cls)[cact] : 0u;
   }
-  const uint32_t G = gridDim.x;
-  if (blockIdx.x >= ntiles) return;
-  const uint32_t nb = (ntiles - blockIdx.x + G - 1) / G;   // tiles of this workgroup
+  // this workgroup's tiles: [tb, tb + nb), the ranges balanced over the grid
+  const uint32_t G = gridDim.x, q = ntiles / G, rem = ntiles % G;
+  const uint32_t nb = q + (blockIdx.x < rem ? 1u : 0u);
+  if (nb == 0) return;
+  const uint32_t tb = blockIdx.x * q + min(blockIdx.x, rem);
   const KeyBuf src = (level & 1) ? w.b : w.a;
   const KeyBuf dst = (level & 1) ? w.a : w.b;
   uint32_t* out_perm = h->d.out_perm;
 
-  place_tiles<NL, NT>(w, cls, level, tw, P, ntiles, 0, s_rec, s_end);
+  place_tiles<NL, NT>(w, cls, level, tw, P, ntiles, tb, s_rec, s_split);
   __syncthreads();
-  TileIO cur = tile_io(s_rec[0], s_end[0], R, P, Tc, level);
+  TileIO cur = tile_io(s_rec[0], s_split[1], R, P, Tc, level);
   Key<NL> pf[E];
   load_tile_regs<NL, NT, E>(src, cur, pf);
   for (uint32_t k = 0; k < nb; ++k) {
@@ -1238,19 +1237,20 @@ __global__ __launch_bounds__(NT) void k_merge(Ws w, int cls, int level, TileWork
       tile.put(cur.cnt + 1, key_sentinel<NL>());
     }
     const bool has_next = k + 1 < nb;
-    if (has_next && (k + 1) % TB == 0) place_tiles<NL, NT>(w, cls, level, tw, P, ntiles, k + 1, s_rec, s_end);
+    const uint32_t kn = (k + 1) % TB;   // the next tile's slot in its batch
+    if (has_next && kn == 0) place_tiles<NL, NT>(w, cls, level, tw, P, ntiles, tb + k + 1, s_rec, s_split);
     __syncthreads();
     TileIO nxt = cur;
     if (has_next) {
-      nxt = tile_io(s_rec[(k + 1) % TB], s_end[(k + 1) % TB], R, P, Tc, level);
+      nxt = tile_io(s_rec[kn], s_split[kn + 1], R, P, Tc, level);
       load_tile_regs<NL, NT, E>(src, nxt, pf);
     }
-    const int cnt = cur.cnt, na = cur.na, nb2 = cnt - na;
+    const int cnt = cur.cnt, na = cur.na, nbv = cnt - na;
     const int diag = threadIdx.x * E;
     Key<NL> e[E];
     if (diag < cnt) {
-      const int sa = padded_merge_path(tile, na, nb2, diag);
-      padded_register_merge<E, MM>(tile, na, nb2, sa, diag - sa, e);
+      const int sa = padded_merge_path(tile, na, nbv, diag);
+      padded_register_merge<E, MM>(tile, na, nbv, sa, diag - sa, e);
     }
     __syncthreads();
     if (diag < cnt) {
