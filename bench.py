@@ -169,15 +169,18 @@ def cpu_baseline(wl, budget_s: float = 12.0) -> dict:
     return res
 
 
-def hbm_traffic(dominant_kernel: str):
+def hbm_traffic(dominant_kernel: str, workload: str):
     """HBM bytes per launch of a kernel family from the committed rocprofv3
-    counter summary, if it was taken on the current kernel source."""
+    counter summary, if it was taken on the current kernel source and on the
+    same workload."""
     try:
         with open(TRAFFIC_FILE) as f:
             t = json.load(f)
     except (OSError, ValueError):
         return None
     if t.get("source_hash") != kernel_source_hash():
+        return None
+    if t.get("workload", "").split(":")[0].strip() != workload:
         return None
     k = t.get("kernels", {}).get(dominant_kernel)
     return None if k is None else k.get("bytes_per_launch")
@@ -408,11 +411,11 @@ def text_bench(args, sw, wordgen, torch, wl, chars, offs, docs, perm, boff, perm
     return {
         "tokenize": {"ms": tok_ms, "text_bytes": nb, "words": nw, "Mwords_per_s": nw / (tok_ms / 1e3) / 1e6,
                      "algorithmic_GBs": tok_bytes / (tok_ms / 1e3) / 1e9, "same_as_word_list": tok_ok,
-                     "traffic_bytes": {k: hbm_traffic(k) for k in ("tok_sum", "tok_scan", "tok_write")},
+                     "traffic_bytes": {k: hbm_traffic(k, args.workload) for k in ("tok_sum", "tok_scan", "tok_write")},
                      "input": "the word list rendered as text: capitals, punctuation, line breaks, digits"},
         "materialize": {"ms": mat_ms, "text_bytes": size, "Mwords_per_s": n / (mat_ms / 1e3) / 1e6,
                         "algorithmic_GBs": mat_bytes / (mat_ms / 1e3) / 1e9, "status": status,
-                        "traffic_bytes": hbm_traffic("materialize"),
+                        "traffic_bytes": hbm_traffic("materialize", args.workload),
                         "sampled_check": bool(mat_ok), "separator": "line feed"},
     }
 
@@ -604,7 +607,7 @@ def main():
     achieved = kern[dom].get("algorithmic_GBs")
     tsum = sum(v["ms_per_step"] for v in kern.values())
     total_bytes = sum(fam_bytes.values())
-    traffic = hbm_traffic(dom)
+    traffic = hbm_traffic(dom, args.workload)
     roof = {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": (achieved / HBM_PEAK_GBS) if achieved else None,
             "traffic": traffic,

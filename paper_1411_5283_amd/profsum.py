@@ -45,7 +45,7 @@ def _family(kernel: str) -> str | None:
     """Kernel name -> the bench's family name (class = template's first argument)."""
     m = re.match(r"(?:void )?sw::k_(\w+?)<(\d+)", kernel)
     if not m:
-        m2 = re.match(r"(?:void )?sw::k_(\w+?)[<(]", kernel)
+        m2 = re.match(r"(?:void )?sw::k_(\w+?)(?:[<(]|$)", kernel)
         return m2.group(1) if m2 else None
     name, nl = m.group(1), int(m.group(2))
     if name in ("scatter_pack", "hist", "tok_scan", "materialize", "pack_full"):
