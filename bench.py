@@ -337,13 +337,17 @@ def serve_python(args, sw, reqs, warm, meas):
     return out, None
 
 
-def text_bench(args, sw, wordgen, torch, wl, chars, offs, docs, perm, boff, perm_h, boff_h, stream):
+def text_bench(args, sw, wordgen, torch, wl, chars, offs, docs, perm, boff, perm_h, boff_h, stream, plan,
+               plan_ms):
     """The steps around the sort on the same workload: the word list written as
     raw text (capitals, punctuation, line breaks) is tokenized back on the GPU
     (lower-case folding), and the sorted result is written out as text with a
-    line break after every word.  Both are timed with HIP events on the bench
-    stream and checked (the tokenized list must equal the word list; sampled
-    words of the sorted text must equal the words perm names)."""
+    line break after every word, from the permutation (sort_words_materialize)
+    and in the sort's own pass from the sorted keys (sw_plan_run_text).  All
+    are timed with HIP events on the bench stream and checked (the tokenized
+    list must equal the word list; sampled words of the sorted text must equal
+    the words perm names; the one-pass text must equal the other byte for
+    byte, and its permutation the plan's)."""
     n, nd = wl.n, wl.n_docs
     dev = chars.device
     t0 = time.perf_counter()
@@ -407,7 +411,24 @@ def text_bench(args, sw, wordgen, torch, wl, chars, offs, docs, perm, boff, perm
         mat_ok &= out_h[pos:pos + L + 1].tobytes() == w + b"\n"
     mat_bytes = 4 * n + 8 * n + letters + size       # perm, offsets, characters, text
     log("materialize: %.3f ms, status=%d, sampled check=%s" % (mat_ms, status, mat_ok))
-    del out
+
+    # sort and text in one pass: the sorted keys are written out as text
+    out2 = torch.empty(max(size, 1), dtype=torch.uint8, device=dev)
+    perm4 = torch.empty_like(perm)
+    run_st = lambda: plan.run_text(chars, offs, docs, nd, n, perm4, boff, 10, out2)
+    run_st()
+    st_status = plan.status_code()
+    e0.record(stream)
+    for _ in range(reps):
+        run_st()
+    e1.record(stream)
+    torch.cuda.synchronize()
+    st_ms = e0.elapsed_time(e1) / reps
+    st_status = st_status or plan.status_code()
+    st_same = st_status == 0 and bool(torch.equal(out2[:size], out[:size])) and bool(torch.equal(perm4, perm))
+    log("sort + text: %.3f ms (sort alone %.3f ms), status=%d, same text and permutation=%s" %
+        (st_ms, plan_ms, st_status, st_same))
+    del out, out2, perm4
     return {
         "tokenize": {"ms": tok_ms, "text_bytes": nb, "words": nw, "Mwords_per_s": nw / (tok_ms / 1e3) / 1e6,
                      "algorithmic_GBs": tok_bytes / (tok_ms / 1e3) / 1e9, "same_as_word_list": tok_ok,
@@ -417,6 +438,12 @@ def text_bench(args, sw, wordgen, torch, wl, chars, offs, docs, perm, boff, perm
                         "algorithmic_GBs": mat_bytes / (mat_ms / 1e3) / 1e9, "status": status,
                         "traffic_bytes": hbm_traffic("materialize", args.workload),
                         "sampled_check": bool(mat_ok), "separator": "line feed"},
+        "sort_and_text": {"ms": st_ms, "sort_alone_ms": plan_ms, "text_ms": st_ms - plan_ms,
+                          "Mwords_per_s": n / (st_ms / 1e3) / 1e6, "status": st_status,
+                          "same_text_as_materialize": st_same,
+                          "traffic_bytes": hbm_traffic("keys_text", args.workload),
+                          "form": "sw_plan_run_text: the sort's graph plus the text written from the sorted "
+                                  "keys (each segment's last level also keeps its keys)"},
     }
 
 
@@ -619,7 +646,7 @@ def main():
             "eager_kernel_sum_ms": tsum}
 
     text = None if args.no_text else text_bench(args, sw, wordgen, torch, wl, chars, offs, docs, perm, boff,
-                                                   perm_h, boff_h, stream)
+                                                   perm_h, boff_h, stream, plan, ms_step)
     cpu = None if args.no_cpu_baseline else cpu_baseline(wl)
     out = {
         "metric": METRIC, "value": value, "unit": "Mwords/s", "n_gpus": 1, "steps": args.steps,

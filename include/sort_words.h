@@ -155,6 +155,21 @@ int sw_plan_create(uint32_t max_words, uint32_t max_docs, void *stream, sw_plan 
 int sw_plan_run(sw_plan *plan, const uint8_t *chars, const uint32_t *offsets,
                 const uint32_t *doc_offsets, uint32_t n_docs, uint32_t n_words,
                 uint32_t *out_perm, uint32_t *out_bucket_offsets);
+/* Sort and sorted text in one pass (section 4 prints the merged result):
+ * sw_plan_run's arguments and outputs, and out_text receives the words in
+ * sorted order, each followed by the byte `sep` (0..255) or back to back when
+ * sep < 0, in exactly the layout sort_words_materialize writes (documents one
+ * after another; out_text holds (offsets[N] - offsets[0]) + (sep >= 0 ? N : 0)
+ * bytes, N the total words).  Every word fits its key (at most 32 bytes), so
+ * the text is written from the sorted keys: no word is read again from
+ * chars.  The first call captures a second graph (the pass plus the text
+ * writer); later calls launch it.  Asynchronous; device errors via
+ * sw_plan_status (on an error out_text is unspecified, and no byte outside
+ * it is written). */
+int sw_plan_run_text(sw_plan *plan, const uint8_t *chars, const uint32_t *offsets,
+                     const uint32_t *doc_offsets, uint32_t n_docs, uint32_t n_words,
+                     uint32_t *out_perm, uint32_t *out_bucket_offsets, int sep,
+                     uint8_t *out_text);
 int sw_plan_status(sw_plan *plan);
 /* sort_words_status_async for a plan (copy enqueued on the plan's stream). */
 int sw_plan_status_async(sw_plan *plan, uint32_t *status_dst);

@@ -78,6 +78,7 @@ def lib() -> ctypes.CDLL:
         "sort_words_status": ([vp, vp], i32),
         "sw_plan_create": ([u32, u32, vp, ctypes.POINTER(vp)], i32),
         "sw_plan_run": ([vp, vp, vp, vp, u32, u32, vp, vp], i32),
+        "sw_plan_run_text": ([vp, vp, vp, vp, u32, u32, vp, vp, i32, vp], i32),
         "sw_plan_status": ([vp], i32),
         "sw_plan_status_async": ([vp, vp], i32),
         "sort_words_status_async": ([vp, vp, vp], i32),
@@ -113,7 +114,7 @@ def lib() -> ctypes.CDLL:
 
 EXPORTED = ("sort_words", "sort_words_workspace_size", "sort_words_ex", "sort_words_batch",
             "sort_words_plain", "sort_words_unbucketed", "sort_words_status", "sort_words_status_async",
-            "sort_words_decode_status", "sw_plan_create", "sw_plan_run",
+            "sort_words_decode_status", "sw_plan_create", "sw_plan_run", "sw_plan_run_text",
             "sw_plan_status", "sw_plan_status_async", "sw_plan_destroy", "sw_get_config", "sw_set_config",
             "sw_num_variants", "sw_variant_tiles", "sw_profile_enable", "sw_profile_reset",
             "sw_profile_read", "sort_words_tokenize_workspace_size", "sort_words_tokenize",
@@ -216,6 +217,14 @@ class Plan:
         return _check(lib().sw_plan_run(self._h, _ptr(chars), _ptr(offsets), _ptr(doc_offsets),
                                         int(n_docs), int(n_words), _ptr(out_perm),
                                         _ptr(out_bucket_offsets)))
+
+    def run_text(self, chars, offsets, doc_offsets, n_docs, n_words, out_perm, out_bucket_offsets, sep,
+                 out_text) -> int:
+        """run() plus the sorted text written from the sorted keys (sw_plan_run_text);
+        out_text: text_size(...) bytes, the layout materialize() writes."""
+        return _check(lib().sw_plan_run_text(self._h, _ptr(chars), _ptr(offsets), _ptr(doc_offsets),
+                                             int(n_docs), int(n_words), _ptr(out_perm),
+                                             _ptr(out_bucket_offsets), int(sep), _ptr(out_text)))
 
     def status(self) -> int:
         return _check(lib().sw_plan_status(self._h))

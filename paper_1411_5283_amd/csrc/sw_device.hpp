@@ -73,6 +73,8 @@ struct RunDesc {
   uint32_t* out_boff;
   uint32_t n_words;              // used when doc_offsets is null
   uint32_t n_docs;
+  uint8_t* out_text;             // non-null: also write the sorted text
+  int32_t sep;                   // its separator byte, or none when negative
 };
 
 struct Header {

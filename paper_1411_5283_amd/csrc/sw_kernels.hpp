@@ -419,7 +419,7 @@ __device__ inline void lds_be_lanes(const uint32_t* dw, uint32_t pos, uint32_t L
 // records which word holds each slot.  Pass 2 walks the slots in order, so
 // consecutive lanes write consecutive positions of one segment (coalesced
 // stores), reading the words from LDS.
-constexpr uint32_t kScatterChars = 32768;
+constexpr uint32_t kScatterChars = 24576;   // three workgroups per CU; a block of 4096 words averages about 18 KB
 template <int NT>
 __global__ __launch_bounds__(NT) void k_scatter_pack(Ws w) {
   constexpr int NW = NT / 64;
@@ -931,6 +931,7 @@ __global__ __launch_bounds__(NT) void k_sort_tiles(Ws w, int cls, TileWork tw) {
     ntiles = h->sort_tiles[cls];
   }
   uint32_t* out_perm = h->d.out_perm;
+  const bool keep = h->d.out_text != nullptr;
   for (uint32_t t = blockIdx.x; t < ntiles; t += gridDim.x) {
     TileSeg g;
     if (tw.direct) {
@@ -963,10 +964,8 @@ __global__ __launch_bounds__(NT) void k_sort_tiles(Ws w, int cls, TileWork tw) {
       const uint32_t i = threadIdx.x + r * NT;
       if (i < cnt) {
         const Key<NL> v = tile.get(i);
-        if (final)
-          out_perm[gb + i] = key_index<NL>(v);
-        else
-          gstore<NL>(w.a, gb + i, v);
+        if (final) out_perm[gb + i] = key_index<NL>(v);
+        if (!final || keep) gstore<NL>(w.a, gb + i, v);
       }
     }
     __syncthreads();
@@ -999,6 +998,7 @@ __global__ __launch_bounds__(kPackTile / E) void k_sort_packed(Ws w, int cls) {
   const uint32_t* vp = w.vpre + ps + cls;     // npack + 1 entries
   const uint32_t ntiles = (h->pack_words[cls] + H - 1) / H;
   uint32_t* out_perm = h->d.out_perm;
+  const bool keep = h->d.out_text != nullptr;
   for (uint32_t k = blockIdx.x; k < ntiles; k += gridDim.x) {
     if (threadIdx.x < 2) {
       // first segment starting at or after k*H (resp. (k+1)*H)
@@ -1049,10 +1049,15 @@ __global__ __launch_bounds__(kPackTile / E) void k_sort_packed(Ws w, int cls) {
         }
       }
       sort_tile_core<NT, E, MM>(tile, e, C, cnt);
+      if (keep) __syncthreads();   // every item read before any is overwritten
 #pragma unroll
       for (int r = 0; r < E; ++r) {
         const uint32_t p = p0 + r;
-        if (p < cnt) out_perm[(size_t)s_base[e[r].tag] + (p - s_start[e[r].tag])] = key_index<NL>(e[r].k);
+        if (p < cnt) {
+          const size_t q = (size_t)s_base[e[r].tag] + (p - s_start[e[r].tag]);
+          out_perm[q] = key_index<NL>(e[r].k);
+          if (keep) gstore<NL>(w.a, q, e[r].k);
+        }
       }
     }
     __syncthreads();
@@ -1220,6 +1225,7 @@ __global__ __launch_bounds__(NT) void k_merge(Ws w, int cls, int level, TileWork
   const KeyBuf src = (level & 1) ? w.b : w.a;
   const KeyBuf dst = (level & 1) ? w.a : w.b;
   uint32_t* out_perm = h->d.out_perm;
+  const bool keep = h->d.out_text != nullptr;
 
   place_tiles<NL, NT>(w, cls, level, tw, P, ntiles, tb, s_rec, s_split);
   __syncthreads();
@@ -1263,10 +1269,8 @@ __global__ __launch_bounds__(NT) void k_merge(Ws w, int cls, int level, TileWork
       const int o = threadIdx.x + r * NT;
       if (o < cnt) {
         const Key<NL> v = tile.get(o);
-        if (cur.final)
-          __builtin_nontemporal_store(key_index<NL>(v), out_perm + cur.ob + o);
-        else
-          gstore_nt<NL>(dst, cur.ob + o, v);
+        if (cur.final) __builtin_nontemporal_store(key_index<NL>(v), out_perm + cur.ob + o);
+        if (!cur.final || keep) gstore_nt<NL>(dst, cur.ob + o, v);
       }
     }
     __syncthreads();

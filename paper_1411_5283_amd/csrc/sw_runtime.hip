@@ -49,6 +49,7 @@ int fail(int code, const char* fmt, ...) {
 
 constexpr int kNT = 256;         // threads per workgroup of the streaming kernels
 constexpr int kScatterNT = 512;  // threads per workgroup of k_scatter_pack
+constexpr int kTextNT = 256, kTextIPT = 8, kTextKTB = 12;   // k_keys_text: threads, words per thread, LDS bytes per word
 
 // ------------------------------------------------------------------ variants
 // A variant fixes, for one key class, the chunk-sort tile (NTS threads x ES
@@ -117,7 +118,7 @@ sw_config current_config() {
 struct DevInfo {
   bool ready = false;
   int cus = 0;
-  int occ_hist = 1, occ_scatter = 1;
+  int occ_hist = 1, occ_scatter = 1, occ_text = 1;
   int occ_sort[sw::kNClass][kMaxVariants] = {};
   int occ_merge[sw::kNClass][kMaxVariants] = {};
 };
@@ -135,6 +136,8 @@ int device_info(DevInfo** out) {
     HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(&d.occ_hist, (const void*)sw::k_hist<kNT>, kNT, 0));
     HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(&d.occ_scatter, (const void*)sw::k_scatter_pack<kScatterNT>,
                                                          kScatterNT, 0));
+    HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(&d.occ_text, (const void*)sw::k_keys_text<kTextNT, kTextIPT, kTextKTB>,
+                                                         kTextNT, 0));
     for (int c = 0; c < sw::kNClass; ++c) {
       int nv;
       const Variant* vs = variants(c, &nv);
@@ -147,6 +150,7 @@ int device_info(DevInfo** out) {
     }
     d.occ_hist = std::max(d.occ_hist, 1);
     d.occ_scatter = std::max(d.occ_scatter, 1);
+    d.occ_text = std::max(d.occ_text, 1);
     d.ready = true;
   }
   *out = &d;
@@ -249,13 +253,13 @@ Ws make_ws(void* base, const Layout& L, const sw_config& cfg) {
 enum KernelId {
   K_BEGIN, K_DOC_PLAN, K_HIST, K_SCAN, K_SEGMENTS, K_SEG_COUNT, K_SEG_SCATTER, K_TILE_PREFIX, K_SCATTER,
   K_SORT0, K_SORT1, K_SORT2, K_SORT3, K_MERGE0, K_MERGE1, K_MERGE2, K_MERGE3,
-  K_PACK0, K_PACK1, K_PACK2, K_PACK3, K_COUNT
+  K_PACK0, K_PACK1, K_PACK2, K_PACK3, K_KEYS_TEXT, K_COUNT
 };
 const char* const kKernelNames[K_COUNT] = {
     "begin", "doc_plan", "hist", "scan_rows", "segments", "seg_count", "seg_scatter", "tile_prefix",
     "scatter_pack", "sort_tiles_c0", "sort_tiles_c1", "sort_tiles_c2", "sort_tiles_c3",
     "merge_c0", "merge_c1", "merge_c2", "merge_c3",
-    "sort_packed_c0", "sort_packed_c1", "sort_packed_c2", "sort_packed_c3"};
+    "sort_packed_c0", "sort_packed_c1", "sort_packed_c2", "sort_packed_c3", "keys_text"};
 
 struct ProfRec {
   int kid;
@@ -305,7 +309,7 @@ struct ProfScope {
 struct Grids {
   uint32_t flags;
   unsigned words, scatter, docs, segs;
-  unsigned sort[sw::kNClass], merge[sw::kNClass], packed;
+  unsigned sort[sw::kNClass], merge[sw::kNClass], packed, text;
   int levels[sw::kNClass];
   const Variant* var[sw::kNClass];
 };
@@ -322,6 +326,7 @@ int make_grids(const Ws& w, const sw_config& cfg, Grids& g) {
   g.docs = clampg((w.Dmax + 3) / 4, cus * 4);
   g.packed = clampg((uint64_t)w.Nmax / sw::kPackMax + 1, cus * 4);
   g.segs = clampg(w.SBmax, cus * 2);
+  g.text = clampg(((uint64_t)w.Nmax + kTextNT * kTextIPT - 1) / (kTextNT * kTextIPT), cus * (uint64_t)d->occ_text);
   for (int c = 0; c < sw::kNClass; ++c) {
     int nv;
     const Variant* vs = variants(c, &nv);
@@ -379,8 +384,9 @@ bool profiling_on() {
 // scatter are enqueued (the per-bucket-launch form continues on the host).
 // With a Fork the key classes run on parallel streams; without one (or while
 // profiling, so that every kernel is timed alone) they run one after another.
+// With `text` the sorted text is written from the sorted keys at the end.
 int enqueue_body(const Ws& w, const Grids& g, hipStream_t s, bool capture, bool through_scatter,
-                 Fork* fork = nullptr) {
+                 Fork* fork = nullptr, bool text = false) {
   {
     ProfScope p(K_DOC_PLAN, s, capture);
     sw::k_doc_plan<1024><<<1, 1024, 0, s>>>(w);
@@ -457,6 +463,10 @@ int enqueue_body(const Ws& w, const Grids& g, hipStream_t s, bool capture, bool 
       HIP_TRY(hipEventRecord(fork->join[c], fork->side[c]));
       HIP_TRY(hipStreamWaitEvent(s, fork->join[c], 0));
     }
+  }
+  if (text) {
+    ProfScope p(K_KEYS_TEXT, s, capture);
+    sw::k_keys_text<kTextNT, kTextIPT, kTextKTB><<<g.text, kTextNT, 0, s>>>(w);
   }
   HIP_TRY(hipGetLastError());
   return SW_OK;
@@ -693,6 +703,8 @@ struct sw_plan {
   bool own_stream = false;
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
+  hipGraph_t graph_text = nullptr;     // the same pass plus the sorted text, captured on first use
+  hipGraphExec_t exec_text = nullptr;
   Fork fork;
 };
 
@@ -701,10 +713,34 @@ static void plan_free(sw_plan* p) {
   if (p->s) (void)hipStreamSynchronize(p->s);
   if (p->exec) (void)hipGraphExecDestroy(p->exec);
   if (p->graph) (void)hipGraphDestroy(p->graph);
+  if (p->exec_text) (void)hipGraphExecDestroy(p->exec_text);
+  if (p->graph_text) (void)hipGraphDestroy(p->graph_text);
   fork_free(p->fork);
   if (p->ws) (void)hipFree(p->ws);
   if (p->own_stream && p->s) (void)hipStreamDestroy(p->s);
   delete p;
+}
+
+// Captures the whole pass (with the sorted text or without) into a graph on
+// the plan's stream.
+static int plan_capture(sw_plan* p, bool text, hipGraph_t* graph_out, hipGraphExec_t* exec_out) {
+  if (hipStreamBeginCapture(p->s, hipStreamCaptureModeThreadLocal) != hipSuccess)
+    return fail(SW_ERR_HIP, "sw_plan: stream capture failed to begin");
+  const int rc = enqueue_body(p->w, p->g, p->s, true, false, &p->fork, text);
+  hipGraph_t graph = nullptr;
+  const hipError_t ec = hipStreamEndCapture(p->s, &graph);
+  if (rc || ec != hipSuccess || !graph) {
+    if (graph) (void)hipGraphDestroy(graph);
+    return rc ? rc : fail(SW_ERR_HIP, "sw_plan: capture failed: %s", hipGetErrorString(ec));
+  }
+  hipGraphExec_t exec = nullptr;
+  if (hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0) != hipSuccess) {
+    (void)hipGraphDestroy(graph);
+    return fail(SW_ERR_HIP, "sw_plan: graph instantiation failed");
+  }
+  *graph_out = graph;
+  *exec_out = exec;
+  return SW_OK;
 }
 
 int sw_plan_create(uint32_t max_words, uint32_t max_docs, void* stream, sw_plan** out) {
@@ -733,52 +769,54 @@ int sw_plan_create(uint32_t max_words, uint32_t max_docs, void* stream, sw_plan*
   const sw_config cfg = current_config();
   p->w = make_ws(p->ws, p->L, cfg);
   int rc = make_grids(p->w, cfg, p->g);
+  if (!rc) rc = fork_init(p->fork);
+  if (!rc) rc = plan_capture(p, false, &p->graph, &p->exec);
   if (rc) {
     plan_free(p);
     return rc;
-  }
-  if ((rc = fork_init(p->fork))) {
-    plan_free(p);
-    return rc;
-  }
-  if (hipStreamBeginCapture(p->s, hipStreamCaptureModeThreadLocal) != hipSuccess) {
-    plan_free(p);
-    return fail(SW_ERR_HIP, "sw_plan_create: stream capture failed to begin");
-  }
-  rc = enqueue_body(p->w, p->g, p->s, true, false, &p->fork);
-  hipGraph_t graph = nullptr;
-  const hipError_t ec = hipStreamEndCapture(p->s, &graph);
-  p->graph = graph;
-  if (rc || ec != hipSuccess || !graph) {
-    plan_free(p);
-    return rc ? rc : fail(SW_ERR_HIP, "sw_plan_create: capture failed: %s", hipGetErrorString(ec));
-  }
-  if (hipGraphInstantiate(&p->exec, p->graph, nullptr, nullptr, 0) != hipSuccess) {
-    p->exec = nullptr;
-    plan_free(p);
-    return fail(SW_ERR_HIP, "sw_plan_create: graph instantiation failed");
   }
   *out = p;
   return SW_OK;
 }
 
-int sw_plan_run(sw_plan* p, const uint8_t* chars, const uint32_t* offsets, const uint32_t* doc_offsets,
-                uint32_t n_docs, uint32_t n_words, uint32_t* out_perm, uint32_t* out_bucket_offsets) {
-  if (!p || !offsets || !out_bucket_offsets) return fail(SW_ERR_INVALID_ARG, "sw_plan_run: null argument");
+static int plan_check(const sw_plan* p, const char* what, const uint32_t* offsets, const uint32_t* doc_offsets,
+                      uint32_t n_docs, uint32_t n_words, const uint32_t* out_perm,
+                      const uint32_t* out_bucket_offsets) {
+  if (!p || !offsets || !out_bucket_offsets) return fail(SW_ERR_INVALID_ARG, "%s: null argument", what);
   if (doc_offsets) {
-    if (n_docs > p->L.Dmax) return fail(SW_ERR_WORKSPACE, "sw_plan_run: %u documents, plan holds %llu", n_docs,
-                                        (unsigned long long)p->L.Dmax);
-    if (!out_perm) return fail(SW_ERR_INVALID_ARG, "sw_plan_run: null out_perm");
+    if (n_docs > p->L.Dmax)
+      return fail(SW_ERR_WORKSPACE, "%s: %u documents, plan holds %llu", what, n_docs, (unsigned long long)p->L.Dmax);
+    if (!out_perm) return fail(SW_ERR_INVALID_ARG, "%s: null out_perm", what);
   } else {
     if (n_words > p->L.Nmax)
-      return fail(SW_ERR_WORKSPACE, "sw_plan_run: %u words, plan holds %llu", n_words,
-                  (unsigned long long)p->L.Nmax);
-    if (n_words && !out_perm) return fail(SW_ERR_INVALID_ARG, "sw_plan_run: null out_perm");
+      return fail(SW_ERR_WORKSPACE, "%s: %u words, plan holds %llu", what, n_words, (unsigned long long)p->L.Nmax);
+    if (n_words && !out_perm) return fail(SW_ERR_INVALID_ARG, "%s: null out_perm", what);
   }
-  RunDesc d{chars, offsets, doc_offsets, out_perm, out_bucket_offsets, n_words, doc_offsets ? n_docs : 1u};
-  int rc = enqueue_begin(p->w, d, p->s);
+  return SW_OK;
+}
+
+int sw_plan_run(sw_plan* p, const uint8_t* chars, const uint32_t* offsets, const uint32_t* doc_offsets,
+                uint32_t n_docs, uint32_t n_words, uint32_t* out_perm, uint32_t* out_bucket_offsets) {
+  int rc = plan_check(p, "sw_plan_run", offsets, doc_offsets, n_docs, n_words, out_perm, out_bucket_offsets);
   if (rc) return rc;
+  RunDesc d{chars, offsets, doc_offsets, out_perm, out_bucket_offsets, n_words, doc_offsets ? n_docs : 1u};
+  if ((rc = enqueue_begin(p->w, d, p->s))) return rc;
   HIP_TRY(hipGraphLaunch(p->exec, p->s));
+  return SW_OK;
+}
+
+int sw_plan_run_text(sw_plan* p, const uint8_t* chars, const uint32_t* offsets, const uint32_t* doc_offsets,
+                     uint32_t n_docs, uint32_t n_words, uint32_t* out_perm, uint32_t* out_bucket_offsets, int sep,
+                     uint8_t* out_text) {
+  int rc = plan_check(p, "sw_plan_run_text", offsets, doc_offsets, n_docs, n_words, out_perm, out_bucket_offsets);
+  if (rc) return rc;
+  if (!out_text) return fail(SW_ERR_INVALID_ARG, "sw_plan_run_text: null out_text");
+  if (sep > 255) return fail(SW_ERR_INVALID_ARG, "sw_plan_run_text: separator %d is not a byte", sep);
+  if (!p->exec_text && (rc = plan_capture(p, true, &p->graph_text, &p->exec_text))) return rc;
+  RunDesc d{chars, offsets, doc_offsets, out_perm, out_bucket_offsets, n_words, doc_offsets ? n_docs : 1u,
+            out_text, sep < 0 ? -1 : sep};
+  if ((rc = enqueue_begin(p->w, d, p->s))) return rc;
+  HIP_TRY(hipGraphLaunch(p->exec_text, p->s));
   return SW_OK;
 }
 

@@ -432,4 +432,206 @@ __global__ __launch_bounds__(NT) void k_materialize(const uint8_t* chars, const 
   }
 }
 
+// ---------------------------------------------------------------- k_keys_text
+// Sorted text from the sorted keys, in the same run as the sort.  A word is
+// at most 32 bytes, so its key lanes (big-endian, zero padded) hold all of its
+// bytes; when the run asks for text, every segment's chunk sort or last merge
+// level leaves its sorted keys in a key buffer besides writing the indices:
+// buffer A when the segment took an even number of merge levels (none
+// included), B when odd.  So the text is written from keys read in order, and
+// no word is read again from the input at a random place.
+//
+// Positions of the sorted order (documents in turn, each document's lengths
+// in turn: the order of the output permutation) are cut into tiles of W; a
+// workgroup takes a contiguous range of tiles.  For a batch of up to NT
+// tiles, thread k first finds where tile k starts: its (document, length)
+// segment and its first byte in the text.  Then tile by tile the workgroup
+// cuts the tile into the pieces of the segments it covers, assembles the
+// text of its words in LDS -- each word followed by the separator when there
+// is one, laid out on the output's dword grid -- and stores it as one
+// stretch (a tile whose text outgrows the LDS stretch, KTB bytes per word
+// on average, writes its words straight to memory instead).  The layout is
+// the permutation-based writer's: document d's text
+// starts at byte (offsets[first word of d] - offsets[0]) + (first word of d)
+// when words are separated, without the second term otherwise.
+struct TextAt {
+  uint32_t seg;   // (document, length) segment holding the position
+  uint64_t pos;   // the position's first text byte
+};
+
+// Segment and text byte of sorted position g (g < N).  Empty documents and
+// segments start where the next one does, so "the last one starting at or
+// before g" skips them.
+__device__ inline TextAt text_at(const Ws& w, const RunDesc& d, uint32_t D, uint32_t sw, uint32_t g) {
+  uint32_t lo = 0, hi = D;
+  while (hi - lo > 1) {
+    const uint32_t mid = (lo + hi) >> 1;
+    if (w.doc_off[mid] <= g)
+      lo = mid;
+    else
+      hi = mid;
+  }
+  const uint32_t* sb = w.seg_base + (size_t)lo * kNB;
+  uint32_t L = 0;
+#pragma unroll
+  for (uint32_t step = 32; step >= 1; step >>= 1)
+    if (L + step <= (uint32_t)kMaxLen && sb[L + step] <= g) L += step;
+  const uint32_t f = w.doc_off[lo];
+  uint64_t pos = (uint64_t)(d.offsets[f] - d.offsets[0]) + (uint64_t)sw * f;
+  const uint32_t* sn = w.seg_n + (size_t)lo * kNB;
+#pragma unroll
+  for (uint32_t l = 0; l < (uint32_t)kMaxLen; ++l)
+    if (l < L) pos += (uint64_t)sn[l] * (l + sw);
+  return TextAt{lo * kNB + L, pos + (uint64_t)(g - sb[L]) * (L + sw)};
+}
+
+// The L bytes of a word from its big-endian key lanes, then the separator
+// when there is one (sw = 1).  Called with an LDS or a global destination, so
+// that each gets its own stores.
+template <class P>
+__device__ inline void put_word_bytes(P dst, const uint64_t (&ln)[4], uint32_t L, uint32_t sw, uint8_t sep) {
+  uint64_t cur = ln[0];
+  for (uint32_t j = 0; j < L; ++j) {
+    dst[j] = (uint8_t)(cur >> 56);
+    cur <<= 8;
+    if ((j & 7u) == 7u) cur = j == 7u ? ln[1] : (j == 15u ? ln[2] : ln[3]);
+  }
+  if (sw) dst[L] = sep;
+}
+
+template <int NT, int IPT, int KTB>
+__global__ __launch_bounds__(NT) void k_keys_text(Ws w) {
+  constexpr uint32_t W = NT * IPT;
+  constexpr uint32_t CAP = W * KTB;      // LDS text bytes of a tile
+  static_assert(NT < 1024 && W * (kMaxLen + 1) < (1u << 22), "piece count and text bytes share one scan");
+  static_assert(W < 65536, "tile positions are 16-bit");
+  __shared__ uint32_t s_txt32[CAP / 4 + 2];
+  __shared__ uint16_t s_first[W + 1];   // first tile position of each piece
+  __shared__ uint32_t s_rel[W];         // its first text byte, counted from the dword below the tile's first
+  __shared__ uint16_t s_info[W];        // length, plus 256 when its keys are in buffer B
+  __shared__ uint32_t s_tseg[NT + 1];   // per tile of the batch: segment of its first position
+  __shared__ uint64_t s_tpos[NT + 1];   // ... and that position's first text byte
+  __shared__ uint32_t s_tmp[NT / 64];
+  uint8_t* s_txt = (uint8_t*)s_txt32;
+  Header* h = w.h;
+  if (h->abort) return;
+  const RunDesc d = h->d;
+  if (d.out_text == nullptr) return;
+  const uint32_t N = h->n_words, D = h->n_docs;
+  const uint32_t sw = d.sep >= 0 ? 1u : 0u;
+  const uint64_t out_size = (uint64_t)(d.offsets[N] - d.offsets[0]) + (uint64_t)sw * N;
+  const uint32_t ntiles = (N + W - 1) / W;
+  const uint32_t G = gridDim.x, q = ntiles / G, rem = ntiles % G;
+  const uint32_t nb = q + (blockIdx.x < rem ? 1u : 0u);
+  const uint32_t tb = blockIdx.x * q + min(blockIdx.x, rem);
+  for (uint32_t c0 = 0; c0 < nb; c0 += NT) {
+    const uint32_t cn = min((uint32_t)NT, nb - c0);
+    // where tiles tb+c0 .. tb+c0+cn-1 start, and the segment of the last
+    // position of the batch (bounding the last tile's pieces)
+    for (uint32_t k = threadIdx.x; k <= cn; k += NT) {
+      const uint32_t g = min((tb + c0 + k) * W, N - 1);
+      const TextAt at = text_at(w, d, D, sw, g);
+      s_tseg[k] = at.seg;
+      s_tpos[k] = at.pos;
+    }
+    __syncthreads();
+    for (uint32_t k = 0; k < cn; ++k) {
+      const uint32_t t = tb + c0 + k;
+      const uint32_t g0 = t * W, g1 = min(N, g0 + W);
+      const uint32_t S0 = s_tseg[k], S1 = s_tseg[k + 1];
+      const uint64_t pos0 = s_tpos[k];
+      // LDS byte of the tile's first text byte: its place in the output's dword grid
+      const uint32_t head = (uint32_t)(((uintptr_t)d.out_text + pos0) & 3u);
+      // the pieces: segments S0..S1 clipped to [g0, g1), the empty ones
+      // dropped; one scan counts them (low 10 bits) and their text bytes
+      uint32_t npieces = 0, tbytes = 0;
+      for (uint32_t sbase = S0; sbase <= S1; sbase += NT) {
+        const uint32_t sg = sbase + threadIdx.x;
+        const uint32_t L = sg % kNB;
+        uint32_t cnt = 0, first = 0, info = 0;
+        if (sg <= S1) {
+          const uint32_t b = w.seg_base[sg], n = w.seg_n[sg];
+          const uint32_t a = max(b, g0), e = min(b + n, g1);
+          if (e > a) {
+            cnt = e - a;
+            first = a - g0;
+            const uint32_t m = n <= kPackMax ? 0u : levels_for(n, w.T[class_of_len(L)]);
+            info = L | ((m & 1u) << 8);
+          }
+        }
+        uint32_t tot;
+        const uint32_t ex = block_excl_scan<NT>((cnt ? 1u : 0u) | ((cnt * (L + sw)) << 10), s_tmp, tot);
+        if (cnt) {
+          s_first[npieces + (ex & 1023u)] = (uint16_t)first;
+          s_rel[npieces + (ex & 1023u)] = head + tbytes + (ex >> 10);
+          s_info[npieces + (ex & 1023u)] = (uint16_t)info;
+        }
+        npieces += tot & 1023u;
+        tbytes += tot >> 10;
+      }
+      if (threadIdx.x == 0) s_first[npieces] = (uint16_t)(g1 - g0);
+      __syncthreads();
+      if (pos0 + tbytes > out_size) {   // cannot happen for checked offsets; never write past the text
+        if (threadIdx.x == 0) atomicOr(&h->status, ST_INVALID);
+        continue;
+      }
+      const bool staged = head + tbytes <= CAP;
+      uint8_t* out = d.out_text + pos0 - head;   // dword aligned; byte `head` is the tile's first
+      // every word's key lanes are requested before any is used
+      uint64_t ln[IPT][4];
+      uint32_t wl[IPT], wrel[IPT];
+#pragma unroll
+      for (int r = 0; r < IPT; ++r) {
+        const uint32_t i = threadIdx.x + (uint32_t)r * NT;
+        wl[r] = 0;
+        wrel[r] = 0;
+        ln[r][0] = ln[r][1] = ln[r][2] = ln[r][3] = 0;
+        if (g0 + i < g1) {
+          uint32_t lo = 0, hi = npieces;   // the last piece starting at or before i
+          while (hi - lo > 1) {
+            const uint32_t mid = (lo + hi) >> 1;
+            if (s_first[mid] <= i)
+              lo = mid;
+            else
+              hi = mid;
+          }
+          const uint32_t info = s_info[lo], L = info & 255u;
+          const bool inb = (info >> 8) != 0;
+          const size_t g = (size_t)g0 + i;
+          wl[r] = L;
+          wrel[r] = s_rel[lo] + (i - s_first[lo]) * (L + sw);
+          ln[r][0] = (inb ? w.b.k[0] : w.a.k[0])[g];   // class 0 keeps its 4 key bytes in the high half
+          if (L > 8) ln[r][1] = (inb ? w.b.k[1] : w.a.k[1])[g];
+          if (L > 16) {
+            ln[r][2] = (inb ? w.b.k[2] : w.a.k[2])[g];
+            ln[r][3] = (inb ? w.b.k[3] : w.a.k[3])[g];
+          }
+        }
+      }
+#pragma unroll
+      for (int r = 0; r < IPT; ++r) {
+        const uint32_t L = wl[r], rel = wrel[r];
+        if (threadIdx.x + (uint32_t)r * NT < g1 - g0) {
+          if (staged)
+            put_word_bytes(s_txt + rel, ln[r], L, sw, (uint8_t)d.sep);
+          else
+            put_word_bytes(out + rel, ln[r], L, sw, (uint8_t)d.sep);
+        }
+      }
+      __syncthreads();
+      if (staged) {
+        // LDS byte j holds the output byte at out + j
+        const uint32_t e = head + tbytes;
+        const uint32_t fb = min(e, 4u);                  // bytes of the first dword
+        const uint32_t nd = e > 4 ? (e - 4) / 4 : 0u;    // whole dwords after it
+        for (uint32_t j = head + threadIdx.x; j < fb; j += NT) out[j] = s_txt[j];
+        uint32_t* o32 = (uint32_t*)(out + 4);
+        for (uint32_t j = threadIdx.x; j < nd; j += NT) o32[j] = s_txt32[1 + j];
+        for (uint32_t j = 4 + 4 * nd + threadIdx.x; j < e; j += NT) out[j] = s_txt[j];
+      }
+      __syncthreads();
+    }
+  }
+}
+
 }  // namespace sw

@@ -48,7 +48,7 @@ def _family(kernel: str) -> str | None:
         m2 = re.match(r"(?:void )?sw::k_(\w+?)(?:[<(]|$)", kernel)
         return m2.group(1) if m2 else None
     name, nl = m.group(1), int(m.group(2))
-    if name in ("scatter_pack", "hist", "tok_scan", "materialize", "pack_full"):
+    if name in ("scatter_pack", "hist", "tok_scan", "materialize", "pack_full", "keys_text"):
         return name
     cls = {0: 0, 1: 1, 2: 2, 4: 3}.get(nl)
     return None if cls is None else "%s_c%d" % (name, cls)

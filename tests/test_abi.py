@@ -76,6 +76,8 @@ def test_text_entry_points_validate_on_host():
     assert L.sort_words_tokenize(1, 10, 0, 1, 1, 4, 1, 1, 8, None) == sw.ERR_WORKSPACE
     # the text writer: null pointers, a separator above 255, n_docs without doc_offsets
     assert L.sort_words_materialize(None, None, None, 1, 0, None, None, 10, None, None, None) == sw.ERR_INVALID_ARG
+    # sort + text: a null plan
+    assert L.sw_plan_run_text(None, None, None, None, 1, 0, None, None, 10, None) == sw.ERR_INVALID_ARG
     assert L.sort_words_materialize(1, 1, None, 1, 5, 1, 1, 256, 1, 1, None) == sw.ERR_INVALID_ARG
     assert L.sort_words_materialize(1, 1, None, 2, 5, 1, 1, 10, 1, 1, None) == sw.ERR_INVALID_ARG
     assert L.sort_words_materialize(1, 1, 1, 0, 5, 1, 1, 10, 1, 1, None) == sw.ERR_INVALID_ARG
