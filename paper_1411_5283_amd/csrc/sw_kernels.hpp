@@ -1137,7 +1137,8 @@ __device__ inline void load_tile_regs(const KeyBuf& src, const TileIO& io, Key<N
 // kPartLanes lanes finds the segment of tile t0+g (a kPartLanes-ary search
 // over the class's tile prefix) and the merge-path split at its first output,
 // so that the split at a tile's last output is the next tile's (NT/kPartLanes
-// searches place NT/kPartLanes - 1 tiles).  Tiles then run as a pipeline:
+// searches place NT/kPartLanes - 1 tiles; groups past the split after the
+// range's last tile search nothing).  Tiles then run as a pipeline:
 // while tile k merges, the inputs of tile k+1 are already on their way into
 // registers.  A tile's two input ranges are staged in LDS as A, sentinel, B,
 // sentinel; each thread finds its diagonal by merge path and merges E
@@ -1146,7 +1147,7 @@ __device__ inline void load_tile_regs(const KeyBuf& src, const TileIO& io, Key<N
 // indices to the output permutation.
 template <int NL, int NT>
 __device__ inline void place_tiles(const Ws& w, int cls, int level, const TileWork& tw, uint32_t P, uint32_t ntiles,
-                                   uint32_t t0, TileRec* s_rec, uint32_t* s_split) {
+                                   uint32_t t0, uint32_t t_end, TileRec* s_rec, uint32_t* s_split) {
   constexpr int NG = NT / kPartLanes;
   static_assert(NG >= 2 && NG <= 16, "groups of kPartLanes lanes");
   Header* h = w.h;
@@ -1154,7 +1155,7 @@ __device__ inline void place_tiles(const Ws& w, int cls, int level, const TileWo
   const uint32_t lane = __lane_id();
   const uint32_t g = threadIdx.x / kPartLanes;
   const uint32_t t = t0 + g;
-  const bool active = t < ntiles;
+  const bool active = t < ntiles && t <= t_end;   // past t_end no split is needed
   TileSeg sg{0, 0, 0};
   if (tw.direct) {
     sg.base = tw.base;
@@ -1227,7 +1228,7 @@ __global__ __launch_bounds__(NT) void k_merge(Ws w, int cls, int level, TileWork
   uint32_t* out_perm = h->d.out_perm;
   const bool keep = h->d.out_text != nullptr;
 
-  place_tiles<NL, NT>(w, cls, level, tw, P, ntiles, tb, s_rec, s_split);
+  place_tiles<NL, NT>(w, cls, level, tw, P, ntiles, tb, tb + nb, s_rec, s_split);
   __syncthreads();
   TileIO cur = tile_io(s_rec[0], s_split[1], R, P, Tc, level);
   Key<NL> pf[E];
@@ -1244,7 +1245,7 @@ __global__ __launch_bounds__(NT) void k_merge(Ws w, int cls, int level, TileWork
     }
     const bool has_next = k + 1 < nb;
     const uint32_t kn = (k + 1) % TB;   // the next tile's slot in its batch
-    if (has_next && kn == 0) place_tiles<NL, NT>(w, cls, level, tw, P, ntiles, tb + k + 1, s_rec, s_split);
+    if (has_next && kn == 0) place_tiles<NL, NT>(w, cls, level, tw, P, ntiles, tb + k + 1, tb + nb, s_rec, s_split);
     __syncthreads();
     TileIO nxt = cur;
     if (has_next) {
