@@ -2,11 +2,15 @@
 
     python -m paper_1411_5283_amd.profsum stats <kernel_stats.csv> "<command>" <out.txt>
     python -m paper_1411_5283_amd.profsum traffic <fetch.csv> <write.csv> <copy_fetch.csv> \
-        <copy_write.csv> <bench.json> <out.json>
+        <copy_write.csv> <bench.json> <out.json> [<text_fetch.csv> <text_write.csv>]
 
 ``traffic`` averages FETCH_SIZE and WRITE_SIZE (KiB per dispatch) per kernel
 family and scales them by what the same counters read for a plain 1 GiB
 device copy (hbm_copy_probe.py), so that the result is HBM bytes per launch.
+The sort's kernels come from a run without the text steps (a run that writes
+text also keeps the sorted keys in the last merge level, which changes that
+level's traffic); the text kernels, found only in the second pair, from a run
+with them.
 """
 from __future__ import annotations
 
@@ -19,8 +23,12 @@ import sys
 COPY_BYTES = 1 << 30
 COMMANDS = [
     "rocprofv3 --pmc FETCH_SIZE --output-format csv -d gpurun_out/pmc_fetch -o f -- python3 bench.py "
-    "--serial --steps 1 --warmup 1 --profile-steps 1 --no-plain --no-cpu-baseline --no-check",
+    "--serial --steps 1 --warmup 1 --profile-steps 1 --no-plain --no-cpu-baseline --no-check --no-text",
     "rocprofv3 --pmc WRITE_SIZE --output-format csv -d gpurun_out/pmc_write -o w -- python3 bench.py "
+    "--serial --steps 1 --warmup 1 --profile-steps 1 --no-plain --no-cpu-baseline --no-check --no-text",
+    "rocprofv3 --pmc FETCH_SIZE --output-format csv -d gpurun_out/pmc_fetch_t -o f -- python3 bench.py "
+    "--serial --steps 1 --warmup 1 --profile-steps 1 --no-plain --no-cpu-baseline --no-check",
+    "rocprofv3 --pmc WRITE_SIZE --output-format csv -d gpurun_out/pmc_write_t -o w -- python3 bench.py "
     "--serial --steps 1 --warmup 1 --profile-steps 1 --no-plain --no-cpu-baseline --no-check",
     "rocprofv3 --pmc FETCH_SIZE --output-format csv -d gpurun_out/pmc_copyf -o cf -- python3 "
     "paper_1411_5283_amd/hbm_copy_probe.py",
@@ -62,9 +70,18 @@ def _per_dispatch(path: str, counter: str) -> dict:
     return {k: (sum(v) / len(v), len(v)) for k, v in agg.items()}
 
 
-def traffic(fetch: str, write: str, cfetch: str, cwrite: str, bench_json: str, out: str) -> None:
+def traffic(fetch: str, write: str, cfetch: str, cwrite: str, bench_json: str, out: str,
+            text_fetch: str | None = None, text_write: str | None = None) -> None:
     f = _per_dispatch(fetch, "FETCH_SIZE")
     w = _per_dispatch(write, "WRITE_SIZE")
+    if text_fetch and text_write:
+        fams = {_family(k) for k in f}
+        tf = _per_dispatch(text_fetch, "FETCH_SIZE")
+        tw = _per_dispatch(text_write, "WRITE_SIZE")
+        for k, v in tf.items():
+            if _family(k) not in fams and k in tw:
+                f[k] = v
+                w[k] = tw[k]
     cf = _per_dispatch(cfetch, "FETCH_SIZE")["__amd_rocclr_copyBuffer"][0]
     cw = _per_dispatch(cwrite, "WRITE_SIZE")["__amd_rocclr_copyBuffer"][0]
     fs, wsc = COPY_BYTES / 1024 / cf, COPY_BYTES / 1024 / cw
@@ -91,6 +108,6 @@ if __name__ == "__main__":
     if sys.argv[1] == "stats":
         stats(*sys.argv[2:5])
     elif sys.argv[1] == "traffic":
-        traffic(*sys.argv[2:8])
+        traffic(*sys.argv[2:10])
     else:
         raise SystemExit(__doc__)
