@@ -12,7 +12,9 @@
 // there none", and three passes suffice: per-block summaries (letters, word
 // starts under either incoming state, outgoing state), one block scanning the
 // summaries, and a write pass that knows every thread's incoming state and
-// output positions.
+// output positions.  A thread classifies its 64 bytes four at a time into bit
+// masks (letters, whitespace), so counts are population counts and the word
+// starts one 64-bit addition.
 #pragma once
 
 #include "sw_device.hpp"
@@ -34,8 +36,6 @@ struct TokSum {
   uint32_t last;            // TS_*
 };
 
-__device__ inline bool tok_space(uint32_t c) { return c == 32u || (c - 9u) < 5u; }
-__device__ inline bool tok_letter(uint32_t c) { return ((c | 32u) - 97u) < 26u; }
 
 // The thread's bytes [p, p + cnt) as 16 dwords (little-endian byte order);
 // bytes past cnt read as 0, which is special and changes nothing.
@@ -58,24 +58,60 @@ __device__ inline void tok_load(const uint8_t* text, uint64_t p, uint32_t cnt, u
   for (uint32_t b = 0; b < cnt; ++b) w[b >> 2] |= (uint32_t)src[b] << (8 * (b & 3));
 }
 
-__device__ inline TokSum tok_summary(const uint32_t (&w)[16]) {
-  TokSum s{0, 0, 0, TS_NONE};
-  uint32_t cur = TS_NONE;
-  bool first_open = false;   // a letter met while the incoming state was still unknown
+// Four bytes at a time: bit 7 of each byte of the result flags a letter
+// (resp. whitespace).  Every byte is brought below 128 before adding, so no
+// sum carries into the next byte; bytes of 128 and above are neither.
+__device__ inline uint32_t swar_letters(uint32_t w) {
+  const uint32_t x = (w | 0x20202020u) & 0x7F7F7F7Fu;   // case folded
+  const uint32_t ge_a = x + 0x1F1F1F1Fu;                 // bit 7: byte >= 'a'
+  const uint32_t ge_brace = x + 0x05050505u;             // bit 7: byte >= '{'
+  return ge_a & ~ge_brace & ~w & 0x80808080u;
+}
+__device__ inline uint32_t swar_spaces(uint32_t w) {
+  const uint32_t y = w ^ 0x20202020u;                                      // zero where w is ' '
+  const uint32_t eq = ~(((y & 0x7F7F7F7Fu) + 0x7F7F7F7Fu) | y) & 0x80808080u;
+  const uint32_t x = w & 0x7F7F7F7Fu;
+  const uint32_t ge9 = x + 0x77777777u;                                    // bit 7: byte >= 9
+  const uint32_t ge14 = x + 0x72727272u;                                   // bit 7: byte >= 14
+  return eq | (ge9 & ~ge14 & ~w & 0x80808080u);
+}
+// bit 7 of each byte -> bits 0..3
+__device__ inline uint32_t swar_pack4(uint32_t f) {
+  f >>= 7;
+  return (f | (f >> 7) | (f >> 14) | (f >> 21)) & 0xFu;
+}
+
+// The thread's 64 bytes as bit masks (bit i: byte i), letters and whitespace.
+struct TokMasks {
+  uint64_t letter, space;
+};
+__device__ inline TokMasks tok_masks(const uint32_t (&w)[16]) {
+  TokMasks m{0, 0};
 #pragma unroll
-  for (int b = 0; b < kTokBytes; ++b) {
-    const uint32_t c = (w[b >> 2] >> (8 * (b & 3))) & 0xFFu;
-    if (tok_space(c)) {
-      cur = TS_SPACE;
-    } else if (tok_letter(c)) {
-      s.letters += 1;
-      if (cur == TS_SPACE) s.starts_letter += 1;
-      if (cur == TS_NONE) first_open = true;
-      cur = TS_LETTER;
-    }
+  for (int j = 0; j < 16; ++j) {
+    m.letter |= (uint64_t)swar_pack4(swar_letters(w[j])) << (4 * j);
+    m.space |= (uint64_t)swar_pack4(swar_spaces(w[j])) << (4 * j);
   }
-  s.starts_space = s.starts_letter + (first_open ? 1u : 0u);
-  s.last = cur;
+  return m;
+}
+
+// Word starts among the thread's bytes: a letter whose last non-special byte
+// before it is whitespace (or, for the first one, the incoming state when
+// `space_in`).  Adding 1 just above each space (and at bit 0 for space_in)
+// to the mask of special bytes carries through the specials that follow and
+// lands on the first non-special byte after them.
+__device__ inline uint64_t tok_starts(const TokMasks& m, bool space_in) {
+  const uint64_t special = ~(m.letter | m.space);
+  return ((special + (m.space << 1) + (space_in ? 1ull : 0ull)) & ~special) & m.letter;
+}
+
+__device__ inline TokSum tok_summary(const TokMasks& m) {
+  TokSum s;
+  s.letters = (uint32_t)__popcll(m.letter);
+  s.starts_letter = (uint32_t)__popcll(tok_starts(m, false));
+  s.starts_space = (uint32_t)__popcll(tok_starts(m, true));
+  const uint64_t ns = m.letter | m.space;
+  s.last = ns ? (((m.space >> (63 - __clzll(ns))) & 1ull) ? TS_SPACE : TS_LETTER) : TS_NONE;
   return s;
 }
 
@@ -124,7 +160,7 @@ __global__ __launch_bounds__(kTokNT) void k_tok_sum(const uint8_t* text, uint64_
   const uint32_t cnt = p < n ? (uint32_t)min<uint64_t>(kTokBytes, n - p) : 0u;
   uint32_t w[16];
   tok_load(text, p, cnt, w);
-  const TokSum s = tok_summary(w);
+  const TokSum s = tok_summary(tok_masks(w));
   const uint32_t carry = tok_carry_in_block<kTokNT>(s.last, s_last);
   // threads with no state before them inside the block depend on the block's
   // incoming state; the others are settled here
@@ -242,7 +278,8 @@ __global__ __launch_bounds__(kTokNT) void k_tok_write(Header* h, const uint8_t* 
   const uint32_t cnt = p < n ? (uint32_t)min<uint64_t>(kTokBytes, n - p) : 0u;
   uint32_t w[16];
   tok_load(text, p, cnt, w);
-  const TokSum s = tok_summary(w);
+  const TokMasks tm = tok_masks(w);
+  const TokSum s = tok_summary(tm);
   const uint4 bp = pre[b];
   uint32_t carry = tok_carry_in_block<kTokNT>(s.last, s_last);
   if (carry == TS_NONE) carry = bp.z;
@@ -251,17 +288,22 @@ __global__ __launch_bounds__(kTokNT) void k_tok_write(Header* h, const uint8_t* 
   const uint32_t lrel = block_excl_scan<kTokNT>(s.letters, s_tmp, nl);   // inside the workgroup
   uint32_t wpos = bp.y + block_excl_scan<kTokNT>(starts, s_tmp, nwd);
   const uint32_t head = (uint32_t)((uintptr_t)(out_chars + bp.x) & 3u);   // LDS byte of the stretch's first letter
-  const uint32_t fold = (flags & kTokFlagLower) ? 32u : 0u;
+  // a letter OR 0x20 is its lower case (lower case letters have the bit)
+  const uint32_t fold = (flags & kTokFlagLower) ? 0x20202020u : 0u;
+  const uint64_t st = tok_starts(tm, carry != TS_LETTER);
   uint32_t lpos = lrel;
-  uint32_t cur = carry;
-  for (uint32_t i = 0; i < cnt; ++i) {
-    const uint32_t c = (w[i >> 2] >> (8 * (i & 3))) & 0xFFu;
-    if (tok_space(c)) {
-      cur = TS_SPACE;
-    } else if (tok_letter(c)) {
-      if (cur != TS_LETTER) out_offsets[wpos++] = bp.x + lpos;
-      s_chr[head + lpos++] = (uint8_t)(c | (c < 97u ? fold : 0u));
-      cur = TS_LETTER;
+#pragma unroll
+  for (int j = 0; j < 16; ++j) {
+    const uint32_t lb = (uint32_t)(tm.letter >> (4 * j)) & 0xFu;
+    if (lb == 0) continue;
+    const uint32_t sb = (uint32_t)(st >> (4 * j)) & 0xFu;
+    const uint32_t v = w[j] | fold;
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+      if ((lb >> t) & 1u) {
+        if ((sb >> t) & 1u) out_offsets[wpos++] = bp.x + lpos;
+        s_chr[head + lpos++] = (uint8_t)(v >> (8 * t));
+      }
     }
   }
   __syncthreads();
