@@ -37,7 +37,7 @@ WORKLOADS = {
               "20k-word Zipf(1.0) vocabulary, lengths 1-20, 8 GiB HBM budget"),
 }
 CSRC = [os.path.join(ROOT, "paper_1411_5283_amd", "csrc", f)
-        for f in ("sw_device.hpp", "sw_kernels.hpp", "sw_text.hpp", "sw_runtime.hip")]
+        for f in ("sw_device.hpp", "sw_kernels.hpp", "sw_text.hpp", "sw_bytes.hpp", "sw_runtime.hip")]
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "hbm_traffic.json")
 
 
