@@ -1111,8 +1111,13 @@ __device__ inline TileIO tile_io(const TileRec& r, uint32_t end_split, uint64_t 
   io.apos = (size_t)r.base + m.ps + r.split;
   io.bpos = (size_t)r.base + m.ps + m.la + (m.d0 - r.split);
   io.ob = (size_t)r.base + m.o0;
-  io.na = (int)(a1 - r.split);
-  io.cnt = (int)(m.d1 - m.d0);
+  // A items [split, a1) and B items from d0 - split: both inside their runs
+  // whenever the two splits come from the same sorted pair, as they do.  The
+  // clamps only keep a tile's loads inside its runs should they not.
+  const int cnt = (int)(m.d1 - m.d0);
+  const int a_left = (int)m.la - (int)r.split, b_left = (int)m.lb - (int)(m.d0 - r.split);
+  io.na = min(max((int)a1 - (int)r.split, 0), min(cnt, max(a_left, 0)));
+  io.cnt = io.na + min(cnt - io.na, max(b_left, 0));
   io.final = levels_pow2(r.n, (uint32_t)__ffs(Tc) - 1) == (uint32_t)level + 1;
   return io;
 }

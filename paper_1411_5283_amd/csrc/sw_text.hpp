@@ -217,14 +217,15 @@ __device__ inline void lds_bytes_to_global(const uint8_t* src, uint32_t len, uin
 
 // Pass 3: every thread rescans its bytes.  Its letters go to LDS at their
 // places in the workgroup's stretch of chars (laid out on the output's dword
-// grid, so that the stretch is stored as whole dwords); the offsets of the
-// words that start among them go straight to memory (a thread's words are
-// consecutive there).
+// grid, so that the stretch is stored as whole dwords), and the offsets of
+// the words that start among them to the workgroup's run of offsets in LDS;
+// both are then stored in order.
 __global__ __launch_bounds__(kTokNT) void k_tok_write(Header* h, const uint8_t* text, uint64_t n, const uint4* pre,
                                                       uint32_t flags, uint8_t* out_chars, uint32_t* out_offsets) {
   __shared__ uint32_t s_last[kTokNT / 64];
   __shared__ uint32_t s_tmp[kTokNT / 64];
   __shared__ uint32_t s_chr32[kTokBlock / 4 + 2];
+  __shared__ uint32_t s_off[kTokBlock / 2];   // a word start needs a letter and a byte before it
   if (h->abort) return;
   uint8_t* s_chr = (uint8_t*)s_chr32;
   const uint64_t b = blockIdx.x;
@@ -240,7 +241,7 @@ __global__ __launch_bounds__(kTokNT) void k_tok_write(Header* h, const uint8_t* 
   const uint32_t starts = carry == TS_LETTER ? s.starts_letter : s.starts_space;
   uint32_t nl, nwd;
   const uint32_t lrel = block_excl_scan<kTokNT>(s.letters, s_tmp, nl);   // inside the workgroup
-  uint32_t wpos = bp.y + block_excl_scan<kTokNT>(starts, s_tmp, nwd);
+  uint32_t wpos = block_excl_scan<kTokNT>(starts, s_tmp, nwd);   // inside the workgroup
   const uint32_t head = (uint32_t)((uintptr_t)(out_chars + bp.x) & 3u);   // LDS byte of the stretch's first letter
   // a letter OR 0x20 is its lower case (lower case letters have the bit)
   const uint32_t fold = (flags & kTokFlagLower) ? 0x20202020u : 0u;
@@ -255,12 +256,13 @@ __global__ __launch_bounds__(kTokNT) void k_tok_write(Header* h, const uint8_t* 
 #pragma unroll
     for (int t = 0; t < 4; ++t) {
       if ((lb >> t) & 1u) {
-        if ((sb >> t) & 1u) out_offsets[wpos++] = bp.x + lpos;
+        if ((sb >> t) & 1u) s_off[wpos++] = bp.x + lpos;
         s_chr[head + lpos++] = (uint8_t)(v >> (8 * t));
       }
     }
   }
   __syncthreads();
+  for (uint32_t k = threadIdx.x; k < nwd; k += kTokNT) out_offsets[bp.y + k] = s_off[k];
   // the stretch [head, head + nl) of LDS to out_chars + bp.x: edge bytes one
   // by one, whole dwords in between (LDS dword k is output dword k)
   uint8_t* dst = out_chars + bp.x - head;
