@@ -680,27 +680,6 @@ __device__ inline int run_merge_path_steps(const RA& A, int la, const RB& B, int
   return lo;
 }
 
-// E outputs of the merge starting at A[ai], B[bi], one after another.  An
-// exhausted side shows the sentinel, which no real key reaches, so the next
-// output is always the smaller head; one load per output refills the side
-// that was taken.
-template <class K, int E, class RA, class RB>
-__device__ inline void run_serial_merge(const RA& A, int la, const RB& B, int lb, int ai, int bi, K (&out)[E]) {
-  K ha = ai < la ? A(ai) : e_sentinel<K>();
-  K hb = bi < lb ? B(bi) : e_sentinel<K>();
-#pragma unroll
-  for (int j = 0; j < E; ++j) {
-    const bool takeB = e_less(hb, ha);
-    out[j] = e_select(takeB, hb, ha);
-    const int ni = takeB ? ++bi : ++ai;
-    const int lim = takeB ? lb : la;
-    K nv = e_sentinel<K>();
-    if (ni < lim) nv = takeB ? B(ni) : A(ni);
-    ha = e_select(takeB, ha, nv);
-    hb = e_select(takeB, nv, hb);
-  }
-}
-
 // The E smallest items of A[ai..ai+E) and B[bi..bi+E), in order, into
 // registers: the candidates are loaded independently (no dependent load
 // chain), min(x[i], y[E-1-i]) keeps the E smallest as a bitonic sequence
@@ -725,24 +704,15 @@ __device__ inline void run_bitonic_merge(const RA& A, int la, const RB& B, int l
   }
 }
 
+// Merge path over two runs held contiguously in LDS.
 template <class Tile>
 __device__ inline int lds_merge_path(const Tile& t, int a0, int la, int b0, int lb, int d) {
   return run_merge_path(LinRun<Tile>{t, a0}, la, LinRun<Tile>{t, b0}, lb, d);
 }
 
-// E merged outputs into registers: MM = 0 serial merge, MM = 1 bitonic merge.
-template <int E, int MM, class Tile>
-__device__ inline void lds_register_merge(const Tile& t, int a0, int la, int b0, int lb, int ai, int bi,
-                                          typename Tile::value_type (&out)[E]) {
-  if (MM == 0)
-    run_serial_merge(LinRun<Tile>{t, a0}, la, LinRun<Tile>{t, b0}, lb, ai, bi, out);
-  else
-    run_bitonic_merge(LinRun<Tile>{t, a0}, la, LinRun<Tile>{t, b0}, lb, ai, bi, out);
-}
-
-// The same two steps on a merge tile laid out with sentinels: run A at
-// [0, la), a sentinel at la, run B at [la+1, la+1+lb), a sentinel after it,
-// and at least E more readable slots.  Reads past both sentinels only feed
+// The diagonal search and the E outputs on a merge tile laid out with
+// sentinels: run A at [0, la), a sentinel at la, run B at [la+1, la+1+lb), a
+// sentinel after it, and at least E more readable slots.  Reads past both sentinels only feed
 // outputs beyond the tile's count, which are never stored, so the serial
 // merge needs no clamping.
 template <class Tile>
@@ -825,37 +795,9 @@ __device__ inline void sort_tile_core(Tile& tile, typename Tile::value_type (&e)
   }
 }
 
-// Merge path on the diagonal d over global memory, by one wave: 64 probes per
-// round.
-template <int NL>
-__device__ inline uint32_t wave_merge_path(const KeyBuf& buf, size_t a_base, uint32_t la, size_t b_base,
-                                           uint32_t lb, uint32_t d) {
-  const uint32_t lane = __lane_id();
-  uint32_t lo = d > lb ? d - lb : 0u;
-  uint32_t hi = d < la ? d : la;
-  while (lo < hi) {
-    const uint32_t step = (hi - lo + 63) >> 6;
-    const uint32_t a = lo + lane * step;
-    bool p = false;
-    if (a < hi) {
-      const Key<NL> A = gload<NL>(buf, a_base + a);
-      const Key<NL> B = gload<NL>(buf, b_base + (d - 1 - a));
-      p = !key_less<NL>(B, A);
-    }
-    const uint32_t c = __popcll(__ballot(p));
-    if (c == 0) {
-      hi = lo;
-    } else {
-      const uint32_t nlo = lo + (c - 1) * step + 1;
-      hi = min(lo + c * step, hi);
-      lo = nlo;
-    }
-  }
-  return lo;
-}
-
-// The same search by groups of K lanes (K divides 64): each group finds the
-// split of its own diagonal, K probes per round.  Fewer probes per round
+// Merge path on a diagonal over global memory, by groups of K lanes (K
+// divides 64): each group finds the split of its own diagonal, K probes per
+// round.  Fewer probes per round
 // touch fewer cache lines; more rounds cost latency.
 template <int NL, int K>
 __device__ inline uint32_t group_merge_path(const KeyBuf& buf, size_t a_base, uint32_t la, size_t b_base,
