@@ -475,8 +475,8 @@ def main():
     ap.add_argument("--serve-python", action="store_true", help="the Python scheduler instead of the native loop")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py: this build runs on one GPU only; --gpus %d is not supported "
-              "(see DESIGN.md for how the sort would shard)" % args.gpus, file=sys.stderr)
+        print("bench.py: the library runs on one GPU; --gpus %d is not supported (sharding across "
+              "GPUs is a design, not code)" % args.gpus, file=sys.stderr)
         sys.exit(2)
 
     import torch
