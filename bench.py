@@ -169,10 +169,10 @@ def cpu_baseline(wl, budget_s: float = 12.0) -> dict:
     return res
 
 
-def hbm_traffic(dominant_kernel: str, workload: str):
+def hbm_traffic(dominant_kernel: str, workload: str, tiles: dict):
     """HBM bytes per launch of a kernel family from the committed rocprofv3
-    counter summary, if it was taken on the current kernel source and on the
-    same workload."""
+    counter summary, if it was taken on the current kernel source, on the
+    same workload and with the same tile configuration."""
     try:
         with open(TRAFFIC_FILE) as f:
             t = json.load(f)
@@ -181,6 +181,8 @@ def hbm_traffic(dominant_kernel: str, workload: str):
     if t.get("source_hash") != kernel_source_hash():
         return None
     if t.get("workload", "").split(":")[0].strip() != workload:
+        return None
+    if t.get("tiles") != tiles:
         return None
     k = t.get("kernels", {}).get(dominant_kernel)
     return None if k is None else k.get("bytes_per_launch")
@@ -338,7 +340,7 @@ def serve_python(args, sw, reqs, warm, meas):
 
 
 def text_bench(args, sw, wordgen, torch, wl, chars, offs, docs, perm, boff, perm_h, boff_h, stream, plan,
-               plan_ms):
+               plan_ms, tile_cfg):
     """The steps around the sort on the same workload: the word list written as
     raw text (capitals, punctuation, line breaks) is tokenized back on the GPU
     (lower-case folding), and the sorted result is written out as text with a
@@ -432,16 +434,16 @@ def text_bench(args, sw, wordgen, torch, wl, chars, offs, docs, perm, boff, perm
     return {
         "tokenize": {"ms": tok_ms, "text_bytes": nb, "words": nw, "Mwords_per_s": nw / (tok_ms / 1e3) / 1e6,
                      "algorithmic_GBs": tok_bytes / (tok_ms / 1e3) / 1e9, "same_as_word_list": tok_ok,
-                     "traffic_bytes": {k: hbm_traffic(k, args.workload) for k in ("tok_sum", "tok_scan", "tok_write")},
+                     "traffic_bytes": {k: hbm_traffic(k, args.workload, tile_cfg) for k in ("tok_sum", "tok_scan", "tok_write")},
                      "input": "the word list rendered as text: capitals, punctuation, line breaks, digits"},
         "materialize": {"ms": mat_ms, "text_bytes": size, "Mwords_per_s": n / (mat_ms / 1e3) / 1e6,
                         "algorithmic_GBs": mat_bytes / (mat_ms / 1e3) / 1e9, "status": status,
-                        "traffic_bytes": hbm_traffic("materialize", args.workload),
+                        "traffic_bytes": hbm_traffic("materialize", args.workload, tile_cfg),
                         "sampled_check": bool(mat_ok), "separator": "line feed"},
         "sort_and_text": {"ms": st_ms, "sort_alone_ms": plan_ms, "text_ms": st_ms - plan_ms,
                           "Mwords_per_s": n / (st_ms / 1e3) / 1e6, "status": st_status,
                           "same_text_as_materialize": st_same,
-                          "traffic_bytes": hbm_traffic("keys_text", args.workload),
+                          "traffic_bytes": hbm_traffic("keys_text", args.workload, tile_cfg),
                           "form": "sw_plan_run_text: the sort's graph plus the text written from the sorted "
                                   "keys (each segment's last level also keeps its keys)"},
     }
@@ -502,6 +504,7 @@ def main():
         sw.set_config(flags=sw.FLAG_SERIAL_CLASSES)
     cfg = sw.get_config()
     tiles = [sw.variant_tiles(c, cfg["variant"][c])[0] for c in range(4)]
+    tile_cfg = {"chunk": list(cfg["chunk"]), "variant": list(cfg["variant"])}
 
     torch.cuda.set_device(0)
     dev = torch.device("cuda:0")
@@ -634,7 +637,7 @@ def main():
     achieved = kern[dom].get("algorithmic_GBs")
     tsum = sum(v["ms_per_step"] for v in kern.values())
     total_bytes = sum(fam_bytes.values())
-    traffic = hbm_traffic(dom, args.workload)
+    traffic = hbm_traffic(dom, args.workload, tile_cfg)
     roof = {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": (achieved / HBM_PEAK_GBS) if achieved else None,
             "traffic": traffic,
@@ -646,7 +649,7 @@ def main():
             "eager_kernel_sum_ms": tsum}
 
     text = None if args.no_text else text_bench(args, sw, wordgen, torch, wl, chars, offs, docs, perm, boff,
-                                                   perm_h, boff_h, stream, plan, ms_step)
+                                                   perm_h, boff_h, stream, plan, ms_step, tile_cfg)
     cpu = None if args.no_cpu_baseline else cpu_baseline(wl)
     out = {
         "metric": METRIC, "value": value, "unit": "Mwords/s", "n_gpus": 1, "steps": args.steps,

@@ -96,6 +96,7 @@ def traffic(fetch: str, write: str, cfetch: str, cwrite: str, bench_json: str, o
         kern[fam] = {"kernel": k, "dispatches": nd, "fetch_kib_per_dispatch": fk, "write_kib_per_dispatch": wk,
                      "bytes_per_launch": fk * 1024 * fs + wk * 1024 * wsc}
     res = {"source_hash": b["kernel_source"], "workload": b["config"]["workload"] + " (bench.py --serial)",
+           "tiles": {"chunk": b["config"].get("chunk"), "variant": b["config"].get("variant")},
            "fetch_scale": fs, "write_scale": wsc,
            "calibration": "plain device copy of 1 GiB (__amd_rocclr_copyBuffer): FETCH_SIZE %.0f KiB, "
                           "WRITE_SIZE %.0f KiB per dispatch" % (cf, cw),

@@ -203,6 +203,7 @@ def main():
     ap.add_argument("--out", default=CACHE)
     ap.add_argument("--plan-only", action="store_true",
                     help="only the second stage, starting from the cached configuration")
+    ap.add_argument("--plan-rounds", type=int, default=3, help="interleaved timing rounds per variant")
     args = ap.parse_args()
     from . import wordgen
     cfg = int(args.workload.lstrip("c"))
@@ -215,7 +216,7 @@ def main():
             raise SystemExit("no cached configuration for %s" % args.workload)
     else:
         res = tune(wl, args.workload, reps=args.reps, log=say)
-    res.update(refine_on_plan(wl, res["config"], log=say))
+    res.update(refine_on_plan(wl, res["config"], rounds=args.plan_rounds, log=say))
     save(res, args.out)
     print(json.dumps({"workload": res["workload"], "config": res["config"], "kernel_ms": res["kernel_ms"],
                       "plan_ms": res["plan_ms"]}), flush=True)
