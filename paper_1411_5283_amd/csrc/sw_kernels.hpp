@@ -1034,9 +1034,11 @@ struct TileRec {
 };
 
 // Merge tiles are placed by groups of kPartLanes lanes (kPartLanes probes per
-// round of the merge-path search): fewer lanes touch fewer cache lines per
-// round, more lanes need fewer rounds.
-constexpr int kPartLanes = 16;
+// round of the merge-path search): fewer lanes touch fewer cache lines in
+// all (a probe is a cache line until the last rounds), more lanes need fewer
+// rounds.  The rounds' latency hides behind the other classes' kernels, so
+// 8 lanes beat 16 (and 16 beat 32 and 64).
+constexpr int kPartLanes = 8;
 
 // Where a merge tile reads and writes, from its placement and the split at
 // its last output.
@@ -1096,7 +1098,7 @@ template <int NL, int NT>
 __device__ inline void place_tiles(const Ws& w, int cls, int level, const TileWork& tw, uint32_t P, uint32_t ntiles,
                                    uint32_t t0, uint32_t t_end, TileRec* s_rec, uint32_t* s_split) {
   constexpr int NG = NT / kPartLanes;
-  static_assert(NG >= 2 && NG <= 16, "groups of kPartLanes lanes");
+  static_assert(NG >= 2 && NG <= 64, "groups of kPartLanes lanes");
   Header* h = w.h;
   const uint64_t R = (uint64_t)w.T[cls] << level;
   const uint32_t lane = __lane_id();
