@@ -1,7 +1,9 @@
-// sw_bytes.hpp -- the tokenizer's byte classes as bit masks, four bytes at
-// a time (plain integer code, also built for the host by its test).  A
-// letter is an ASCII letter; whitespace is tab, line feed, vertical tab, form
-// feed, carriage return or space; every other byte is special.
+// sw_bytes.hpp -- byte-level helpers of the text kernels as plain integer
+// code, also built for the host by their tests: the tokenizer's byte classes
+// as bit masks, four bytes at a time (a letter is an ASCII letter;
+// whitespace is tab, line feed, vertical tab, form feed, carriage return or
+// space; every other byte is special), and the stores that write a word's
+// text from its key lanes a dword at a time.
 #pragma once
 
 #include <cstdint>
@@ -53,6 +55,61 @@ __host__ __device__ inline TokMasks tok_masks(const uint32_t (&w)[16]) {
 __host__ __device__ inline uint64_t tok_starts(const TokMasks& m, bool space_in) {
   const uint64_t special = ~(m.letter | m.space);
   return ((special + (m.space << 1) + (space_in ? 1ull : 0ull)) & ~special) & m.letter;
+}
+
+// A word's text from its key lanes: its L bytes (big-endian lanes ln[0..3],
+// byte j at bits 63-8(j%8) of lane j/8; whatever the lanes hold past the
+// word is masked off), then the separator when sw = 1.  The word starts at
+// byte o (0..3) of the aligned destination dst; output dword k covers word
+// bytes 4k-o .. 4k-o+3, built from two consecutive dwords of the word with
+// one funnel shift.  Dwords wholly inside the word are stored whole, the
+// word's first and last dwords (shared with its neighbours) byte- and
+// halfword-wise, so that words written by different threads never overlap.
+__host__ __device__ inline void store_part(uint8_t* dst, uint32_t v, uint32_t fb, uint32_t lb) {
+  // bytes [fb, lb) of v to dst[fb..lb): a byte to reach an even address, then
+  // a halfword, then a last byte
+  uint32_t p = fb;
+  if ((p & 1u) && p < lb) {
+    dst[p] = (uint8_t)(v >> (8 * p));
+    ++p;
+  }
+  if (p + 2 <= lb) {
+    *(uint16_t*)(dst + p) = (uint16_t)(v >> (8 * p));
+    p += 2;
+  }
+  if (p < lb) dst[p] = (uint8_t)(v >> (8 * p));
+}
+
+template <class P>
+__host__ __device__ inline void put_word_text(P dst, uint32_t o, const uint64_t (&ln)[4], uint32_t L, uint32_t sw,
+                                              uint32_t sep) {
+  const uint32_t n = L + sw;
+  if (n == 0) return;
+  const uint32_t K = (o + n - 1) >> 2;           // last output dword
+  const uint32_t last = ((o + n - 1) & 3u) + 1;  // bytes of it that are the word's
+  const uint32_t ks = (o + L) >> 2, sepv = (sep & 255u) << (8 * ((o + L) & 3u));
+  uint32_t W[9];   // word bytes 4i..4i+3, little-endian
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    W[2 * i] = __builtin_bswap32((uint32_t)(ln[i] >> 32));
+    W[2 * i + 1] = __builtin_bswap32((uint32_t)ln[i]);
+  }
+  W[8] = 0;
+#pragma unroll
+  for (uint32_t k = 0; k < 9; ++k) {
+    if (k <= K) {
+      const uint64_t two = ((uint64_t)W[k] << 32) | (k ? W[k - 1] : 0u);
+      uint32_t v = (uint32_t)(two >> (32 - 8 * o));
+      const int keep = (int)(L + o) - 4 * (int)k;   // output bytes of this dword below the word's end
+      v &= keep >= 4 ? ~0u : (keep <= 0 ? 0u : (1u << (8 * keep)) - 1u);
+      if (sw && k == ks) v |= sepv;
+      const uint32_t fb = k == 0 ? o : 0u, lb = k == K ? last : 4u;
+      if (fb == 0 && lb == 4)
+        *(uint32_t*)(dst + 4 * k) = v;
+      else
+        store_part((uint8_t*)(dst + 4 * k), v, fb, lb);
+    }
+  }
 }
 
 }  // namespace sw

@@ -446,8 +446,9 @@ __global__ __launch_bounds__(NT) void k_materialize(const uint8_t* chars, const 
 // segment and its first byte in the text.  Then tile by tile the workgroup
 // cuts the tile into the pieces of the segments it covers, assembles the
 // text of its words in LDS -- each word followed by the separator when there
-// is one, laid out on the output's dword grid -- and stores it as one
-// stretch (a tile whose text outgrows the LDS stretch, KTB bytes per word
+// is one, laid out on the output's dword grid, the dwords wholly inside a
+// word written whole and only its edges by byte and halfword -- and stores
+// it as one stretch (a tile whose text outgrows the LDS stretch, KTB bytes per word
 // on average, writes its words straight to memory instead).  The layout is
 // the permutation-based writer's: document d's text
 // starts at byte (offsets[first word of d] - offsets[0]) + (first word of d)
@@ -483,9 +484,12 @@ __device__ inline TextAt text_at(const Ws& w, const RunDesc& d, uint32_t D, uint
   return TextAt{lo * kNB + L, pos + (uint64_t)(g - sb[L]) * (L + sw)};
 }
 
+constexpr uint32_t kTextDwordMin = 12;   // words of this many text bytes or more are written by dwords
+
 // The L bytes of a word from its big-endian key lanes, then the separator
-// when there is one (sw = 1).  Called with an LDS or a global destination, so
-// that each gets its own stores.
+// when there is one (sw = 1), one byte at a time: for short words, whose
+// dword writer would mostly make partial stores at both edges.  Called with
+// an LDS or a global destination, so that each gets its own stores.
 template <class P>
 __device__ inline void put_word_bytes(P dst, const uint64_t (&ln)[4], uint32_t L, uint32_t sw, uint8_t sep) {
   uint64_t cur = ln[0];
@@ -598,7 +602,7 @@ __global__ __launch_bounds__(NT) void k_keys_text(Ws w) {
           const size_t g = (size_t)g0 + i;
           wl[r] = L;
           wrel[r] = s_rel[lo] + (i - s_first[lo]) * (L + sw);
-          ln[r][0] = (inb ? w.b.k[0] : w.a.k[0])[g];   // class 0 keeps its 4 key bytes in the high half
+          ln[r][0] = (inb ? w.b.k[0] : w.a.k[0])[g];   // class 0: its index in the low half is masked off
           if (L > 8) ln[r][1] = (inb ? w.b.k[1] : w.a.k[1])[g];
           if (L > 16) {
             ln[r][2] = (inb ? w.b.k[2] : w.a.k[2])[g];
@@ -610,8 +614,13 @@ __global__ __launch_bounds__(NT) void k_keys_text(Ws w) {
       for (int r = 0; r < IPT; ++r) {
         const uint32_t L = wl[r], rel = wrel[r];
         if (threadIdx.x + (uint32_t)r * NT < g1 - g0) {
-          if (staged)
+          const bool dw = L + sw >= kTextDwordMin;
+          if (staged && dw)
+            put_word_text(s_txt + (rel & ~3u), rel & 3u, ln[r], L, sw, (uint32_t)d.sep);
+          else if (staged)
             put_word_bytes(s_txt + rel, ln[r], L, sw, (uint8_t)d.sep);
+          else if (dw)
+            put_word_text(out + (rel & ~3u), rel & 3u, ln[r], L, sw, (uint32_t)d.sep);
           else
             put_word_bytes(out + rel, ln[r], L, sw, (uint8_t)d.sep);
         }
