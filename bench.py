@@ -501,7 +501,7 @@ def main():
         from paper_1411_5283_amd import tune
         tuned = tune.apply(args.workload)
     if args.serial:
-        sw.set_config(flags=sw.FLAG_SERIAL_CLASSES)
+        sw.set_config(flags=sw.get_config()["flags"] | sw.FLAG_SERIAL_CLASSES)
     cfg = sw.get_config()
     tiles = [sw.variant_tiles(c, cfg["variant"][c])[0] for c in range(4)]
     tile_cfg = {"chunk": list(cfg["chunk"]), "variant": list(cfg["variant"])}
@@ -658,7 +658,9 @@ def main():
         "config": {"workload": "%s: %s" % (args.workload, desc), "n_words": n, "n_docs": nd,
                    "form": "graph-captured plan (batched, device-side segment scheduling)",
                    "chunk": cfg["chunk"], "variant": cfg["variant"], "sort_tile": tiles,
-                   "tuned": tuned is not None, "classes": "serial" if args.serial else "parallel streams"},
+                   "tuned": tuned is not None, "classes": "serial" if args.serial else "parallel streams",
+                   "short_segments": "before the chunk sort" if cfg["flags"] & sw.FLAG_PACKED_FIRST
+                   else "after the chunk sort"},
         "eager_ms_per_step": eager_ms,
         "per_bucket_launch": plain,
         "batched_over_plain": (value / plain["value"]) if plain else None,

@@ -188,6 +188,12 @@ typedef struct {
 /* Run the key classes one after another on the caller's stream instead of on
  * parallel streams (for per-kernel measurement; results are identical). */
 #define SW_FLAG_SERIAL_CLASSES 1u
+/* Enqueue each key class's short-segment sort (segments of at most 1024
+ * words, several to a tile) before the class's chunk sort instead of after
+ * it.  Results are identical; which order is faster depends on the workload
+ * (measured: first is faster for thousands of small documents, after for one
+ * large one), so the autotuner chooses it per workload. */
+#define SW_FLAG_PACKED_FIRST 2u
 int sw_get_config(sw_config *out);
 int sw_set_config(const sw_config *cfg);
 /* Number of compiled variants of class c, and the chunk-sort tile (words per

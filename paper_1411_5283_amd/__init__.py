@@ -36,6 +36,7 @@ class SortWordsError(RuntimeError):
 
 
 FLAG_SERIAL_CLASSES = 1
+FLAG_PACKED_FIRST = 2
 
 
 class sw_config(ctypes.Structure):

@@ -440,13 +440,17 @@ int enqueue_body(const Ws& w, const Grids& g, hipStream_t s, bool capture, bool 
   int max_levels = 0;
   for (int c = 0; c < sw::kNClass; ++c) {
     hipStream_t cs = cstream(c);
-    {
-      ProfScope p(K_SORT0 + c, cs, capture);
-      g.var[c]->sort(w, c, none, g.sort[c], cs);
-    }
-    {
-      ProfScope p(K_PACK0 + c, cs, capture);
-      g.var[c]->packed(w, c, g.packed, cs);
+    // the short segments are disjoint from the chunk-sorted ones, so the two
+    // kernels may go in either order (which is faster depends on the workload)
+    const bool packed_first = (g.flags & SW_FLAG_PACKED_FIRST) != 0;
+    for (int step = 0; step < 2; ++step) {
+      if ((step == 0) == packed_first) {
+        ProfScope p(K_PACK0 + c, cs, capture);
+        g.var[c]->packed(w, c, g.packed, cs);
+      } else {
+        ProfScope p(K_SORT0 + c, cs, capture);
+        g.var[c]->sort(w, c, none, g.sort[c], cs);
+      }
     }
     max_levels = std::max(max_levels, g.levels[c]);
   }
@@ -851,7 +855,8 @@ int sw_set_config(const sw_config* cfg) {
     if (cfg->variant[c] >= (uint32_t)nv)
       return fail(SW_ERR_INVALID_ARG, "sw_set_config: variant[%d]=%u out of range", c, cfg->variant[c]);
   }
-  if (cfg->flags & ~SW_FLAG_SERIAL_CLASSES) return fail(SW_ERR_INVALID_ARG, "sw_set_config: unknown flags");
+  if (cfg->flags & ~(SW_FLAG_SERIAL_CLASSES | SW_FLAG_PACKED_FIRST))
+    return fail(SW_ERR_INVALID_ARG, "sw_set_config: unknown flags");
   std::lock_guard<std::mutex> lk(g_cfg_mu);
   g_cfg = *cfg;
   return SW_OK;

@@ -128,8 +128,10 @@ def _plan_ms(sw, torch, cfg, words, ref, runs: int = 10) -> float:
         plan.close()
 
 
-def refine_on_plan(wl, cfg: dict, rounds: int = 3, log=print) -> dict:
-    """Second stage: per class, the variant with the lowest median plan time."""
+def refine_on_plan(wl, cfg: dict, rounds: int = 3, log=print, variants: bool = True) -> dict:
+    """Second stage: per class, the variant with the lowest median plan time;
+    then whether each class's short-segment sort goes before its chunk sort
+    (FLAG_PACKED_FIRST).  With variants=False only the order is timed."""
     import torch
     import paper_1411_5283_amd as sw
 
@@ -141,7 +143,7 @@ def refine_on_plan(wl, cfg: dict, rounds: int = 3, log=print) -> dict:
     perm = torch.empty(max(n, 1), dtype=torch.int32, device=dev)
     boff = torch.empty(nd * 34, dtype=torch.int32, device=dev)
     words = (chars, offs, docs, n, nd, perm, boff, stream)
-    best = {"chunk": list(cfg["chunk"]), "variant": list(cfg["variant"])}
+    best = {"chunk": list(cfg["chunk"]), "variant": list(cfg["variant"]), "flags": int(cfg.get("flags", 0))}
     sw.set_config(**best)
     plan = sw.Plan(n, nd, stream=stream)
     plan.run(chars, offs, docs, nd, n, perm, boff)
@@ -149,11 +151,11 @@ def refine_on_plan(wl, cfg: dict, rounds: int = 3, log=print) -> dict:
     plan.close()
     ref = (perm.clone(), boff.clone())
     trials = []
-    for c in range(NUM_CLASSES):
+    for c in range(NUM_CLASSES if variants else 0):
         times = {v: [] for v in range(sw.num_variants(c))}
         for _ in range(rounds):
             for v in times:
-                trial = {"chunk": list(best["chunk"]), "variant": list(best["variant"])}
+                trial = dict(best, variant=list(best["variant"]))
                 trial["variant"][c] = v
                 times[v].append(_plan_ms(sw, torch, trial, words, ref))
         med = {v: float(np.median(t)) for v, t in times.items()}
@@ -163,9 +165,23 @@ def refine_on_plan(wl, cfg: dict, rounds: int = 3, log=print) -> dict:
         bv = min(med, key=med.get)
         if med[bv] < 0.995 * med[best["variant"][c]]:
             best["variant"][c] = bv
+    times = {f: [] for f in (0, sw.FLAG_PACKED_FIRST)}
+    for _ in range(rounds):
+        for f in times:
+            times[f].append(_plan_ms(sw, torch, dict(best, flags=f), words, ref))
+    med = {f: float(np.median(t)) for f, t in times.items()}
+    flag_trials = [{"flags": f, "plan_ms": m} for f, m in med.items()]
+    for f, m in med.items():
+        log("plan: flags %d: %.4f ms (median of %d)" % (f, m, rounds))
+    bf = min(med, key=med.get)
+    if med[bf] < 0.995 * med[best["flags"]]:
+        best["flags"] = bf
     sw.set_config(**best)
     final = float(np.median([_plan_ms(sw, torch, best, words, ref) for _ in range(rounds)]))
-    return {"config": best, "plan_ms": final, "plan_trials": trials}
+    out = {"config": best, "plan_ms": final, "flag_trials": flag_trials}
+    if variants:
+        out["plan_trials"] = trials
+    return out
 
 
 def load_cache(path: str = CACHE) -> dict:
@@ -192,7 +208,7 @@ def apply(workload: str, path: str = CACHE) -> dict | None:
     if not entry:
         return None
     cfg = entry["config"]
-    return sw.set_config(chunk=cfg["chunk"], variant=cfg["variant"])
+    return sw.set_config(chunk=cfg["chunk"], variant=cfg["variant"], flags=int(cfg.get("flags", 0)))
 
 
 def main():
@@ -204,6 +220,8 @@ def main():
     ap.add_argument("--plan-only", action="store_true",
                     help="only the second stage, starting from the cached configuration")
     ap.add_argument("--plan-rounds", type=int, default=3, help="interleaved timing rounds per variant")
+    ap.add_argument("--order-only", action="store_true",
+                    help="with --plan-only: keep the cached variants, time only the short-segment order")
     args = ap.parse_args()
     from . import wordgen
     cfg = int(args.workload.lstrip("c"))
@@ -216,7 +234,8 @@ def main():
             raise SystemExit("no cached configuration for %s" % args.workload)
     else:
         res = tune(wl, args.workload, reps=args.reps, log=say)
-    res.update(refine_on_plan(wl, res["config"], rounds=args.plan_rounds, log=say))
+    res.update(refine_on_plan(wl, res["config"], rounds=args.plan_rounds, log=say,
+                              variants=not (args.plan_only and args.order_only)))
     save(res, args.out)
     print(json.dumps({"workload": res["workload"], "config": res["config"], "kernel_ms": res["kernel_ms"],
                       "plan_ms": res["plan_ms"]}), flush=True)

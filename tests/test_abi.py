@@ -58,6 +58,14 @@ def test_host_side_calls_without_gpu():
     for k in range(4):
         bad.chunk[k] = 48            # not a power of two
     assert L.sw_set_config(ctypes.byref(bad)) == sw.ERR_INVALID_ARG
+    flagged = sw.sw_config()
+    ctypes.memmove(ctypes.byref(flagged), ctypes.byref(cfg), ctypes.sizeof(cfg))
+    flagged.flags = 4                # no such flag
+    assert L.sw_set_config(ctypes.byref(flagged)) == sw.ERR_INVALID_ARG
+    flagged.flags = sw.FLAG_SERIAL_CLASSES | sw.FLAG_PACKED_FIRST
+    assert L.sw_set_config(ctypes.byref(flagged)) == 0
+    assert sw.get_config()["flags"] == 3
+    assert L.sw_set_config(ctypes.byref(cfg)) == 0
     assert sw.num_variants(0) >= 1 and sw.num_variants(7) == 0
     t, p = sw.variant_tiles(0, 0)
     assert t >= 1024 and p >= 1024 and (t & (t - 1)) == 0

@@ -249,3 +249,31 @@ def test_packed_short_segments(gpu, oracle_mod):
     wl = wordgen.concat_docs(docs)
     _say("case packed segments docs=%d n=%d" % (wl.n_docs, wl.n))
     _same(gpu.sort_wordlist(wl), _expect(oracle_mod, wl, bubble=False), "packed")
+
+
+@pytest.mark.parametrize("flags", [0, 2])
+def test_short_segment_order_flag(gpu, oracle_mod, default_config, flags):
+    # the short-segment sort enqueued after (0) or before (FLAG_PACKED_FIRST)
+    # each class's chunk sort: the same result, eager and replayed in a plan
+    import torch
+    docs = [wordgen.config(1, 0.1), _doc_with_segment_sizes([1023, 1024, 1025, 5, 2048], seed=4)]
+    docs += [_doc_with_segment_sizes([1, 0, 1, 3], seed=20 + d) for d in range(300)]
+    docs += [wordgen.config(2, 0.05)]
+    wl = wordgen.concat_docs(docs)
+    _say("case short-segment order flags=%d docs=%d n=%d" % (flags, wl.n_docs, wl.n))
+    assert gpu.FLAG_PACKED_FIRST == 2
+    gpu.set_config(flags=flags)
+    exp = _expect(oracle_mod, wl, bubble=False)
+    _same(gpu.sort_wordlist(wl), exp, "flags %d eager" % flags)
+    chars, offs, ddocs = gpu.device_words(wl)
+    perm = torch.empty(wl.n, dtype=torch.int32, device="cuda")
+    boff = torch.empty(wl.n_docs * 34, dtype=torch.int32, device="cuda")
+    plan = gpu.Plan(wl.n, wl.n_docs)
+    try:
+        for rep in range(2):
+            plan.run(chars, offs, ddocs, wl.n_docs, wl.n, perm, boff)
+            plan.status()
+            _same((gpu.to_u32(perm), gpu.to_u32(boff).reshape(wl.n_docs, 34)), exp,
+                  "flags %d plan replay %d" % (flags, rep))
+    finally:
+        plan.close()
