@@ -660,7 +660,9 @@ def main():
                    "chunk": cfg["chunk"], "variant": cfg["variant"], "sort_tile": tiles,
                    "tuned": tuned is not None, "classes": "serial" if args.serial else "parallel streams",
                    "short_segments": "before the chunk sort" if cfg["flags"] & sw.FLAG_PACKED_FIRST
-                   else "after the chunk sort"},
+                   else "after the chunk sort",
+                   "segment_scheduling": "beside the scatter" if cfg["flags"] & sw.FLAG_SCHEDULE_BESIDE_SCATTER
+                   else "before the scatter"},
         "eager_ms_per_step": eager_ms,
         "per_bucket_launch": plain,
         "batched_over_plain": (value / plain["value"]) if plain else None,

@@ -194,6 +194,13 @@ typedef struct {
  * (measured: first is faster for thousands of small documents, after for one
  * large one), so the autotuner chooses it per workload. */
 #define SW_FLAG_PACKED_FIRST 2u
+/* Run the segment scheduling (the counting sort of (document, length)
+ * segments and the tile prefixes, which the bucket scatter does not read) on
+ * a side stream beside the scatter instead of before it.  Results are
+ * identical; it pays with thousands of documents (many segments) and costs
+ * with one large document, so the autotuner chooses it per workload.  Plans
+ * and the batched entry points with parallel classes only. */
+#define SW_FLAG_SCHEDULE_BESIDE_SCATTER 4u
 int sw_get_config(sw_config *out);
 int sw_set_config(const sw_config *cfg);
 /* Number of compiled variants of class c, and the chunk-sort tile (words per

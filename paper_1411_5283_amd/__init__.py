@@ -37,6 +37,7 @@ class SortWordsError(RuntimeError):
 
 FLAG_SERIAL_CLASSES = 1
 FLAG_PACKED_FIRST = 2
+FLAG_SCHEDULE_BESIDE_SCATTER = 4
 
 
 class sw_config(ctypes.Structure):

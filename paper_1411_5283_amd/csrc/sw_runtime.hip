@@ -350,6 +350,7 @@ struct Fork {
   hipStream_t side[sw::kNClass] = {};   // side[0] unused: class 0 stays on the main stream
   hipEvent_t fork = nullptr;
   hipEvent_t join[sw::kNClass] = {};
+  hipEvent_t seg_fork = nullptr, seg_join = nullptr;
   bool ready = false;
 };
 
@@ -358,6 +359,8 @@ int fork_init(Fork& f) {
   for (int c = 1; c < sw::kNClass; ++c) HIP_TRY(hipStreamCreateWithFlags(&f.side[c], hipStreamNonBlocking));
   HIP_TRY(hipEventCreateWithFlags(&f.fork, hipEventDisableTiming));
   for (int c = 1; c < sw::kNClass; ++c) HIP_TRY(hipEventCreateWithFlags(&f.join[c], hipEventDisableTiming));
+  HIP_TRY(hipEventCreateWithFlags(&f.seg_fork, hipEventDisableTiming));
+  HIP_TRY(hipEventCreateWithFlags(&f.seg_join, hipEventDisableTiming));
   f.ready = true;
   return SW_OK;
 }
@@ -372,6 +375,8 @@ void fork_free(Fork& f) {
     if (f.join[c]) (void)hipEventDestroy(f.join[c]);
   }
   if (f.fork) (void)hipEventDestroy(f.fork);
+  if (f.seg_fork) (void)hipEventDestroy(f.seg_fork);
+  if (f.seg_join) (void)hipEventDestroy(f.seg_join);
   f = Fork();
 }
 
@@ -403,30 +408,42 @@ int enqueue_body(const Ws& w, const Grids& g, hipStream_t s, bool capture, bool 
     ProfScope p(K_SEGMENTS, s, capture);
     sw::k_segments<kNT><<<g.docs, kNT, 0, s>>>(w);
   }
+  const bool par = !through_scatter && fork && fork->ready && !(!capture && profiling_on()) &&
+                   !(g.flags & SW_FLAG_SERIAL_CLASSES);
+  // the segment scheduling reads only the segment table, so it may run
+  // beside the scatter (on class 1's side stream, joined before the classes fork)
+  const bool beside = par && (g.flags & SW_FLAG_SCHEDULE_BESIDE_SCATTER);
   if (!through_scatter) {
-    {
-      ProfScope p(K_SEG_COUNT, s, capture);
-      sw::k_seg_count<kNT><<<g.segs, kNT, 0, s>>>(w);
+    hipStream_t ss = s;
+    if (beside) {
+      ss = fork->side[1];
+      HIP_TRY(hipEventRecord(fork->seg_fork, s));
+      HIP_TRY(hipStreamWaitEvent(ss, fork->seg_fork, 0));
     }
     {
-      ProfScope p(K_SCAN, s, capture);
-      sw::k_scan_rows<1024, 4><<<sw::kNKeys, 1024, 0, s>>>(w, w.segcnt, sw::kNKeys, w.SBmax + 1, 1);
+      ProfScope p(K_SEG_COUNT, ss, capture);
+      sw::k_seg_count<kNT><<<g.segs, kNT, 0, ss>>>(w);
     }
     {
-      ProfScope p(K_SEG_SCATTER, s, capture);
-      sw::k_seg_scatter<kNT><<<g.segs, kNT, 0, s>>>(w);
+      ProfScope p(K_SCAN, ss, capture);
+      sw::k_scan_rows<1024, 4><<<sw::kNKeys, 1024, 0, ss>>>(w, w.segcnt, sw::kNKeys, w.SBmax + 1, 1);
     }
     {
-      ProfScope p(K_TILE_PREFIX, s, capture);
-      sw::k_tile_prefix<1024><<<3 * sw::kNClass, 1024, 0, s>>>(w);
+      ProfScope p(K_SEG_SCATTER, ss, capture);
+      sw::k_seg_scatter<kNT><<<g.segs, kNT, 0, ss>>>(w);
     }
+    {
+      ProfScope p(K_TILE_PREFIX, ss, capture);
+      sw::k_tile_prefix<1024><<<3 * sw::kNClass, 1024, 0, ss>>>(w);
+    }
+    if (beside) HIP_TRY(hipEventRecord(fork->seg_join, ss));
   }
   {
     ProfScope p(K_SCATTER, s, capture);
     sw::k_scatter_pack<kScatterNT><<<g.scatter, kScatterNT, 0, s>>>(w);
   }
   if (through_scatter) return SW_OK;
-  const bool par = fork && fork->ready && !(!capture && profiling_on()) && !(g.flags & SW_FLAG_SERIAL_CLASSES);
+  if (beside) HIP_TRY(hipStreamWaitEvent(s, fork->seg_join, 0));
   if (par) {
     HIP_TRY(hipEventRecord(fork->fork, s));
     for (int c = 1; c < sw::kNClass; ++c) HIP_TRY(hipStreamWaitEvent(fork->side[c], fork->fork, 0));
@@ -855,7 +872,7 @@ int sw_set_config(const sw_config* cfg) {
     if (cfg->variant[c] >= (uint32_t)nv)
       return fail(SW_ERR_INVALID_ARG, "sw_set_config: variant[%d]=%u out of range", c, cfg->variant[c]);
   }
-  if (cfg->flags & ~(SW_FLAG_SERIAL_CLASSES | SW_FLAG_PACKED_FIRST))
+  if (cfg->flags & ~(SW_FLAG_SERIAL_CLASSES | SW_FLAG_PACKED_FIRST | SW_FLAG_SCHEDULE_BESIDE_SCATTER))
     return fail(SW_ERR_INVALID_ARG, "sw_set_config: unknown flags");
   std::lock_guard<std::mutex> lk(g_cfg_mu);
   g_cfg = *cfg;

@@ -130,8 +130,10 @@ def _plan_ms(sw, torch, cfg, words, ref, runs: int = 10) -> float:
 
 def refine_on_plan(wl, cfg: dict, rounds: int = 3, log=print, variants: bool = True) -> dict:
     """Second stage: per class, the variant with the lowest median plan time;
-    then whether each class's short-segment sort goes before its chunk sort
-    (FLAG_PACKED_FIRST).  With variants=False only the order is timed."""
+    then the launch-order flags: whether each class's short-segment sort goes
+    before its chunk sort (FLAG_PACKED_FIRST) and whether the segment
+    scheduling runs beside the scatter (FLAG_SCHEDULE_BESIDE_SCATTER), every
+    combination timed.  With variants=False only the flags are timed."""
     import torch
     import paper_1411_5283_amd as sw
 
@@ -165,7 +167,9 @@ def refine_on_plan(wl, cfg: dict, rounds: int = 3, log=print, variants: bool = T
         bv = min(med, key=med.get)
         if med[bv] < 0.995 * med[best["variant"][c]]:
             best["variant"][c] = bv
-    times = {f: [] for f in (0, sw.FLAG_PACKED_FIRST)}
+    tunable = (sw.FLAG_PACKED_FIRST, sw.FLAG_SCHEDULE_BESIDE_SCATTER)
+    combos = [sum(f for k, f in enumerate(tunable) if (m >> k) & 1) for m in range(1 << len(tunable))]
+    times = {f: [] for f in combos}
     for _ in range(rounds):
         for f in times:
             times[f].append(_plan_ms(sw, torch, dict(best, flags=f), words, ref))
@@ -221,7 +225,7 @@ def main():
                     help="only the second stage, starting from the cached configuration")
     ap.add_argument("--plan-rounds", type=int, default=3, help="interleaved timing rounds per variant")
     ap.add_argument("--order-only", action="store_true",
-                    help="with --plan-only: keep the cached variants, time only the short-segment order")
+                    help="with --plan-only: keep the cached variants, time only the launch-order flags")
     args = ap.parse_args()
     from . import wordgen
     cfg = int(args.workload.lstrip("c"))

@@ -60,11 +60,11 @@ def test_host_side_calls_without_gpu():
     assert L.sw_set_config(ctypes.byref(bad)) == sw.ERR_INVALID_ARG
     flagged = sw.sw_config()
     ctypes.memmove(ctypes.byref(flagged), ctypes.byref(cfg), ctypes.sizeof(cfg))
-    flagged.flags = 4                # no such flag
+    flagged.flags = 8                # no such flag
     assert L.sw_set_config(ctypes.byref(flagged)) == sw.ERR_INVALID_ARG
-    flagged.flags = sw.FLAG_SERIAL_CLASSES | sw.FLAG_PACKED_FIRST
+    flagged.flags = sw.FLAG_SERIAL_CLASSES | sw.FLAG_PACKED_FIRST | sw.FLAG_SCHEDULE_BESIDE_SCATTER
     assert L.sw_set_config(ctypes.byref(flagged)) == 0
-    assert sw.get_config()["flags"] == 3
+    assert sw.get_config()["flags"] == 7
     assert L.sw_set_config(ctypes.byref(cfg)) == 0
     assert sw.num_variants(0) >= 1 and sw.num_variants(7) == 0
     t, p = sw.variant_tiles(0, 0)

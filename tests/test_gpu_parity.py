@@ -251,17 +251,19 @@ def test_packed_short_segments(gpu, oracle_mod):
     _same(gpu.sort_wordlist(wl), _expect(oracle_mod, wl, bubble=False), "packed")
 
 
-@pytest.mark.parametrize("flags", [0, 2])
+@pytest.mark.parametrize("flags", [0, 2, 4, 6])
 def test_short_segment_order_flag(gpu, oracle_mod, default_config, flags):
     # the short-segment sort enqueued after (0) or before (FLAG_PACKED_FIRST)
-    # each class's chunk sort: the same result, eager and replayed in a plan
+    # each class's chunk sort, the segment scheduling before or beside
+    # (FLAG_SCHEDULE_BESIDE_SCATTER) the scatter: the same result, eager and
+    # replayed in a plan
     import torch
     docs = [wordgen.config(1, 0.1), _doc_with_segment_sizes([1023, 1024, 1025, 5, 2048], seed=4)]
     docs += [_doc_with_segment_sizes([1, 0, 1, 3], seed=20 + d) for d in range(300)]
     docs += [wordgen.config(2, 0.05)]
     wl = wordgen.concat_docs(docs)
     _say("case short-segment order flags=%d docs=%d n=%d" % (flags, wl.n_docs, wl.n))
-    assert gpu.FLAG_PACKED_FIRST == 2
+    assert gpu.FLAG_PACKED_FIRST == 2 and gpu.FLAG_SCHEDULE_BESIDE_SCATTER == 4
     gpu.set_config(flags=flags)
     exp = _expect(oracle_mod, wl, bubble=False)
     _same(gpu.sort_wordlist(wl), exp, "flags %d eager" % flags)
