@@ -662,7 +662,8 @@ def main():
                    "short_segments": "before the chunk sort" if cfg["flags"] & sw.FLAG_PACKED_FIRST
                    else "after the chunk sort",
                    "segment_scheduling": "beside the scatter" if cfg["flags"] & sw.FLAG_SCHEDULE_BESIDE_SCATTER
-                   else "before the scatter"},
+                   else "before the scatter",
+                   "class_order": sw.class_order((cfg["flags"] & sw.FLAG_ORDER_MASK) >> sw.FLAG_ORDER_SHIFT)},
         "eager_ms_per_step": eager_ms,
         "per_bucket_launch": plain,
         "batched_over_plain": (value / plain["value"]) if plain else None,

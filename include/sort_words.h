@@ -201,6 +201,14 @@ typedef struct {
  * with one large document, so the autotuner chooses it per workload.  Plans
  * and the batched entry points with parallel classes only. */
 #define SW_FLAG_SCHEDULE_BESIDE_SCATTER 4u
+/* Bits SW_FLAG_ORDER_SHIFT.. of flags: the order in which the key classes'
+ * work is enqueued, as an index 0..23 into the 24 orders of the four classes
+ * taken in lexicographic order (0: 0-1-2-3, 1: 0-1-3-2, ..., 23: 3-2-1-0).
+ * The classes' chains run concurrently either way; the order decides which
+ * chunk sorts start first and hold the LDS.  Results are identical; the
+ * autotuner chooses it per workload.  Larger indices are rejected. */
+#define SW_FLAG_ORDER_SHIFT 8
+#define SW_FLAG_ORDER_MASK (31u << SW_FLAG_ORDER_SHIFT)
 int sw_get_config(sw_config *out);
 int sw_set_config(const sw_config *cfg);
 /* Number of compiled variants of class c, and the chunk-sort tile (words per

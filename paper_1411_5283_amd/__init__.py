@@ -38,6 +38,15 @@ class SortWordsError(RuntimeError):
 FLAG_SERIAL_CLASSES = 1
 FLAG_PACKED_FIRST = 2
 FLAG_SCHEDULE_BESIDE_SCATTER = 4
+FLAG_ORDER_SHIFT = 8        # bits 8..12: index (0..23) of the classes' enqueue order
+FLAG_ORDER_MASK = 31 << FLAG_ORDER_SHIFT
+
+
+def class_order(index: int) -> list:
+    """The classes' enqueue order that order index 0..23 names (the orders of
+    0..3 in lexicographic order), for reporting a configuration."""
+    import itertools
+    return list(list(itertools.permutations(range(NUM_CLASSES)))[index])
 
 
 class sw_config(ctypes.Structure):

@@ -341,6 +341,24 @@ int make_grids(const Ws& w, const sw_config& cfg, Grids& g) {
   return SW_OK;
 }
 
+// The k-th order of the four classes in lexicographic order (k < 24): the
+// factorial number system picks each position's class among those left.
+void class_order(uint32_t k, int (&order)[sw::kNClass]) {
+  static_assert(sw::kNClass == 4, "24 orders of four classes");
+  int left[sw::kNClass];
+  for (int c = 0; c < sw::kNClass; ++c) left[c] = c;
+  int n = sw::kNClass;
+  uint32_t f = 6;   // (kNClass - 1)!
+  for (int i = 0; i < sw::kNClass; ++i) {
+    const int j = (int)(k / f);
+    order[i] = left[j];
+    for (int t = j; t + 1 < n; ++t) left[t] = left[t + 1];
+    --n;
+    k %= f;
+    if (n > 0) f /= (uint32_t)n;
+  }
+}
+
 // Side streams and events for running the four key classes concurrently:
 // after the scatter the classes share nothing, so each class's chain (chunk
 // sort, then one merge per level) goes on its own stream, forked
@@ -454,8 +472,11 @@ int enqueue_body(const Ws& w, const Grids& g, hipStream_t s, bool capture, bool 
   // class, level 1, ...), so that a runtime which maps the parallel chains
   // onto fewer hardware queues still finds every class's next kernel early.
   auto cstream = [&](int c) { return (par && c > 0) ? fork->side[c] : s; };
+  int order[sw::kNClass];
+  class_order((g.flags & SW_FLAG_ORDER_MASK) >> SW_FLAG_ORDER_SHIFT, order);
   int max_levels = 0;
-  for (int c = 0; c < sw::kNClass; ++c) {
+  for (int k = 0; k < sw::kNClass; ++k) {
+    const int c = order[k];
     hipStream_t cs = cstream(c);
     // the short segments are disjoint from the chunk-sorted ones, so the two
     // kernels may go in either order (which is faster depends on the workload)
@@ -472,7 +493,8 @@ int enqueue_body(const Ws& w, const Grids& g, hipStream_t s, bool capture, bool 
     max_levels = std::max(max_levels, g.levels[c]);
   }
   for (int l = 0; l < max_levels; ++l) {
-    for (int c = 0; c < sw::kNClass; ++c) {
+    for (int k = 0; k < sw::kNClass; ++k) {
+      const int c = order[k];
       if (l >= g.levels[c]) continue;
       hipStream_t cs = cstream(c);
       ProfScope p(K_MERGE0 + c, cs, capture);
@@ -872,8 +894,12 @@ int sw_set_config(const sw_config* cfg) {
     if (cfg->variant[c] >= (uint32_t)nv)
       return fail(SW_ERR_INVALID_ARG, "sw_set_config: variant[%d]=%u out of range", c, cfg->variant[c]);
   }
-  if (cfg->flags & ~(SW_FLAG_SERIAL_CLASSES | SW_FLAG_PACKED_FIRST | SW_FLAG_SCHEDULE_BESIDE_SCATTER))
+  if (cfg->flags &
+      ~(SW_FLAG_SERIAL_CLASSES | SW_FLAG_PACKED_FIRST | SW_FLAG_SCHEDULE_BESIDE_SCATTER | SW_FLAG_ORDER_MASK))
     return fail(SW_ERR_INVALID_ARG, "sw_set_config: unknown flags");
+  if (((cfg->flags & SW_FLAG_ORDER_MASK) >> SW_FLAG_ORDER_SHIFT) >= 24)
+    return fail(SW_ERR_INVALID_ARG, "sw_set_config: class order index %u is not below 24",
+                (cfg->flags & SW_FLAG_ORDER_MASK) >> SW_FLAG_ORDER_SHIFT);
   std::lock_guard<std::mutex> lk(g_cfg_mu);
   g_cfg = *cfg;
   return SW_OK;

@@ -133,7 +133,8 @@ def refine_on_plan(wl, cfg: dict, rounds: int = 3, log=print, variants: bool = T
     then the launch-order flags: whether each class's short-segment sort goes
     before its chunk sort (FLAG_PACKED_FIRST) and whether the segment
     scheduling runs beside the scatter (FLAG_SCHEDULE_BESIDE_SCATTER), every
-    combination timed.  With variants=False only the flags are timed."""
+    combination timed; then, with those, the 24 enqueue orders of the
+    classes.  With variants=False only the flags and the order are timed."""
     import torch
     import paper_1411_5283_amd as sw
 
@@ -169,20 +170,35 @@ def refine_on_plan(wl, cfg: dict, rounds: int = 3, log=print, variants: bool = T
             best["variant"][c] = bv
     tunable = (sw.FLAG_PACKED_FIRST, sw.FLAG_SCHEDULE_BESIDE_SCATTER)
     combos = [sum(f for k, f in enumerate(tunable) if (m >> k) & 1) for m in range(1 << len(tunable))]
+    order_bits = best["flags"] & sw.FLAG_ORDER_MASK
     times = {f: [] for f in combos}
     for _ in range(rounds):
         for f in times:
-            times[f].append(_plan_ms(sw, torch, dict(best, flags=f), words, ref))
+            times[f].append(_plan_ms(sw, torch, dict(best, flags=f | order_bits), words, ref))
     med = {f: float(np.median(t)) for f, t in times.items()}
     flag_trials = [{"flags": f, "plan_ms": m} for f, m in med.items()]
     for f, m in med.items():
         log("plan: flags %d: %.4f ms (median of %d)" % (f, m, rounds))
     bf = min(med, key=med.get)
-    if med[bf] < 0.995 * med[best["flags"]]:
-        best["flags"] = bf
+    cur = best["flags"] & ~sw.FLAG_ORDER_MASK
+    if med[bf] < 0.995 * med.get(cur, float("inf")):
+        cur = bf
+    order = (best["flags"] & sw.FLAG_ORDER_MASK) >> sw.FLAG_ORDER_SHIFT
+    # then the classes' enqueue order (the 24 orders), with those flags
+    times = {k: [] for k in range(24)}
+    for _ in range(rounds):
+        for k in times:
+            times[k].append(_plan_ms(sw, torch, dict(best, flags=cur | (k << sw.FLAG_ORDER_SHIFT)), words, ref))
+    med = {k: float(np.median(t)) for k, t in times.items()}
+    order_trials = [{"order": k, "plan_ms": m} for k, m in med.items()]
+    log("plan: class orders: " + ", ".join("%d: %.4f" % (k, m) for k, m in med.items()))
+    bk = min(med, key=med.get)
+    if med[bk] < 0.995 * med[order]:
+        order = bk
+    best["flags"] = cur | (order << sw.FLAG_ORDER_SHIFT)
     sw.set_config(**best)
     final = float(np.median([_plan_ms(sw, torch, best, words, ref) for _ in range(rounds)]))
-    out = {"config": best, "plan_ms": final, "flag_trials": flag_trials}
+    out = {"config": best, "plan_ms": final, "flag_trials": flag_trials, "order_trials": order_trials}
     if variants:
         out["plan_trials"] = trials
     return out

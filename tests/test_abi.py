@@ -65,6 +65,12 @@ def test_host_side_calls_without_gpu():
     flagged.flags = sw.FLAG_SERIAL_CLASSES | sw.FLAG_PACKED_FIRST | sw.FLAG_SCHEDULE_BESIDE_SCATTER
     assert L.sw_set_config(ctypes.byref(flagged)) == 0
     assert sw.get_config()["flags"] == 7
+    flagged.flags = 24 << sw.FLAG_ORDER_SHIFT     # only 24 class orders
+    assert L.sw_set_config(ctypes.byref(flagged)) == sw.ERR_INVALID_ARG
+    flagged.flags = 23 << sw.FLAG_ORDER_SHIFT
+    assert L.sw_set_config(ctypes.byref(flagged)) == 0
+    assert sw.class_order(0) == [0, 1, 2, 3] and sw.class_order(1) == [0, 1, 3, 2]
+    assert sw.class_order(23) == [3, 2, 1, 0]
     assert L.sw_set_config(ctypes.byref(cfg)) == 0
     assert sw.num_variants(0) >= 1 and sw.num_variants(7) == 0
     t, p = sw.variant_tiles(0, 0)

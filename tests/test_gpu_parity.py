@@ -279,3 +279,28 @@ def test_short_segment_order_flag(gpu, oracle_mod, default_config, flags):
                   "flags %d plan replay %d" % (flags, rep))
     finally:
         plan.close()
+
+
+def test_every_class_order(gpu, oracle_mod, default_config):
+    # the 24 enqueue orders of the classes (with both launch-order flags and
+    # without): the same result, eager and in a plan
+    import torch
+    docs = [wordgen.config(1, 0.1), _doc_with_segment_sizes([1023, 1024, 1025, 5, 2048], seed=5)]
+    docs += [_doc_with_segment_sizes([1, 0, 1, 3], seed=40 + d) for d in range(100)]
+    wl = wordgen.concat_docs(docs)
+    exp = _expect(oracle_mod, wl, bubble=False)
+    chars, offs, ddocs = gpu.device_words(wl)
+    perm = torch.empty(wl.n, dtype=torch.int32, device="cuda")
+    boff = torch.empty(wl.n_docs * 34, dtype=torch.int32, device="cuda")
+    for k in range(24):
+        flags = (k << gpu.FLAG_ORDER_SHIFT) | (6 if k % 2 else 0)
+        _say("case class order %d flags=%d n=%d" % (k, flags, wl.n))
+        gpu.set_config(flags=flags)
+        _same(gpu.sort_wordlist(wl), exp, "order %d eager" % k)
+        plan = gpu.Plan(wl.n, wl.n_docs)
+        try:
+            plan.run(chars, offs, ddocs, wl.n_docs, wl.n, perm, boff)
+            plan.status()
+            _same((gpu.to_u32(perm), gpu.to_u32(boff).reshape(wl.n_docs, 34)), exp, "order %d plan" % k)
+        finally:
+            plan.close()
