@@ -75,7 +75,7 @@ def _load():
         lib.oracle_rank.argtypes = [u8p, u32p, ctypes.c_uint32, ctypes.c_uint32]
         lib.oracle_rank.restype = ctypes.c_uint64
         lib.oracle_length_counts.argtypes = [u32p, ctypes.c_uint32, u64p]
-        lib.oracle_length_counts.restype = None
+        lib.oracle_length_counts.restype = ctypes.c_int
         lib.oracle_tokenize.argtypes = [u8p, ctypes.c_uint64, ctypes.c_uint32, u8p, u32p,
                                         ctypes.c_uint32, u32p]
         lib.oracle_tokenize.restype = ctypes.c_int
@@ -157,8 +157,10 @@ def oracle_rank(chars, offsets, i: int) -> int:
 def oracle_length_counts(offsets) -> np.ndarray:
     offsets = np.ascontiguousarray(offsets, dtype=np.uint32)
     out = np.zeros(MAX_LEN + 1, np.uint64)
-    _load().oracle_length_counts(_p(offsets, ctypes.c_uint32), offsets.shape[0] - 1,
-                                 _p(out, ctypes.c_uint64))
+    rc = _load().oracle_length_counts(_p(offsets, ctypes.c_uint32), offsets.shape[0] - 1,
+                                      _p(out, ctypes.c_uint64))
+    if rc != OK:
+        raise OracleError(rc)
     return out
 
 

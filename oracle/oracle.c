@@ -258,15 +258,23 @@ uint64_t oracle_rank(const uint8_t *chars, const uint32_t *offsets, uint32_t n, 
     return r;
 }
 
-/* Number of words of each length (for bucket checks at any size). */
-void oracle_length_counts(const uint32_t *offsets, uint32_t n, uint64_t *counts)
+/* Number of words of each length 0..32: the sizes of the phase-2 lists
+ * (Abstract: a sub-array's size is the number of words with that many
+ * characters), for bucket checks at any size.  The same checks and return
+ * codes as the sorts: offsets that decrease are -1, a word longer than 32
+ * bytes is -2 (counts are then unspecified). */
+int oracle_length_counts(const uint32_t *offsets, uint32_t n, uint64_t *counts)
 {
+    if (!offsets || !counts)
+        return ORC_INVALID;
+    const int rc = check_words(offsets, n);
+    if (rc != ORC_OK)
+        return rc;
     for (int L = 0; L < ORC_NBUCKET; ++L)
         counts[L] = 0;
-    for (uint32_t i = 0; i < n; ++i) {
-        uint32_t L = word_len(offsets, i);
-        counts[L > ORC_MAX_LEN ? ORC_MAX_LEN : L] += 1;
-    }
+    for (uint32_t i = 0; i < n; ++i)
+        counts[offsets[i + 1] - offsets[i]] += 1;
+    return ORC_OK;
 }
 
 /* ---------------------------------------------------------------- phase 1

@@ -209,3 +209,54 @@ def test_invariant_checker_rejects_wrong_orders(oracle_mod):
     badb[5] += 1                                       # bucket offset off by one
     with pytest.raises(AssertionError):
         check_invariants(wl.chars, wl.offsets, perm, badb)
+
+
+# ---------------------------------------------------------------- length counts
+# oracle_length_counts gives the sizes of the phase-2 lists (Abstract: one
+# sub-array per character count, sized by how many words have that count).
+# Pinned against numpy's bincount (a library routine), closed forms, the
+# bucket offsets that the brute force fixes, and its error codes.
+
+@pytest.mark.parametrize("cfg,scale", [(1, 1.0), (2, 0.5), (4, 0.002)])
+def test_length_counts_equal_bincount(oracle_mod, cfg, scale):
+    wl = wordgen.config(cfg, scale)
+    lens = np.diff(wl.offsets.astype(np.int64))
+    exp = np.bincount(lens, minlength=33)
+    got = oracle_mod.oracle_length_counts(wl.offsets)
+    assert got.shape == (33,) and np.array_equal(got, exp)
+    assert int(got.sum()) == wl.n
+
+
+def test_length_counts_closed_forms(oracle_mod):
+    # n empty words: everything in list 0
+    got = oracle_mod.oracle_length_counts(np.zeros(1001, np.uint32))
+    assert got[0] == 1000 and not got[1:].any()
+    # every length 0..32 once, in either order: all ones
+    for lens in (np.arange(33), np.arange(33)[::-1]):
+        offs = np.concatenate([[0], np.cumsum(lens)]).astype(np.uint32)
+        assert np.array_equal(oracle_mod.oracle_length_counts(offs), np.ones(33, np.uint64))
+    # a non-zero first offset changes nothing
+    offs = np.array([7, 7, 9, 9, 41, 44], np.uint32)      # lengths 0, 2, 0, 32, 3
+    exp = np.zeros(33, np.uint64)
+    exp[[0, 2, 32, 3]] = [2, 1, 1, 1]
+    assert np.array_equal(oracle_mod.oracle_length_counts(offs), exp)
+    # no words at all
+    assert not oracle_mod.oracle_length_counts(np.array([5], np.uint32)).any()
+
+
+def test_length_counts_are_the_brute_force_bucket_sizes(oracle_mod):
+    for words in _tiny_cases():
+        wl = wordgen.from_words(words)
+        _, boff = brute_force(words)
+        got = oracle_mod.oracle_length_counts(wl.offsets)
+        assert np.array_equal(got, np.diff(boff.astype(np.int64))[:33]), words
+
+
+def test_length_counts_error_codes(oracle_mod):
+    with pytest.raises(oracle_mod.OracleError) as e:
+        oracle_mod.oracle_length_counts(np.array([0, 33], np.uint32))
+    assert e.value.code == oracle_mod.WORD_TOO_LONG
+    with pytest.raises(oracle_mod.OracleError) as e:
+        oracle_mod.oracle_length_counts(np.array([0, 40, 5], np.uint32))   # decreases and too long
+    assert e.value.code == oracle_mod.INVALID_ARG
+    assert oracle_mod.oracle_length_counts(np.array([0, 32], np.uint32))[32] == 1

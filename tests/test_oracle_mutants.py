@@ -78,3 +78,64 @@ def test_pins_reject_mutant(name):
             if caught:
                 break
         assert caught, "planted mistake %r passed every pin" % name
+
+
+# Planted mistakes in oracle_length_counts: an index off by one, a word
+# skipped at either end of the loop, the byte at the start counted instead of
+# the length, the error check dropped for long words (they would then be
+# counted past the last list, so the mutant clamps them the way an earlier
+# version did).
+COUNT_MUTANTS = {
+    "index_minus_one": ("counts[offsets[i + 1] - offsets[i]] += 1;",
+                        "counts[offsets[i + 1] - offsets[i] - (offsets[i + 1] > offsets[i])] += 1;"),
+    "index_plus_one": ("counts[offsets[i + 1] - offsets[i]] += 1;",
+                       "counts[offsets[i + 1] - offsets[i] + (offsets[i + 1] - offsets[i] < 32)] += 1;"),
+    "first_word_skipped": ("    for (uint32_t i = 0; i < n; ++i)\n        counts[offsets[i + 1]",
+                           "    for (uint32_t i = 1; i < n; ++i)\n        counts[offsets[i + 1]"),
+    "last_word_skipped": ("    for (uint32_t i = 0; i < n; ++i)\n        counts[offsets[i + 1]",
+                          "    for (uint32_t i = 0; i + 1 < n; ++i)\n        counts[offsets[i + 1]"),
+    "offset_not_length": ("counts[offsets[i + 1] - offsets[i]] += 1;",
+                          "counts[offsets[i + 1] % 33] += 1;"),
+    "long_words_clamped": ("    const int rc = check_words(offsets, n);\n    if (rc != ORC_OK)\n        return rc;\n"
+                           "    for (int L = 0; L < ORC_NBUCKET; ++L)\n        counts[L] = 0;\n"
+                           "    for (uint32_t i = 0; i < n; ++i)\n        counts[offsets[i + 1] - offsets[i]] += 1;",
+                           "    for (int L = 0; L < ORC_NBUCKET; ++L)\n        counts[L] = 0;\n"
+                           "    for (uint32_t i = 0; i < n; ++i)\n        counts[offsets[i + 1] - offsets[i] > 32 ? 32 : "
+                           "offsets[i + 1] - offsets[i]] += 1;"),
+}
+
+
+def _length_counts(lib, offsets):
+    offsets = np.ascontiguousarray(offsets, np.uint32)
+    out = np.zeros(33, np.uint64)
+    lib.oracle_length_counts.restype = ctypes.c_int
+    rc = lib.oracle_length_counts(offsets.ctypes.data_as(ctypes.POINTER(ctypes.c_uint32)),
+                                  ctypes.c_uint32(offsets.shape[0] - 1),
+                                  out.ctypes.data_as(ctypes.POINTER(ctypes.c_uint64)))
+    return rc, out
+
+
+@pytest.mark.skipif(shutil.which("gcc") is None, reason="needs gcc")
+@pytest.mark.parametrize("name", sorted(COUNT_MUTANTS))
+def test_length_count_pins_reject_mutant(name):
+    old, new = COUNT_MUTANTS[name]
+    with tempfile.TemporaryDirectory() as tmp:
+        lib = _build(tmp, name, old, new)
+        caught = False
+        # the pins of test_oracle.py: bincount on generated text, closed forms,
+        # the brute-force bucket sizes, the error code for a long word
+        wl = wordgen.config(1, 0.2)
+        rc, got = _length_counts(lib, wl.offsets)
+        caught |= rc != 0 or not np.array_equal(got, np.bincount(np.diff(wl.offsets.astype(np.int64)),
+                                                                 minlength=33))
+        lens = np.arange(33)
+        rc, got = _length_counts(lib, np.concatenate([[0], np.cumsum(lens)]))
+        caught |= rc != 0 or not np.array_equal(got, np.ones(33, np.uint64))
+        for words in list(_tiny_cases())[:50]:
+            w = wordgen.from_words(words)
+            _, boff = brute_force(words)
+            rc, got = _length_counts(lib, w.offsets)
+            caught |= rc != 0 or not np.array_equal(got, np.diff(boff.astype(np.int64))[:33])
+        rc, _ = _length_counts(lib, np.array([0, 33], np.uint32))
+        caught |= rc != -2
+        assert caught, "planted mistake %r passed every pin" % name
