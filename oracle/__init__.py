@@ -11,6 +11,8 @@ Functions (host numpy arrays in, numpy arrays out):
   phase 3), lists concatenated shorter-first.  Plain C, ``oracle.c``.
 * ``oracle_chunked`` -- the paper's parallel form (sections 3.2 and 4): chunks
   bubble-sorted alone, then merged.  Plain C.
+* ``oracle_chunks``  -- the chunk step alone (section 4, each slave's bubble
+  sort of its chunk): chunks sorted, not merged.  Plain C.
 * ``oracle_def``     -- the definition the method reaches: indices ordered by
   the total order (length, bytes unsigned, index).  Plain C over qsort.
 * ``oracle_sorted``  -- the same definition with Python's ``sorted``.
@@ -70,8 +72,10 @@ def _load():
             f = getattr(lib, name)
             f.argtypes = [u8p, u32p, ctypes.c_uint32, u32p, u32p]
             f.restype = ctypes.c_int
-        lib.oracle_chunked.argtypes = [u8p, u32p, ctypes.c_uint32, ctypes.c_uint32, u32p, u32p]
-        lib.oracle_chunked.restype = ctypes.c_int
+        for name in ("oracle_chunked", "oracle_chunks"):
+            f = getattr(lib, name)
+            f.argtypes = [u8p, u32p, ctypes.c_uint32, ctypes.c_uint32, u32p, u32p]
+            f.restype = ctypes.c_int
         lib.oracle_rank.argtypes = [u8p, u32p, ctypes.c_uint32, ctypes.c_uint32]
         lib.oracle_rank.restype = ctypes.c_uint64
         lib.oracle_length_counts.argtypes = [u32p, ctypes.c_uint32, u64p]
@@ -135,16 +139,28 @@ def oracle_status(chars, offsets, fn: str = "oracle_bubble") -> int:
     return rc
 
 
-def oracle_chunked(chars, offsets, chunk: int):
+def _call_chunk(fn, chars, offsets, chunk):
     chars, offsets = _prep(chars, offsets)
     n = offsets.shape[0] - 1
     perm = np.zeros(max(n, 1), np.uint32)
     boff = np.zeros(N_OFFSETS, np.uint32)
-    rc = _load().oracle_chunked(_p(chars, ctypes.c_uint8), _p(offsets, ctypes.c_uint32), n,
-                                int(chunk), _p(perm, ctypes.c_uint32), _p(boff, ctypes.c_uint32))
+    rc = fn(_p(chars, ctypes.c_uint8), _p(offsets, ctypes.c_uint32), n,
+            int(chunk), _p(perm, ctypes.c_uint32), _p(boff, ctypes.c_uint32))
     if rc != OK:
         raise OracleError(rc)
     return perm[:n], boff
+
+
+def oracle_chunked(chars, offsets, chunk: int):
+    """(perm, bucket_offsets): chunks of each length list bubble-sorted alone, then merged."""
+    return _call_chunk(_load().oracle_chunked, chars, offsets, chunk)
+
+
+def oracle_chunks(chars, offsets, chunk: int):
+    """(perm, bucket_offsets) after the chunk step alone: each length list's chunks of
+    `chunk` words bubble-sorted, laid out one after another, NOT merged (section 4's
+    slaves before the master's merge)."""
+    return _call_chunk(_load().oracle_chunks, chars, offsets, chunk)
 
 
 def oracle_rank(chars, offsets, i: int) -> int:

@@ -202,6 +202,34 @@ int oracle_chunked(const uint8_t *chars, const uint32_t *offsets, uint32_t n,
 }
 
 /* ------------------------------------------------------------------------
+ * The slaves' step of section 4 alone: each length list is cut into chunks of
+ * `chunk` words from its start (the last one shorter) and each chunk is
+ * bubble-sorted on its own; the chunks are not merged.  perm holds the lists
+ * in length order, each list's chunks one after another.  bucket_offsets as
+ * in oracle_bubble. */
+int oracle_chunks(const uint8_t *chars, const uint32_t *offsets, uint32_t n,
+                  uint32_t chunk, uint32_t *perm, uint32_t *bucket_offsets)
+{
+    uint32_t counts[ORC_NBUCKET], start[ORC_NBUCKET + 1];
+    if (!offsets || !bucket_offsets || (n && (!chars || !perm)) || chunk == 0)
+        return ORC_INVALID;
+    int rc = check_words(offsets, n);
+    if (rc != ORC_OK)
+        return rc;
+    bucket_by_length(offsets, n, counts, start, perm);
+    for (int L = 0; L < ORC_NBUCKET; ++L) {
+        uint32_t *v = perm + start[L];
+        for (uint32_t lo = 0; lo < counts[L]; lo += chunk) {
+            uint32_t len = (counts[L] - lo < chunk) ? counts[L] - lo : chunk;
+            bubble_sort_words(chars, offsets, v + lo, len, (uint32_t)L);
+        }
+    }
+    for (int L = 0; L <= ORC_NBUCKET; ++L)
+        bucket_offsets[L] = start[L];
+    return ORC_OK;
+}
+
+/* ------------------------------------------------------------------------
  * The definition the method reaches: the unique ordering of the indices by
  * the total order key(i) = (length, bytes as unsigned, i).  A library sort
  * (qsort) serves as the step; the index in the key makes every key distinct,

@@ -260,3 +260,51 @@ def test_length_counts_error_codes(oracle_mod):
         oracle_mod.oracle_length_counts(np.array([0, 40, 5], np.uint32))   # decreases and too long
     assert e.value.code == oracle_mod.INVALID_ARG
     assert oracle_mod.oracle_length_counts(np.array([0, 32], np.uint32))[32] == 1
+
+
+def chunks_brute_force(words, chunk):
+    """The chunk step by brute force: each length list (input order) cut into
+    chunks of `chunk` from its start, each chunk ordered by the one strictly
+    increasing permutation of its (bytes, index) keys."""
+    out = []
+    for L in range(33):
+        lst = [i for i, w in enumerate(words) if len(w) == L]
+        for lo in range(0, len(lst), chunk):
+            part = lst[lo:lo + chunk]
+            local, _ = brute_force([words[i] for i in part])
+            out += [part[k] for k in local]
+    boff = [sum(1 for w in words if len(w) < L) for L in range(34)]
+    return np.asarray(out, np.uint32), np.asarray(boff, np.uint32)
+
+
+def test_chunk_step_pins(oracle_mod):
+    # brute force per chunk on the tiny cases, every chunk size that matters
+    for words in list(_tiny_cases())[::3]:
+        wl = wordgen.from_words(words)
+        for c in range(1, len(words) + 2):
+            exp_perm, exp_boff = chunks_brute_force(words, c)
+            perm, boff = oracle_mod.oracle_chunks(wl.chars, wl.offsets, c)
+            assert np.array_equal(perm, exp_perm), (c, words)
+            assert np.array_equal(boff, exp_boff)
+    wl = wordgen.config(1, 0.1)
+    lens = np.diff(wl.offsets.astype(np.int64))
+    # chunk 1: nothing is exchanged, the lists keep input order (stable argsort of lengths)
+    perm, _ = oracle_mod.oracle_chunks(wl.chars, wl.offsets, 1)
+    assert np.array_equal(perm, np.argsort(lens, kind="stable"))
+    # one chunk per list: the whole sort
+    full, fboff = oracle_mod.oracle_def(wl.chars, wl.offsets)
+    perm, boff = oracle_mod.oracle_chunks(wl.chars, wl.offsets, wl.n)
+    assert np.array_equal(perm, full) and np.array_equal(boff, fboff)
+    # merging the sorted chunks of every list (Python's heapq) gives the whole sort
+    import heapq
+    words = wl.words()
+    for c in (7, 64, 1000):
+        perm, boff = oracle_mod.oracle_chunks(wl.chars, wl.offsets, c)
+        merged = []
+        for L in range(33):
+            lo, hi = int(boff[L]), int(boff[L + 1])
+            runs = [[(words[i], i) for i in perm[a:min(a + c, hi)]] for a in range(lo, hi, c)]
+            for r in runs:
+                assert r == sorted(r)
+            merged += [i for _, i in heapq.merge(*runs)]
+        assert np.array_equal(np.asarray(merged, np.uint32), full), c

@@ -15,7 +15,7 @@ import numpy as np
 import pytest
 
 from paper_1411_5283_amd import wordgen
-from test_oracle import _tiny_cases, brute_force
+from test_oracle import _tiny_cases, brute_force, chunks_brute_force
 
 SRC = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "oracle", "oracle.c")
 
@@ -138,4 +138,37 @@ def test_length_count_pins_reject_mutant(name):
             caught |= rc != 0 or not np.array_equal(got, np.diff(boff.astype(np.int64))[:33])
         rc, _ = _length_counts(lib, np.array([0, 33], np.uint32))
         caught |= rc != -2
+        assert caught, "planted mistake %r passed every pin" % name
+
+
+# Planted mistakes in the chunk step alone (oracle_chunks): chunk boundaries
+# shifted, the last chunk cut short, a chunk one word too long.
+CHUNK_MUTANTS = {
+    "chunk_stride_plus_one": ("for (uint32_t lo = 0; lo < counts[L]; lo += chunk) {",
+                              "for (uint32_t lo = 0; lo < counts[L]; lo += chunk + 1) {"),
+    "chunk_starts_at_one": ("for (uint32_t lo = 0; lo < counts[L]; lo += chunk) {",
+                            "for (uint32_t lo = counts[L] > chunk; lo < counts[L]; lo += chunk) {"),
+    "last_chunk_short": ("uint32_t len = (counts[L] - lo < chunk) ? counts[L] - lo : chunk;",
+                         "uint32_t len = (counts[L] - lo < chunk) ? counts[L] - lo - (counts[L] - lo > 1) : chunk;"),
+    "chunk_one_too_long": ("uint32_t len = (counts[L] - lo < chunk) ? counts[L] - lo : chunk;",
+                           "uint32_t len = (counts[L] - lo <= chunk) ? counts[L] - lo : chunk + 1;"),
+}
+
+
+@pytest.mark.skipif(shutil.which("gcc") is None, reason="needs gcc")
+@pytest.mark.parametrize("name", sorted(CHUNK_MUTANTS))
+def test_chunk_step_pins_reject_mutant(name):
+    old, new = CHUNK_MUTANTS[name]
+    with tempfile.TemporaryDirectory() as tmp:
+        lib = _build(tmp, name, old, new)
+        caught = False
+        for words in _tiny_cases():
+            for c in (1, 2, 3):
+                exp_perm, exp_boff = chunks_brute_force(words, c)
+                perm, boff = _run(lib, "oracle_chunks", words, c)
+                if not (np.array_equal(perm, exp_perm) and np.array_equal(boff, exp_boff)):
+                    caught = True
+                    break
+            if caught:
+                break
         assert caught, "planted mistake %r passed every pin" % name
