@@ -449,6 +449,19 @@ def text_bench(args, sw, wordgen, torch, wl, chars, offs, docs, perm, boff, perm
     }
 
 
+# ------------------------------------------------------------------ counter calibration
+def copy_calibration(torch, nbytes: int = 1 << 30):
+    """A plain device copy of a known size, three times (read nbytes, write nbytes)."""
+    a = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
+    b = torch.empty_like(a)
+    a.fill_(1)
+    torch.cuda.synchronize()
+    for _ in range(3):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_calibration_bytes": nbytes, "copies": 3}), flush=True)
+
+
 # ------------------------------------------------------------------ main
 def main():
     ap = argparse.ArgumentParser()
@@ -475,6 +488,10 @@ def main():
     ap.add_argument("--serve-max-wait-ms", type=float, default=1.0)
     ap.add_argument("--serve-copy-threads", type=int, default=10)
     ap.add_argument("--serve-python", action="store_true", help="the Python scheduler instead of the native loop")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only copy 1 GiB on the device three times: run under rocprofv3 --pmc FETCH_SIZE "
+                         "(then WRITE_SIZE), what the counters read for a copy of known size scales the "
+                         "sort's counters into HBM bytes")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py: the library runs on one GPU; --gpus %d is not supported (sharding across "
@@ -482,6 +499,9 @@ def main():
         sys.exit(2)
 
     import torch
+    if args.copy_calibration:
+        copy_calibration(torch)
+        return
     import paper_1411_5283_amd as sw
     from paper_1411_5283_amd import wordgen
 

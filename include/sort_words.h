@@ -116,6 +116,19 @@ int sort_words_plain(const uint8_t *chars, const uint32_t *offsets,
                      uint32_t *out_perm, uint32_t *out_bucket_offsets,
                      void *workspace, size_t workspace_bytes, void *stream);
 
+/* The chunk step alone (section 4: each slave bubble-sorts its chunk; the
+ * master's merge is left out): every length list is cut into chunks of
+ * `chunk` words from its start (the last chunk shorter), and each chunk is
+ * sorted by odd-even transposition on its own.  out_perm holds, for every
+ * length list in length order, its chunks one after another, each chunk's
+ * indices in sorted order; the chunks are NOT merged.  A power of two in
+ * [2, 1024]; the tile configuration is the current sw_config's.  Arguments
+ * otherwise as sort_words_ex (one document); SYNCHRONOUS (the host reads the
+ * length histogram back, like sort_words_plain). */
+int sort_words_chunks(const uint8_t *chars, const uint32_t *offsets, uint32_t n, uint32_t chunk,
+                      uint32_t *out_perm, uint32_t *out_bucket_offsets,
+                      void *workspace, size_t workspace_bytes, void *stream);
+
 /* Baseline without length lists (the whole-file sorts of Table 2): every word
  * becomes one 32-byte key (its length in the top byte, then its bytes) and
  * the whole list is chunk-sorted and merged as one sequence.  The order is the
@@ -141,17 +154,24 @@ int sort_words_decode_status(uint32_t status_word);
 /* Persistent plan for repeated batched sorts (serving, benchmarks): owns its
  * workspace and a captured HIP graph of the whole pass, so one run is one
  * small descriptor kernel plus one hipGraphLaunch on the plan's stream.
- *   sw_plan_create  capacity max_words / max_docs; `stream` as above;
- *                   *out receives the plan (NULL on error)
- *   sw_plan_run     same arguments and result as sort_words_batch
- *                   (doc_offsets may be NULL: one document of n_words words);
- *                   asynchronous; device errors via sw_plan_status
+ *   sw_plan_create  capacity max_words words, max_docs documents and
+ *                   max_chars characters (the span offsets[N] - offsets[0]
+ *                   of a run, below 2^32); `stream` as above; *out receives
+ *                   the plan (NULL on error)
+ *   sw_plan_run     same arguments and result as sort_words_batch, plus
+ *                   n_words: doc_offsets may be NULL, and the run is then one
+ *                   document of n_words words (with doc_offsets, n_words is
+ *                   not read: the total is doc_offsets[n_docs], read on the
+ *                   device); asynchronous; a run above any capacity is
+ *                   SW_ERR_WORKSPACE (documents and, without doc_offsets,
+ *                   words checked on the host; the device checks the total
+ *                   words and characters), device errors via sw_plan_status
  *   sw_plan_status  waits for the plan's stream, returns the device status
  *   sw_plan_destroy frees the plan (waits for its stream first)
  * A plan is not thread-safe; distinct plans may be used from distinct
  * threads. */
 typedef struct sw_plan sw_plan;
-int sw_plan_create(uint32_t max_words, uint32_t max_docs, void *stream, sw_plan **out);
+int sw_plan_create(uint32_t max_words, uint32_t max_docs, uint64_t max_chars, void *stream, sw_plan **out);
 int sw_plan_run(sw_plan *plan, const uint8_t *chars, const uint32_t *offsets,
                 const uint32_t *doc_offsets, uint32_t n_docs, uint32_t n_words,
                 uint32_t *out_perm, uint32_t *out_bucket_offsets);
@@ -178,7 +198,9 @@ void sw_plan_destroy(sw_plan *plan);
 /* Tuning knobs, process-wide, read when work is enqueued (and when a plan's
  * graph is captured).  chunk[c] is the odd-even chunk size of key class c
  * (section 5: chunk size = array size / processors; here a power of two in
- * [2, 1024]); variant[c] selects a compiled tile configuration of class c
+ * [2, 1024], used as given by every tile configuration: a chunk may lie
+ * inside one thread's registers, span lanes of a wave or span waves);
+ * variant[c] selects a compiled tile configuration of class c
  * (0 .. sw_num_variants(c)-1).  Results never depend on these values. */
 typedef struct {
     uint32_t chunk[SW_NUM_CLASSES];
@@ -307,7 +329,9 @@ int sw_server_submit(sw_server *srv, const uint8_t *chars, const uint32_t *offse
                      uint32_t *out_perm, uint32_t *out_bucket_offsets, uint64_t *out_ticket);
 /* Blocks until the request completes; returns its status (a batch that failed
  * on the device fails all its requests) and its latency from submission to
- * the completion seen by the server thread.  A ticket is waited for once. */
+ * the completion seen by the server thread.  A ticket is waited for once:
+ * waiting for an unknown ticket, or for one another thread is already
+ * waiting for or has waited for, is SW_ERR_INVALID_ARG. */
 int sw_server_wait(sw_server *srv, uint64_t ticket, double *latency_s);
 int sw_server_stats(sw_server *srv, sw_server_counts *out);
 size_t sw_server_fixed_bytes(const sw_server_config *cfg);

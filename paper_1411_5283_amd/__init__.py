@@ -86,8 +86,9 @@ def lib() -> ctypes.CDLL:
         "sort_words_batch": ([vp, vp, vp, u32, vp, vp, vp, sz, vp], i32),
         "sort_words_plain": ([vp, vp, vp, u32, vp, vp, vp, sz, vp], i32),
         "sort_words_unbucketed": ([vp, vp, u32, vp, vp, vp, sz, vp], i32),
+        "sort_words_chunks": ([vp, vp, u32, u32, vp, vp, vp, sz, vp], i32),
         "sort_words_status": ([vp, vp], i32),
-        "sw_plan_create": ([u32, u32, vp, ctypes.POINTER(vp)], i32),
+        "sw_plan_create": ([u32, u32, ctypes.c_uint64, vp, ctypes.POINTER(vp)], i32),
         "sw_plan_run": ([vp, vp, vp, vp, u32, u32, vp, vp], i32),
         "sw_plan_run_text": ([vp, vp, vp, vp, u32, u32, vp, vp, i32, vp], i32),
         "sw_plan_status": ([vp], i32),
@@ -124,7 +125,8 @@ def lib() -> ctypes.CDLL:
 
 
 EXPORTED = ("sort_words", "sort_words_workspace_size", "sort_words_ex", "sort_words_batch",
-            "sort_words_plain", "sort_words_unbucketed", "sort_words_status", "sort_words_status_async",
+            "sort_words_plain", "sort_words_unbucketed", "sort_words_chunks",
+            "sort_words_status", "sort_words_status_async",
             "sort_words_decode_status", "sw_plan_create", "sw_plan_run", "sw_plan_run_text",
             "sw_plan_status", "sw_plan_status_async", "sw_plan_destroy", "sw_get_config", "sw_set_config",
             "sw_num_variants", "sw_variant_tiles", "sw_profile_enable", "sw_profile_reset",
@@ -196,6 +198,13 @@ def sort_words_unbucketed(chars, offsets, n, out_perm, out_bucket_offsets, works
                                               workspace.numel() * workspace.element_size(), _stream(stream)))
 
 
+def sort_words_chunks(chars, offsets, n, chunk, out_perm, out_bucket_offsets, workspace, stream=None) -> int:
+    """The chunk step alone: each length list's chunks of `chunk` words sorted, not merged (synchronous)."""
+    return _check(lib().sort_words_chunks(_ptr(chars), _ptr(offsets), int(n), int(chunk), _ptr(out_perm),
+                                          _ptr(out_bucket_offsets), _ptr(workspace),
+                                          workspace.numel() * workspace.element_size(), _stream(stream)))
+
+
 def sort_words_status(workspace, stream=None) -> int:
     """Device status of the last call enqueued with this workspace (raises on error)."""
     return _check(lib().sort_words_status(_ptr(workspace), _stream(stream)))
@@ -217,12 +226,12 @@ def decode_status(word: int) -> int:
 class Plan:
     """Graph-captured persistent plan (sw_plan_*)."""
 
-    def __init__(self, max_words: int, max_docs: int = 1, stream=None):
+    def __init__(self, max_words: int, max_docs: int = 1, stream=None, max_chars: int = (1 << 32) - 1):
         h = ctypes.c_void_p()
         s = None if stream is None else _stream(stream)
-        _check(lib().sw_plan_create(int(max_words), int(max_docs), s, ctypes.byref(h)))
+        _check(lib().sw_plan_create(int(max_words), int(max_docs), int(max_chars), s, ctypes.byref(h)))
         self._h = h
-        self.max_words, self.max_docs = int(max_words), int(max_docs)
+        self.max_words, self.max_docs, self.max_chars = int(max_words), int(max_docs), int(max_chars)
 
     def run(self, chars, offsets, doc_offsets, n_docs, n_words, out_perm, out_bucket_offsets) -> int:
         return _check(lib().sw_plan_run(self._h, _ptr(chars), _ptr(offsets), _ptr(doc_offsets),

@@ -114,16 +114,20 @@ struct Ws {
   KeyBuf a;             // key buffer 0 (scatter output, chunk sort in place)
   KeyBuf b;             // key buffer 1 (ping-pong for merge levels)
   uint32_t Nmax, Dmax, Bmax, Smax, SBmax;
+  uint64_t Cmax;            // characters a run may span (offsets[N] - offsets[0])
   uint32_t T[kNClass];      // chunk-sort tile (items per workgroup)
   uint32_t P[kNClass];      // merge tile
   uint32_t chunk[kNClass];  // odd-even chunk size
 };
 
 // A workgroup's work: from the device-side segment lists, or one segment given
-// directly by the host (the per-bucket-launch form).
+// directly by the host (the per-bucket-launch form).  With chunks_only (direct
+// work only) the chunk sort writes each chunk's sorted indices and stops: the
+// slaves' step of section 4 without the master's merge.
 struct TileWork {
   uint32_t direct;
   uint32_t base, n, m;
+  uint32_t chunks_only;
 };
 
 // ---------------------------------------------------------------- wave tools

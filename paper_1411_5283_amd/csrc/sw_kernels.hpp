@@ -129,6 +129,8 @@ __global__ __launch_bounds__(NT) void k_hist(Ws w) {
   const uint32_t off_lo = off[0], off_hi = off[N];
   const uint32_t rs = w.Bmax + 1;
   uint32_t flags = 0;
+  // the characters must fit the capacity the workspace was made for
+  if (blockIdx.x == 0 && off_hi >= off_lo && (uint64_t)(off_hi - off_lo) > w.Cmax) flags |= ST_WORKSPACE;
   for (uint32_t b = blockIdx.x; b < nblk; b += gridDim.x) {
     if (threadIdx.x < kNB) s_cnt[threadIdx.x] = 0;
     const BlockRange r = block_range<NT>(w, b, D, &s_doc);   // has a barrier
@@ -604,33 +606,64 @@ __global__ __launch_bounds__(NT) void k_pack_full(Ws w) {
 
 // ---------------------------------------------------------------- chunk sort
 // Odd-even transposition (the parallel form of bubble sort's adjacent
-// compare-exchanges, section 2) on chunks of C consecutive items.  Thread t of
-// a wave holds items t*E .. t*E+E-1 in registers; a chunk spans C/E lanes
-// (E <= C <= 64*E, both powers of two).  C phases sort a chunk; the loop also
-// stops early once an even and an odd phase exchange nothing anywhere in the
-// wave, bubble sort's own stopping rule.
-template <class K, int E>
+// compare-exchanges, section 2) on chunks of C consecutive items of a tile.
+// Thread t of the workgroup holds items t*E .. t*E+E-1 in registers; C is a
+// power of two in [2, NT*E], so a chunk is either inside one thread (C <= E:
+// an odd pair (2k+1, 2k+2) is skipped where 2k+2 starts a chunk), spread over
+// C/E lanes of one wave (E < C <= 64E: the neighbours at a thread edge are
+// exchanged with wave shuffles), or over C/(64E) waves (C > 64E: the
+// neighbours at a wave edge go through LDS, two barriers a phase).  C phases
+// sort a chunk; the loop also stops early once an even and an odd phase
+// exchange nothing (in the wave, or in the workgroup when chunks span waves),
+// bubble sort's own stopping rule.  Every thread of the workgroup must call
+// it with the same C.
+template <int NT, class K, int E>
 __device__ inline void oddeven_chunks(K (&e)[E], uint32_t C) {
-  const uint32_t lane = __lane_id();
-  const bool cross = C > (uint32_t)E;
-  const bool has_next = cross && (((lane + 1) * E) & (C - 1)) != 0;
-  const bool has_prev = cross && ((lane * E) & (C - 1)) != 0;
-  for (uint32_t p = 0; p < C; p += 2) {
+  constexpr int NW = NT / 64;
+  __shared__ K s_first[NW], s_last[NW];
+  __shared__ uint32_t s_any[2];
+  const uint32_t lane = __lane_id(), wave = threadIdx.x >> 6;
+  const bool cross = C > (uint32_t)E;             // chunks span threads
+  const bool waves = C > 64u * E;                 // ... and waves (block-uniform)
+  const uint32_t first = threadIdx.x * E;          // tile index of this thread's first item
+  const bool has_next = cross && threadIdx.x + 1 < (uint32_t)NT && ((first + E) & (C - 1)) != 0;
+  const bool has_prev = cross && threadIdx.x > 0 && (first & (C - 1)) != 0;
+  if (waves && threadIdx.x == 0) s_any[0] = 0;
+  for (uint32_t p = 0, par = 0; p < C; p += 2, par ^= 1) {
     bool sw = false;
 #pragma unroll
     for (int j = 0; j + 1 < E; j += 2) sw |= e_cmp_xchg(e[j], e[j + 1]);
 #pragma unroll
-    for (int j = 1; j + 1 < E; j += 2) sw |= e_cmp_xchg(e[j], e[j + 1]);
+    for (int j = 1; j + 1 < E; j += 2)
+      if (cross || ((uint32_t)(j + 1) & (C - 1)) != 0) sw |= e_cmp_xchg(e[j], e[j + 1]);
     if (cross) {
-      const K nx = e_shfl(e[0], (int)min(lane + 1, 63u));
-      const K pv = e_shfl(e[E - 1], (int)(lane ? lane - 1 : 0u));
+      K nx = e_shfl(e[0], (int)min(lane + 1, 63u));
+      K pv = e_shfl(e[E - 1], (int)(lane ? lane - 1 : 0u));
+      if (waves) {
+        if (lane == 0) s_first[wave] = e[0];
+        if (lane == 63) s_last[wave] = e[E - 1];
+        __syncthreads();
+        // every thread has read the previous iteration's flag before this
+        // barrier, so its slot may be cleared for the next iteration
+        if (threadIdx.x == 0) s_any[par ^ 1] = 0;
+        if (lane == 63 && wave + 1 < (uint32_t)NW) nx = s_first[wave + 1];
+        if (lane == 0 && wave > 0) pv = s_last[wave - 1];
+      }
+      // without `waves`, lane 63 never has its next item in its chunk (64E is
+      // a multiple of C), nor lane 0 its previous one
       if (has_next && e_less(nx, e[E - 1])) {
         e[E - 1] = nx;
         sw = true;
       }
       if (has_prev && e_less(e[0], pv)) e[0] = pv;
     }
-    if (!__any(sw)) break;
+    if (waves) {
+      if (__any(sw) && lane == 0) atomicOr(&s_any[par], 1u);
+      __syncthreads();
+      if (!s_any[par]) break;   // the same value in every thread
+    } else if (!__any(sw)) {
+      break;
+    }
   }
 }
 
@@ -750,18 +783,25 @@ __device__ inline void padded_register_merge(const Tile& t, int la, int lb, int 
 
 // Sorting core of a tile held as E items per thread in registers (blocked:
 // thread t holds items t*E..t*E+E-1 of the tile): odd-even transposition on
-// chunks of C, then merge-path rounds through LDS until one run covers the
-// tile's cnt real items (the rest of the tile is sentinels, already in place).
+// chunks of C, then (unless only the chunks are wanted) the merge of the
+// sorted chunks -- inside a thread's registers while runs are shorter than E,
+// then merge-path rounds through LDS until one run covers the tile's cnt real
+// items (the rest of the tile is sentinels, already in place).
 // In the round that merges runs of R, item i sits in slot i + i/R: every run
 // is followed by a sentinel slot, so the serial merge reads one slot per
 // output without a bounds test (its positions only stop at the run's
 // sentinel).  The tile must hold T + T/E slots.
 template <int NT, int E, int MM, class Tile>
-__device__ inline void sort_tile_core(Tile& tile, typename Tile::value_type (&e)[E], uint32_t C, uint32_t cnt) {
+__device__ inline void sort_tile_core(Tile& tile, typename Tile::value_type (&e)[E], uint32_t C, uint32_t cnt,
+                                      bool merge = true) {
   using K = typename Tile::value_type;
   constexpr int T = NT * E;
-  oddeven_chunks(e, C);
-  for (uint32_t R = C; R < (uint32_t)T && R < cnt; R <<= 1) {
+  oddeven_chunks<NT>(e, C);
+  if (!merge) return;
+  // runs of C inside a thread are merged there by the same transposition on
+  // all E items (the merge strategy is free: the result is unique)
+  if (C < (uint32_t)E) oddeven_chunks<NT>(e, (uint32_t)E);
+  for (uint32_t R = C < (uint32_t)E ? (uint32_t)E : C; R < (uint32_t)T && R < cnt; R <<= 1) {
     const int lr = __ffs((int)R) - 1;   // R is a power of two, at least E
     const int o = threadIdx.x * E;
     const int g = o + (o >> lr);        // a thread's E items lie inside one run
@@ -860,8 +900,7 @@ __global__ __launch_bounds__(NT) void k_sort_tiles(Ws w, int cls, TileWork tw) {
   __shared__ LdsTile<NL, T + T / E> tile;
   Header* h = w.h;
   if (h->abort) return;
-  uint32_t C = w.chunk[cls];
-  C = C < (uint32_t)E ? (uint32_t)E : (C > 64u * E ? 64u * E : C);
+  const uint32_t C = w.chunk[cls];   // a power of two in [2, 1024], at most T
   uint32_t ntiles, cstart = 0, ccount = 0;
   const uint32_t* st = nullptr;
   if (tw.direct) {
@@ -885,7 +924,9 @@ __global__ __launch_bounds__(NT) void k_sort_tiles(Ws w, int cls, TileWork tw) {
     }
     const uint32_t lo = g.j * T;
     const uint32_t cnt = min((uint32_t)T, g.n - lo);
-    const bool final = g.n <= (uint32_t)T;
+    // only the chunks: every tile writes its chunk-sorted indices (the
+    // segment's runs of C are not merged)
+    const bool final = g.n <= (uint32_t)T || tw.chunks_only;
     const size_t gb = (size_t)g.base + lo;
 #pragma unroll
     for (int r = 0; r < E; ++r) {
@@ -896,7 +937,7 @@ __global__ __launch_bounds__(NT) void k_sort_tiles(Ws w, int cls, TileWork tw) {
     Key<NL> e[E];
 #pragma unroll
     for (int r = 0; r < E; ++r) e[r] = tile.get(threadIdx.x * E + r);
-    sort_tile_core<NT, E, MM>(tile, e, C, cnt);
+    sort_tile_core<NT, E, MM>(tile, e, C, cnt, !tw.chunks_only);
     __syncthreads();
 #pragma unroll
     for (int r = 0; r < E; ++r) tile.put(threadIdx.x * E + r, e[r]);
@@ -907,7 +948,7 @@ __global__ __launch_bounds__(NT) void k_sort_tiles(Ws w, int cls, TileWork tw) {
       if (i < cnt) {
         const Key<NL> v = tile.get(i);
         if (final) out_perm[gb + i] = key_index<NL>(v);
-        if (!final || keep) gstore<NL>(w.a, gb + i, v);
+        if ((!final || keep) && !tw.chunks_only) gstore<NL>(w.a, gb + i, v);
       }
     }
     __syncthreads();
@@ -933,8 +974,7 @@ __global__ __launch_bounds__(kPackTile / E) void k_sort_packed(Ws w, int cls) {
   __shared__ uint32_t s_rng[3];
   Header* h = w.h;
   if (h->abort) return;
-  uint32_t C = w.chunk[cls];
-  C = C < (uint32_t)E ? (uint32_t)E : (C > 64u * E ? 64u * E : C);
+  const uint32_t C = w.chunk[cls];   // a power of two in [2, 1024], at most kPackTile
   const uint32_t ps = h->pack_start[cls];
   const uint32_t npack = h->cls_start[cls + 1] - ps;
   const uint32_t* vp = w.vpre + ps + cls;     // npack + 1 entries

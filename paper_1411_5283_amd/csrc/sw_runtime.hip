@@ -78,6 +78,7 @@ struct V {
   }
   static Variant get() {
     static_assert(NTM * EM <= 2 * NTS * ES, "merge tile must divide a pair of sorted tiles");
+    static_assert(NTS * ES >= 1024 && sw::kPackTile >= 1024, "a chunk of up to 1024 items fits every tile");
     return Variant{sort, packed, merge, (const void*)sw::k_sort_tiles<NL, NTS, ES, MM>,
                    (const void*)sw::k_merge<NL, NTM, EM, MM>, (uint32_t)(NTS * ES), (uint32_t)(NTM * EM), NTS, NTM};
   }
@@ -214,9 +215,10 @@ uint64_t capacity_for(size_t bytes, uint64_t Dmax) {
   return lo;
 }
 
-Ws make_ws(void* base, const Layout& L, const sw_config& cfg) {
+Ws make_ws(void* base, const Layout& L, const sw_config& cfg, uint64_t max_chars = ~0ull) {
   char* p = (char*)base;
   Ws w;
+  w.Cmax = max_chars;
   w.h = (Header*)(p + L.o_hdr);
   w.doc_off = (uint32_t*)(p + L.o_doc_off);
   w.doc_blk = (uint32_t*)(p + L.o_doc_blk);
@@ -466,7 +468,7 @@ int enqueue_body(const Ws& w, const Grids& g, hipStream_t s, bool capture, bool 
     HIP_TRY(hipEventRecord(fork->fork, s));
     for (int c = 1; c < sw::kNClass; ++c) HIP_TRY(hipStreamWaitEvent(fork->side[c], fork->fork, 0));
   }
-  const TileWork none{0, 0, 0, 0};
+  const TileWork none{0, 0, 0, 0, 0};
   // Each class keeps its own order on its own stream; across classes the work
   // is enqueued stage by stage (all chunk sorts, then merge level 0 of every
   // class, level 1, ...), so that a runtime which maps the parallel chains
@@ -682,7 +684,7 @@ int sort_words_plain(const uint8_t* chars, const uint32_t* offsets, const uint32
     const int c = sw::class_of_len((uint32_t)(sidx % sw::kNB));
     const Variant& v = *g.var[c];
     const uint32_t m = sw::levels_for(n, v.T);
-    const TileWork tw{1, seg_base[sidx], n, m};
+    const TileWork tw{1, seg_base[sidx], n, m, 0};
     {
       ProfScope p(K_SORT0 + c, s, false);
       v.sort(w, c, tw, (n + v.T - 1) / v.T, s);
@@ -692,6 +694,43 @@ int sort_words_plain(const uint8_t* chars, const uint32_t* offsets, const uint32
       ProfScope p(K_MERGE0 + c, s, false);
       v.merge(w, c, (int)l, tw, mtiles, s);
     }
+  }
+  HIP_TRY(hipGetLastError());
+  return read_status(workspace, s);
+}
+
+int sort_words_chunks(const uint8_t* chars, const uint32_t* offsets, uint32_t n, uint32_t chunk,
+                      uint32_t* out_perm, uint32_t* out_bucket_offsets, void* workspace, size_t workspace_bytes,
+                      void* stream) {
+  if (!offsets || !out_bucket_offsets || !workspace || (n && !out_perm))
+    return fail(SW_ERR_INVALID_ARG, "sort_words_chunks: null pointer argument");
+  if (chunk < 2 || chunk > 1024 || (chunk & (chunk - 1)))
+    return fail(SW_ERR_INVALID_ARG, "sort_words_chunks: chunk %u is not a power of two in [2,1024]", chunk);
+  Layout L;
+  if (!make_layout(n, 1, L)) return fail(SW_ERR_INVALID_ARG, "sort_words_chunks: n out of range");
+  if (L.total > workspace_bytes)
+    return fail(SW_ERR_WORKSPACE, "sort_words_chunks: workspace of %zu bytes, need %zu", workspace_bytes, L.total);
+  hipStream_t s = (hipStream_t)stream;
+  sw_config cfg = current_config();
+  for (int c = 0; c < sw::kNClass; ++c) cfg.chunk[c] = chunk;
+  const Ws w = make_ws(workspace, L, cfg);
+  Grids g;
+  int rc = make_grids(w, cfg, g);
+  if (rc) return rc;
+  RunDesc d{chars, offsets, nullptr, out_perm, out_bucket_offsets, n, 1};
+  if ((rc = enqueue_begin(w, d, s))) return rc;
+  if ((rc = enqueue_body(w, g, s, false, true))) return rc;
+  if ((rc = read_status(workspace, s))) return rc;
+  std::vector<uint32_t> seg_n(sw::kNB), seg_base(sw::kNB);
+  HIP_TRY(hipMemcpy(seg_n.data(), w.seg_n, 4 * sw::kNB, hipMemcpyDeviceToHost));
+  HIP_TRY(hipMemcpy(seg_base.data(), w.seg_base, 4 * sw::kNB, hipMemcpyDeviceToHost));
+  for (int len = 0; len < sw::kNB; ++len) {
+    const uint32_t m = seg_n[len];
+    if (!m) continue;
+    const int c = sw::class_of_len((uint32_t)len);
+    const Variant& v = *g.var[c];
+    const TileWork tw{1, seg_base[len], m, 0, 1};
+    v.sort(w, c, tw, (m + v.T - 1) / v.T, s);
   }
   HIP_TRY(hipGetLastError());
   return read_status(workspace, s);
@@ -726,7 +765,7 @@ int sort_words_unbucketed(const uint8_t* chars, const uint32_t* offsets, uint32_
     constexpr int c = sw::kNClass - 1;
     const Variant& v = *g.var[c];
     const uint32_t m = sw::levels_for(n, v.T);
-    const TileWork tw{1, 0, n, m};
+    const TileWork tw{1, 0, n, m, 0};
     v.sort(w, c, tw, (n + v.T - 1) / v.T, s);
     const uint32_t mtiles = (n + v.P - 1) / v.P;
     for (uint32_t l = 0; l < m; ++l)
@@ -786,9 +825,10 @@ static int plan_capture(sw_plan* p, bool text, hipGraph_t* graph_out, hipGraphEx
   return SW_OK;
 }
 
-int sw_plan_create(uint32_t max_words, uint32_t max_docs, void* stream, sw_plan** out) {
+int sw_plan_create(uint32_t max_words, uint32_t max_docs, uint64_t max_chars, void* stream, sw_plan** out) {
   if (!out) return fail(SW_ERR_INVALID_ARG, "sw_plan_create: null out");
   *out = nullptr;
+  if (max_chars >= (1ull << 32)) return fail(SW_ERR_INVALID_ARG, "sw_plan_create: max_chars must be below 2^32");
   sw_plan* p = new sw_plan();
   if (!make_layout(max_words, max_docs, p->L)) {
     delete p;
@@ -810,7 +850,7 @@ int sw_plan_create(uint32_t max_words, uint32_t max_docs, void* stream, sw_plan*
     return fail(SW_ERR_OOM, "sw_plan_create: cannot allocate %zu bytes", p->L.total);
   }
   const sw_config cfg = current_config();
-  p->w = make_ws(p->ws, p->L, cfg);
+  p->w = make_ws(p->ws, p->L, cfg, max_chars);
   int rc = make_grids(p->w, cfg, p->g);
   if (!rc) rc = fork_init(p->fork);
   if (!rc) rc = plan_capture(p, false, &p->graph, &p->exec);
@@ -1202,7 +1242,7 @@ struct sw_server {
   std::mutex mu;
   std::condition_variable cv_in, cv_done;
   std::deque<swsrv::Request*> intake;
-  std::unordered_map<uint64_t, swsrv::Request*> live;
+  swsrv::TicketBook live;
   swsrv::Counters counters;
   uint64_t next_ticket = 1;
   bool stop = false;
@@ -1257,8 +1297,7 @@ static void server_free(sw_server* sv) {
       if (h) (void)hipHostFree(h);
     if (sl.s) (void)hipStreamDestroy(sl.s);
   }
-  for (auto& kv : sv->live) delete kv.second;
-  delete sv;
+  delete sv;   // the ticket book frees the requests never waited for
 }
 
 extern "C" {
@@ -1297,7 +1336,7 @@ int sw_server_create(const sw_server_config* cfg, sw_server** out) {
     if (hipStreamCreateWithFlags(&sl.s, hipStreamNonBlocking) != hipSuccess ||
         hipEventCreateWithFlags(&sl.ev, hipEventDisableTiming) != hipSuccess)
       return cleanup(fail(SW_ERR_HIP, "sw_server_create: stream or event creation failed"));
-    int rc = sw_plan_create((uint32_t)W, (uint32_t)D, sl.s, &sl.plan);
+    int rc = sw_plan_create((uint32_t)W, (uint32_t)D, C, sl.s, &sl.plan);
     if (rc) return cleanup(rc);
     if (hipMalloc(&sl.d_chars, C) != hipSuccess || hipMalloc(&sl.d_offsets, 4 * (W + 1)) != hipSuccess ||
         hipMalloc(&sl.d_docs, 4 * (D + 1)) != hipSuccess || hipMalloc(&sl.d_perm, 4 * W) != hipSuccess ||
@@ -1340,7 +1379,7 @@ int sw_server_submit(sw_server* sv, const uint8_t* chars, const uint32_t* offset
     std::lock_guard<std::mutex> lk(sv->mu);
     r->ticket = sv->next_ticket++;
     r->arrival = srv_now();
-    sv->live[r->ticket] = r;
+    sv->live.add(r);
     sv->intake.push_back(r);
     *out_ticket = r->ticket;
   }
@@ -1351,15 +1390,14 @@ int sw_server_submit(sw_server* sv, const uint8_t* chars, const uint32_t* offset
 int sw_server_wait(sw_server* sv, uint64_t ticket, double* latency_s) {
   if (!sv) return fail(SW_ERR_INVALID_ARG, "sw_server_wait: null server");
   std::unique_lock<std::mutex> lk(sv->mu);
-  auto it = sv->live.find(ticket);
-  if (it == sv->live.end()) return fail(SW_ERR_INVALID_ARG, "sw_server_wait: unknown ticket %llu",
-                                        (unsigned long long)ticket);
-  swsrv::Request* r = it->second;
+  swsrv::Request* r = nullptr;
+  if (sv->live.claim(ticket, &r))
+    return fail(SW_ERR_INVALID_ARG, "sw_server_wait: ticket %llu is unknown or already waited for",
+                (unsigned long long)ticket);
   sv->cv_done.wait(lk, [r] { return r->finished; });
   const int st = r->status;
   if (latency_s) *latency_s = r->done - r->arrival;
-  sv->live.erase(it);
-  delete r;
+  sv->live.release(ticket);
   return st ? fail(st, "sw_server_wait: the request's batch failed") : SW_OK;
 }
 

@@ -22,6 +22,7 @@
 #include <algorithm>
 #include <cstdint>
 #include <deque>
+#include <unordered_map>
 #include <vector>
 
 namespace swsrv {
@@ -38,6 +39,37 @@ struct Request {
   double arrival = 0, start = 0, done = 0;
   int status = 0;
   bool finished = false;            // set by the serving thread under its lock
+  bool claimed = false;             // a caller is waiting for it
+};
+
+// The requests that have a ticket and have not been waited for.  A ticket is
+// claimed by one waiter; a second claim, or a claim of an unknown ticket, is
+// refused (the caller's lock guards every call).
+class TicketBook {
+ public:
+  ~TicketBook() {
+    for (auto& kv : live_) delete kv.second;
+  }
+  void add(Request* r) { live_[r->ticket] = r; }
+  // 0 and the request on success; -1 for an unknown or already claimed ticket
+  int claim(uint64_t ticket, Request** out) {
+    auto it = live_.find(ticket);
+    if (it == live_.end() || it->second->claimed) return -1;
+    it->second->claimed = true;
+    *out = it->second;
+    return 0;
+  }
+  // the claimed request is done with: forgotten and freed
+  void release(uint64_t ticket) {
+    auto it = live_.find(ticket);
+    if (it == live_.end()) return;
+    delete it->second;
+    live_.erase(it);
+  }
+  size_t size() const { return live_.size(); }
+
+ private:
+  std::unordered_map<uint64_t, Request*> live_;
 };
 
 struct Batch {

@@ -6,7 +6,8 @@
 
 ``traffic`` averages FETCH_SIZE and WRITE_SIZE (KiB per dispatch) per kernel
 family and scales them by what the same counters read for a plain 1 GiB
-device copy (hbm_copy_probe.py), so that the result is HBM bytes per launch.
+device copy (``bench.py --copy-calibration``), so that the result is HBM
+bytes per launch.
 The sort's kernels come from a run without the text steps (a run that writes
 text also keeps the sorted keys in the last merge level, which changes that
 level's traffic); the text kernels, found only in the second pair, from a run
@@ -31,9 +32,9 @@ COMMANDS = [
     "rocprofv3 --pmc WRITE_SIZE --output-format csv -d gpurun_out/pmc_write_t -o w -- python3 bench.py "
     "--serial --steps 1 --warmup 1 --profile-steps 1 --no-plain --no-cpu-baseline --no-check",
     "rocprofv3 --pmc FETCH_SIZE --output-format csv -d gpurun_out/pmc_copyf -o cf -- python3 "
-    "paper_1411_5283_amd/hbm_copy_probe.py",
+    "bench.py --copy-calibration",
     "rocprofv3 --pmc WRITE_SIZE --output-format csv -d gpurun_out/pmc_copyw -o cw -- python3 "
-    "paper_1411_5283_amd/hbm_copy_probe.py",
+    "bench.py --copy-calibration",
 ]
 
 

@@ -284,7 +284,7 @@ class GpuExecutor:
             s = torch.cuda.Stream(device=self.device)
             slot = {
                 "stream": s,
-                "plan": Plan(self.max_words, self.max_docs, stream=s),
+                "plan": Plan(self.max_words, self.max_docs, stream=s, max_chars=self.max_chars),
                 "chars": torch.empty(max(self.max_chars, 1), dtype=torch.uint8, device=self.device),
                 "offsets": torch.empty(self.max_words + 1, dtype=torch.int32, device=self.device),
                 "docs": torch.empty(self.max_docs + 1, dtype=torch.int32, device=self.device),

@@ -181,6 +181,26 @@ int main() {
     CHECK(swsrv::check_request(lng, 2, 32) == -2, "33-byte word accepted");
     CHECK(swsrv::check_request(ok, 0, 32) == 0, "empty request refused");
   }
+  // 5. tickets: one waiter per ticket; a second claim, or a claim after the
+  // wait, is refused; requests never waited for are freed with the book
+  {
+    swsrv::TicketBook book;
+    std::vector<uint32_t> st;
+    for (uint64_t t = 1; t <= 3; ++t) book.add(make(t, 4, 0, st));
+    Request* r = nullptr;
+    CHECK(book.claim(2, &r) == 0 && r && r->ticket == 2, "first claim refused");
+    Request* r2 = nullptr;
+    CHECK(book.claim(2, &r2) != 0 && r2 == nullptr, "second waiter of one ticket accepted");
+    CHECK(book.claim(9, &r2) != 0, "unknown ticket accepted");
+    book.release(2);
+    CHECK(book.claim(2, &r2) != 0, "a ticket waited for twice");
+    CHECK(book.size() == 2, "book holds %zu requests, expected 2", book.size());
+    // a claim keeps the request alive until its release, whatever else is added
+    CHECK(book.claim(3, &r) == 0, "claim of ticket 3 refused");
+    for (uint64_t t = 10; t < 2000; ++t) book.add(make(t, 1, 0, st));
+    CHECK(r->ticket == 3 && r->claimed, "claimed request changed");
+    book.release(3);
+  }
   std::printf("OK\n");
   return 0;
 }

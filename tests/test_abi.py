@@ -51,6 +51,13 @@ def test_host_side_calls_without_gpu():
     assert L.sort_words_ex(None, None, 0, None, None, None, 0, None) == sw.ERR_INVALID_ARG
     assert L.sort_words_batch(None, None, None, 1, None, None, None, 0, None) == sw.ERR_INVALID_ARG
     assert b"null" in L.sort_words_last_error()
+    # the chunk step checks its chunk size before any device call
+    dummy = ctypes.create_string_buffer(64)
+    p = ctypes.addressof(dummy)
+    assert L.sort_words_chunks(p, p, 3, 3, p, p, p, 1 << 20, None) == sw.ERR_INVALID_ARG
+    assert b"power of two" in L.sort_words_last_error()
+    assert L.sort_words_chunks(p, p, 3, 2048, p, p, p, 1 << 20, None) == sw.ERR_INVALID_ARG
+
     # config validation
     cfg = sw.sw_config()
     assert L.sw_get_config(ctypes.byref(cfg)) == 0

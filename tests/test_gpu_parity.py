@@ -71,14 +71,52 @@ def test_config1_bit_exact(gpu, oracle_mod):
     _same(gpu.sort_wordlist(wl), _expect(oracle_mod, wl), "config1")
 
 
-def test_config2_chunk1024_bit_exact(gpu, oracle_mod, default_config):
+@pytest.mark.parametrize("variant", [0, 1])
+def test_config2_chunk1024_bit_exact(gpu, oracle_mod, default_config, variant):
+    # 1024-word odd-even chunks in every class, as configured: variant 0 holds
+    # 8 items per thread in classes 2 and 3 (a chunk spans two waves), variant 1
+    # 8 in classes 0-2 and 16 in class 3 (a chunk spans one wave); the short
+    # segments' tiles always hold 8 per thread
     wl = wordgen.config(2)
-    _say("case config2 n=%d chunk=1024" % wl.n)
-    gpu.set_config(chunk=[1024] * 4, variant=[0] * 4)
+    _say("case config2 n=%d chunk=1024 variant=%d" % (wl.n, variant))
+    cfg = gpu.set_config(chunk=[1024] * 4, variant=[variant] * 4)
+    assert cfg["chunk"] == [1024] * 4
     _same(gpu.sort_wordlist(wl), _expect(oracle_mod, wl, bubble=False), "config2")
 
 
-@pytest.mark.parametrize("chunk", [16, 32, 64, 128, 256, 512, 1024])
+def _chunk_step_words():
+    # a few long lists (several tiles of every variant), short ones, ragged tails
+    wl = wordgen.single(70_000, 2500, 1.0, 32, seed=31)
+    return wl
+
+
+CHUNK_WL = None
+
+
+@pytest.mark.parametrize("chunk", [2, 4, 8, 16, 32, 64, 128, 256, 512, 1024])
+@pytest.mark.parametrize("variant", [0, 1, 2, 3, 4, 5, 6])
+def test_chunk_step_bit_exact(gpu, oracle_mod, default_config, chunk, variant):
+    # the chunk step alone (odd-even transposition on each chunk of C, no
+    # merge) against the oracle's bubble sort of each chunk: every chunk size
+    # runs as given, inside a thread, across lanes and across waves
+    import torch
+    global CHUNK_WL
+    if CHUNK_WL is None:
+        CHUNK_WL = _chunk_step_words()
+    wl = CHUNK_WL
+    var = [min(variant, gpu.num_variants(c) - 1) for c in range(4)]
+    _say("case chunk step chunk=%d variant=%s n=%d" % (chunk, var, wl.n))
+    gpu.set_config(variant=var)
+    chars, offs, _ = gpu.device_words(wl, "cuda")
+    perm = torch.empty(wl.n, dtype=torch.int32, device="cuda")
+    boff = torch.empty(34, dtype=torch.int32, device="cuda")
+    ws = torch.empty(gpu.sort_words_workspace_size(wl.n, 1), dtype=torch.uint8, device="cuda")
+    gpu.sort_words_chunks(chars, offs, wl.n, chunk, perm, boff, ws)
+    _same((gpu.to_u32(perm), gpu.to_u32(boff)), oracle_mod.oracle_chunks(wl.chars, wl.offsets, chunk),
+          "chunk step %d variant %s" % (chunk, var))
+
+
+@pytest.mark.parametrize("chunk", [2, 4, 8, 16, 32, 64, 128, 256, 512, 1024])
 @pytest.mark.parametrize("variant", [0, 1, 2, 3, 4, 5, 6])
 def test_chunk_and_variant_sweep(gpu, oracle_mod, default_config, chunk, variant):
     # several tiles, merge levels and a ragged tail in every class
@@ -224,6 +262,18 @@ def test_device_detected_errors(gpu):
     d = torch.tensor(np.asarray([0, 100], np.uint32).view(np.int32), device="cuda")
     gpu.sort_words_batch(chars, o100, d, 1, perm100, boff, ws_small)
     assert gpu.sort_words_status_code(ws_small) == gpu.ERR_WORKSPACE
+    # a plan made for 200 characters: ten words of 30 bytes (300 characters)
+    # are SW_ERR_WORKSPACE, six (180, starting at byte 150) sort
+    plan = gpu.Plan(64, 1, max_chars=200)
+    big_chars = torch.zeros(400, dtype=torch.uint8, device="cuda")
+    try:
+        for offs_np, code in ((np.arange(0, 301, 30), gpu.ERR_WORKSPACE), (np.arange(150, 331, 30), gpu.OK)):
+            o = torch.tensor(offs_np.astype(np.uint32).view(np.int32), device="cuda")
+            nw = len(offs_np) - 1
+            plan.run(big_chars, o, None, 1, nw, perm100, boff)
+            assert plan.status_code() == code, offs_np
+    finally:
+        plan.close()
     # after errors the library still sorts correctly
     wl = wordgen.from_words([b"b", b"a"])
     p, b = gpu.sort_wordlist(wl)
