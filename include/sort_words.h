@@ -87,6 +87,27 @@ int sort_words_ex(const uint8_t *chars, const uint32_t *offsets, uint32_t n,
                   uint32_t *out_perm, uint32_t *out_bucket_offsets,
                   void *workspace, size_t workspace_bytes, void *stream);
 
+/* For callers that cannot allocate device memory (code under graph capture,
+ * tight serving loops, harnesses that forbid hipMalloc): sort_words_ex with
+ * the library's own fixed scratch array as its workspace.  It calls no
+ * hipMalloc, hipFree or other allocating routine, and every kernel goes on
+ * `stream` in order (no side streams, no events).
+ *   out_status  device, 1 word: receives the device status word of the run
+ *               (0 when it sorted; sort_words_decode_status() turns it into
+ *               an sw_status), written on `stream` after the sort
+ * The scratch is SW_NOALLOC_SCRATCH_BYTES of device memory, one copy per
+ * GPU, held from the library's load until the process ends.  n is limited to
+ * the largest count whose sort_words_workspace_size(n, 1) fits it (about 460
+ * thousand words); a larger n is SW_ERR_WORKSPACE, returned at once.  Every
+ * call on one GPU uses that GPU's one scratch, which keeps the last call's
+ * contents (each call rewrites what it reads): calls that overlap on one GPU
+ * (two streams or two threads) race, so the caller must serialize them.
+ * Other arguments as sort_words_ex; asynchronous. */
+#define SW_NOALLOC_SCRATCH_BYTES (32u << 20)
+int sort_words_noalloc(const uint8_t *chars, const uint32_t *offsets, uint32_t n,
+                       uint32_t *out_perm, uint32_t *out_bucket_offsets,
+                       uint32_t *out_status, void *stream);
+
 /* Batched form: n_docs independent documents sorted in one pass; every
  * (document, length) pair is one segment (section 3.2: each sub-array is
  * given to its own worker).

@@ -87,6 +87,7 @@ def lib() -> ctypes.CDLL:
         "sort_words_plain": ([vp, vp, vp, u32, vp, vp, vp, sz, vp], i32),
         "sort_words_unbucketed": ([vp, vp, u32, vp, vp, vp, sz, vp], i32),
         "sort_words_chunks": ([vp, vp, u32, u32, vp, vp, vp, sz, vp], i32),
+        "sort_words_noalloc": ([vp, vp, u32, vp, vp, vp, vp], i32),
         "sort_words_status": ([vp, vp], i32),
         "sw_plan_create": ([u32, u32, ctypes.c_uint64, vp, ctypes.POINTER(vp)], i32),
         "sw_plan_run": ([vp, vp, vp, vp, u32, u32, vp, vp], i32),
@@ -125,7 +126,7 @@ def lib() -> ctypes.CDLL:
 
 
 EXPORTED = ("sort_words", "sort_words_workspace_size", "sort_words_ex", "sort_words_batch",
-            "sort_words_plain", "sort_words_unbucketed", "sort_words_chunks",
+            "sort_words_plain", "sort_words_unbucketed", "sort_words_chunks", "sort_words_noalloc",
             "sort_words_status", "sort_words_status_async",
             "sort_words_decode_status", "sw_plan_create", "sw_plan_run", "sw_plan_run_text",
             "sw_plan_status", "sw_plan_status_async", "sw_plan_destroy", "sw_get_config", "sw_set_config",
@@ -173,6 +174,16 @@ def sort_words_ex(chars, offsets, n, out_perm, out_bucket_offsets, workspace, st
     return _check(lib().sort_words_ex(_ptr(chars), _ptr(offsets), int(n), _ptr(out_perm),
                                       _ptr(out_bucket_offsets), _ptr(workspace),
                                       workspace.numel() * workspace.element_size(), _stream(stream)))
+
+
+NOALLOC_SCRATCH_BYTES = 32 << 20
+
+
+def sort_words_noalloc(chars, offsets, n, out_perm, out_bucket_offsets, out_status, stream=None) -> int:
+    """sort_words_ex on the library's fixed scratch (no allocation; asynchronous).
+    out_status: a 1-element int32 device tensor that receives the device status word."""
+    return _check(lib().sort_words_noalloc(_ptr(chars), _ptr(offsets), int(n), _ptr(out_perm),
+                                           _ptr(out_bucket_offsets), _ptr(out_status), _stream(stream)))
 
 
 def sort_words_batch(chars, offsets, doc_offsets, n_docs, out_perm, out_bucket_offsets, workspace,

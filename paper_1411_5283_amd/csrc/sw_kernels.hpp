@@ -44,6 +44,12 @@ __global__ void k_begin(Ws w, RunDesc d) {
   }
 }
 
+// The run's status word, copied out for a caller that has no access to the
+// workspace.
+__global__ void k_status_out(Ws w, uint32_t* dst) {
+  if (threadIdx.x == 0) *dst = w.h->status;
+}
+
 // ---------------------------------------------------------------- k_doc_plan
 // One workgroup.  Copies (or synthesizes) the document offsets, validates
 // them, and gives every document ceil(words / kWordsPerBlock) word blocks.

@@ -571,6 +571,35 @@ Cache g_cache[64];
 
 }  // namespace
 
+// Workspace of sort_words_noalloc: a fixed array in device memory, one copy
+// per GPU, held until the process ends.  Host code never uses its name as an
+// address (on the host the name is only a stand-in): the device address comes
+// from hipGetSymbolAddress, once per device, with that device current.
+static __device__ __align__(256) uint8_t scratch[SW_NOALLOC_SCRATCH_BYTES];
+
+namespace {
+
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[64];
+
+int scratch_address(void** out) {
+  int dev = 0;
+  HIP_TRY(hipGetDevice(&dev));
+  if (dev < 0 || dev >= 64) return fail(SW_ERR_HIP, "device id %d out of range", dev);
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !p)
+      return fail(SW_ERR_HIP, "hipGetSymbolAddress(scratch): %s", hipGetErrorString(e));
+    g_scratch_ptr[dev] = p;
+  }
+  *out = g_scratch_ptr[dev];
+  return SW_OK;
+}
+
+}  // namespace
+
 // =================================================================== C ABI
 extern "C" {
 
@@ -581,6 +610,34 @@ size_t sort_words_workspace_size(uint32_t max_words, uint32_t max_docs) {
   Layout L;
   if (!make_layout(max_words, max_docs, L)) return 0;
   return L.total;
+}
+
+int sort_words_noalloc(const uint8_t* chars, const uint32_t* offsets, uint32_t n, uint32_t* out_perm,
+                       uint32_t* out_bucket_offsets, uint32_t* out_status, void* stream) {
+  if (!offsets || !out_bucket_offsets || !out_status || (n && !out_perm))
+    return fail(SW_ERR_INVALID_ARG, "sort_words_noalloc: null pointer argument");
+  Layout L;
+  if (!make_layout(n, 1, L)) return fail(SW_ERR_INVALID_ARG, "sort_words_noalloc: n out of range");
+  if (L.total > SW_NOALLOC_SCRATCH_BYTES)
+    return fail(SW_ERR_WORKSPACE, "sort_words_noalloc: %u words need %zu bytes of workspace; the scratch holds %u "
+                "(at most %llu words)", n, L.total, (unsigned)SW_NOALLOC_SCRATCH_BYTES,
+                (unsigned long long)capacity_for(SW_NOALLOC_SCRATCH_BYTES, 1));
+  void* ws = nullptr;
+  int rc = scratch_address(&ws);
+  if (rc) return rc;
+  const sw_config cfg = current_config();
+  const Ws w = make_ws(ws, L, cfg);
+  Grids g;
+  if ((rc = make_grids(w, cfg, g))) return rc;
+  hipStream_t s = (hipStream_t)stream;
+  const RunDesc d{chars, offsets, nullptr, out_perm, out_bucket_offsets, n, 1};
+  sw::k_begin<<<1, 64, 0, s>>>(w, d);
+  // every kernel on the caller's stream, in order (no side streams, no events,
+  // no timing), so the call may also be captured into a graph
+  if ((rc = enqueue_body(w, g, s, true, false, nullptr))) return rc;
+  sw::k_status_out<<<1, 64, 0, s>>>(w, out_status);
+  HIP_TRY(hipGetLastError());
+  return SW_OK;
 }
 
 int sort_words_ex(const uint8_t* chars, const uint32_t* offsets, uint32_t n, uint32_t* out_perm,

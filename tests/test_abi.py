@@ -51,13 +51,16 @@ def test_host_side_calls_without_gpu():
     assert L.sort_words_ex(None, None, 0, None, None, None, 0, None) == sw.ERR_INVALID_ARG
     assert L.sort_words_batch(None, None, None, 1, None, None, None, 0, None) == sw.ERR_INVALID_ARG
     assert b"null" in L.sort_words_last_error()
-    # the chunk step checks its chunk size before any device call
+    # the chunk step checks its chunk size, the no-allocation form its
+    # arguments and its capacity, before any device call
     dummy = ctypes.create_string_buffer(64)
     p = ctypes.addressof(dummy)
     assert L.sort_words_chunks(p, p, 3, 3, p, p, p, 1 << 20, None) == sw.ERR_INVALID_ARG
     assert b"power of two" in L.sort_words_last_error()
     assert L.sort_words_chunks(p, p, 3, 2048, p, p, p, 1 << 20, None) == sw.ERR_INVALID_ARG
-
+    assert L.sort_words_noalloc(p, p, 3, p, p, None, None) == sw.ERR_INVALID_ARG
+    assert L.sort_words_noalloc(p, p, 1 << 22, p, p, p, None) == sw.ERR_WORKSPACE
+    assert b"scratch" in L.sort_words_last_error()
     # config validation
     cfg = sw.sw_config()
     assert L.sw_get_config(ctypes.byref(cfg)) == 0
