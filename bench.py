@@ -37,7 +37,8 @@ WORKLOADS = {
               "20k-word Zipf(1.0) vocabulary, lengths 1-20, 8 GiB HBM budget"),
 }
 CSRC = [os.path.join(ROOT, "paper_1411_5283_amd", "csrc", f)
-        for f in ("sw_device.hpp", "sw_kernels.hpp", "sw_text.hpp", "sw_bytes.hpp", "sw_runtime.hip")]
+        for f in ("sw_device.hpp", "sw_keys.hpp", "sw_split.hpp", "sw_merge4.hpp", "sw_kernels.hpp", "sw_text.hpp",
+                  "sw_bytes.hpp", "sw_runtime.hip")]
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "hbm_traffic.json")
 
 
@@ -71,14 +72,22 @@ def levels_for(n: int, T: int) -> int:
     return m
 
 
-def algorithmic_bytes(seg_sizes, tiles):
+def merge_passes(n: int, T: int, fan: int) -> int:
+    """HBM merge passes of a segment of n items after tiles of T: two-way
+    levels double the run length, four-way passes quadruple it."""
+    m = levels_for(n, T)
+    return (m + 1) // 2 if fan == 4 else m
+
+
+def algorithmic_bytes(seg_sizes, tiles, fans=(2, 2, 2, 2)):
     """Bytes each kernel family must move, per step, for the given segments.
 
-    seg_sizes: list of (length L, words n).  tiles[c] = (chunk-sort tile T).
-    chunk sort: read the element, write it back (or 4-byte index if the
-    segment is finished); merge level l < m: read + write the element, the
-    last level writes the 4-byte index instead.  Scatter: 4 B offset + L
-    chars in, one element out.  Histogram: 4 B offset per word."""
+    seg_sizes: list of (length L, words n).  tiles[c] = (chunk-sort tile T),
+    fans[c] = runs merged per HBM pass (2 or 4).  chunk sort: read the
+    element, write it back (or 4-byte index if the segment is finished);
+    merge pass p < m: read + write the element, the last pass writes the
+    4-byte index instead.  Scatter: 4 B offset + L chars in, one element out.
+    Histogram: 4 B offset per word."""
     fam = {}
 
     def add(k, v):
@@ -96,8 +105,9 @@ def algorithmic_bytes(seg_sizes, tiles):
             add("sort_packed_c%d" % c, (e + 4) * n)
             continue
         add("sort_tiles_c%d" % c, (e + (e if m else 4)) * n)
-        for l in range(m):
-            add("merge_c%d" % c, (e + (e if l < m - 1 else 4)) * n)
+        passes = merge_passes(n, tiles[c], fans[c])
+        for l in range(passes):
+            add("merge_c%d" % c, (e + (e if l < passes - 1 else 4)) * n)
     return fam
 
 
@@ -479,6 +489,9 @@ def main():
                     help="skip the tokenizer and sorted-text measurements around the sort")
     ap.add_argument("--serial", action="store_true",
                     help="run the key classes one after another (for per-kernel profiling)")
+    ap.add_argument("--merge", default=None,
+                    help="merge choice per class, e.g. 0,0,0,0 (two-way levels) or 1,1,1,1 (four-way); "
+                         "default: the tuned or built-in choice")
     ap.add_argument("--serve-warmup", type=int, default=200)
     ap.add_argument("--serve-requests", type=int, default=1000)
     ap.add_argument("--serve-slots", type=int, default=2)
@@ -522,9 +535,11 @@ def main():
         tuned = tune.apply(args.workload)
     if args.serial:
         sw.set_config(flags=sw.get_config()["flags"] | sw.FLAG_SERIAL_CLASSES)
+    if args.merge:
+        sw.set_config(merge=[int(x) for x in args.merge.split(",")])
     cfg = sw.get_config()
     tiles = [sw.variant_tiles(c, cfg["variant"][c])[0] for c in range(4)]
-    tile_cfg = {"chunk": list(cfg["chunk"]), "variant": list(cfg["variant"])}
+    tile_cfg = {"chunk": list(cfg["chunk"]), "variant": list(cfg["variant"]), "merge": list(cfg["merge"])}
 
     torch.cuda.set_device(0)
     dev = torch.device("cuda:0")
@@ -641,7 +656,7 @@ def main():
     # algorithmic bytes from the (document, length) segment sizes of the result
     bo = boff_h[:nd * 34].reshape(nd, 34).astype(np.int64)
     segs = [(L, int(c)) for row in np.diff(bo, axis=1) for L, c in enumerate(row)]
-    fam_bytes = algorithmic_bytes(segs, tiles)
+    fam_bytes = algorithmic_bytes(segs, tiles, [4 if m else 2 for m in cfg["merge"]])
     kern = {}
     for name, (launches, ms) in prof.items():
         if launches == 0:
@@ -677,7 +692,7 @@ def main():
         "vs_baseline": None, "dtype": "u64", "data": "synthetic",
         "config": {"workload": "%s: %s" % (args.workload, desc), "n_words": n, "n_docs": nd,
                    "form": "graph-captured plan (batched, device-side segment scheduling)",
-                   "chunk": cfg["chunk"], "variant": cfg["variant"], "sort_tile": tiles,
+                   "chunk": cfg["chunk"], "variant": cfg["variant"], "merge": cfg["merge"], "sort_tile": tiles,
                    "tuned": tuned is not None, "classes": "serial" if args.serial else "parallel streams",
                    "short_segments": "before the chunk sort" if cfg["flags"] & sw.FLAG_PACKED_FIRST
                    else "after the chunk sort",

@@ -227,6 +227,12 @@ typedef struct {
     uint32_t chunk[SW_NUM_CLASSES];
     uint32_t variant[SW_NUM_CLASSES];
     uint32_t flags;   /* SW_FLAG_* */
+    /* merge[c]: how class c merges the sorted tiles across HBM.  0: two-way
+     * merge-path levels (each pass doubles the run length, tiles of the
+     * variant's merge tile); k >= 1: four-way passes with compiled
+     * configuration k-1 (each pass merges four runs into one through LDS, two
+     * doublings per HBM read and write).  0 .. sw_num_merges(c)-1. */
+    uint32_t merge[SW_NUM_CLASSES];
 } sw_config;
 /* Run the key classes one after another on the caller's stream instead of on
  * parallel streams (for per-kernel measurement; results are identical). */
@@ -257,6 +263,9 @@ int sw_set_config(const sw_config *cfg);
 /* Number of compiled variants of class c, and the chunk-sort tile (words per
  * workgroup) and merge tile of a variant. */
 int sw_num_variants(int cls);
+/* Number of merge choices of class c (two-way, then the four-way
+ * configurations): the range of sw_config.merge[c]. */
+int sw_num_merges(int cls);
 int sw_variant_tiles(int cls, int variant, uint32_t *sort_tile, uint32_t *merge_tile);
 
 /* Kernel timing for measurement: while enabled, every kernel the library

@@ -51,7 +51,7 @@ def class_order(index: int) -> list:
 
 class sw_config(ctypes.Structure):
     _fields_ = [("chunk", ctypes.c_uint32 * NUM_CLASSES), ("variant", ctypes.c_uint32 * NUM_CLASSES),
-                ("flags", ctypes.c_uint32)]
+                ("flags", ctypes.c_uint32), ("merge", ctypes.c_uint32 * NUM_CLASSES)]
 
 
 class sw_server_config(ctypes.Structure):
@@ -100,6 +100,7 @@ def lib() -> ctypes.CDLL:
         "sw_get_config": ([ctypes.POINTER(sw_config)], i32),
         "sw_set_config": ([ctypes.POINTER(sw_config)], i32),
         "sw_num_variants": ([i32], i32),
+        "sw_num_merges": ([i32], i32),
         "sw_variant_tiles": ([i32, i32, ctypes.POINTER(u32), ctypes.POINTER(u32)], i32),
         "sw_profile_enable": ([i32], i32),
         "sw_profile_reset": ([], i32),
@@ -130,7 +131,7 @@ EXPORTED = ("sort_words", "sort_words_workspace_size", "sort_words_ex", "sort_wo
             "sort_words_status", "sort_words_status_async",
             "sort_words_decode_status", "sw_plan_create", "sw_plan_run", "sw_plan_run_text",
             "sw_plan_status", "sw_plan_status_async", "sw_plan_destroy", "sw_get_config", "sw_set_config",
-            "sw_num_variants", "sw_variant_tiles", "sw_profile_enable", "sw_profile_reset",
+            "sw_num_variants", "sw_num_merges", "sw_variant_tiles", "sw_profile_enable", "sw_profile_reset",
             "sw_profile_read", "sort_words_tokenize_workspace_size", "sort_words_tokenize",
             "sort_words_materialize", "sw_server_create", "sw_server_submit", "sw_server_wait",
             "sw_server_stats", "sw_server_fixed_bytes", "sw_server_destroy", "sort_words_last_error",
@@ -282,15 +283,16 @@ class Plan:
 def get_config() -> dict:
     c = sw_config()
     _check(lib().sw_get_config(ctypes.byref(c)))
-    return {"chunk": list(c.chunk), "variant": list(c.variant), "flags": int(c.flags)}
+    return {"chunk": list(c.chunk), "variant": list(c.variant), "flags": int(c.flags), "merge": list(c.merge)}
 
 
-def set_config(chunk=None, variant=None, flags=None) -> dict:
+def set_config(chunk=None, variant=None, flags=None, merge=None) -> dict:
     cur = get_config()
     c = sw_config()
     for k in range(NUM_CLASSES):
         c.chunk[k] = int((chunk if chunk is not None else cur["chunk"])[k])
         c.variant[k] = int((variant if variant is not None else cur["variant"])[k])
+        c.merge[k] = int((merge if merge is not None else cur["merge"])[k])
     c.flags = int(flags if flags is not None else cur["flags"])
     _check(lib().sw_set_config(ctypes.byref(c)))
     return get_config()
@@ -298,6 +300,11 @@ def set_config(chunk=None, variant=None, flags=None) -> dict:
 
 def num_variants(cls: int) -> int:
     return int(lib().sw_num_variants(int(cls)))
+
+
+def num_merges(cls: int) -> int:
+    """Choices of sw_config.merge[cls]: 0 two-way levels, 1.. four-way configurations."""
+    return int(lib().sw_num_merges(int(cls)))
 
 
 def variant_tiles(cls: int, variant: int) -> tuple[int, int]:

@@ -18,6 +18,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include "sw_keys.hpp"
+
 namespace sw {
 
 constexpr int kMaxLen = 32;
@@ -54,6 +56,13 @@ __host__ __device__ inline uint32_t levels_for(uint32_t n, uint32_t T) {
     ++m;
   }
   return m;
+}
+
+// HBM merge passes of such a segment when each pass merges `fan` runs (2 or
+// 4) into one: a four-way pass does two doublings.
+__host__ __device__ inline uint32_t merge_passes(uint32_t n, uint32_t T, uint32_t fan) {
+  const uint32_t m = levels_for(n, T);
+  return fan == 4 ? (m + 1) / 2 : m;
 }
 
 // The same for a power-of-two tile T = 2^lt: the smallest m with T*2^m >= n is
@@ -93,10 +102,6 @@ struct Header {
   uint32_t pack_words[kNClass];            // words in the short segments of each class
 };
 
-struct KeyBuf {
-  uint64_t* k[4];
-  uint32_t* idx;
-};
 
 // Workspace view handed to every kernel (by value).
 struct Ws {
@@ -111,6 +116,7 @@ struct Ws {
   uint32_t* st;         // [Smax+kNClass]  chunk-sort tile prefix per class
   uint32_t* mt;         // [Smax+kNClass]  merge tile prefix per class
   uint32_t* vpre;       // [Smax+kNClass]  prefix of short-segment sizes per class
+  uint32_t* wpre;       // [Smax+kNClass]  word prefix of the other segments per class
   KeyBuf a;             // key buffer 0 (scatter output, chunk sort in place)
   KeyBuf b;             // key buffer 1 (ping-pong for merge levels)
   uint32_t Nmax, Dmax, Bmax, Smax, SBmax;
@@ -118,6 +124,7 @@ struct Ws {
   uint32_t T[kNClass];      // chunk-sort tile (items per workgroup)
   uint32_t P[kNClass];      // merge tile
   uint32_t chunk[kNClass];  // odd-even chunk size
+  uint32_t fan[kNClass];    // runs merged per HBM pass: 2 or 4
 };
 
 // A workgroup's work: from the device-side segment lists, or one segment given
@@ -196,75 +203,6 @@ __device__ inline uint32_t wave_find(const uint32_t* prefix, uint32_t count, uin
   return lo;
 }
 
-// ---------------------------------------------------------------- keys
-template <int NL>
-struct Key {
-  uint64_t k[NL];
-  uint32_t idx;
-};
-template <>
-struct Key<0> {
-  uint64_t k;
-};
-
-template <int NL>
-__device__ inline bool key_less(const Key<NL>& a, const Key<NL>& b) {
-  bool lt = a.idx < b.idx;
-#pragma unroll
-  for (int q = NL - 1; q >= 0; --q) lt = (a.k[q] == b.k[q]) ? lt : (a.k[q] < b.k[q]);
-  return lt;
-}
-template <>
-__device__ inline bool key_less<0>(const Key<0>& a, const Key<0>& b) {
-  return a.k < b.k;
-}
-
-template <int NL>
-__device__ inline Key<NL> key_sentinel() {
-  Key<NL> s;
-#pragma unroll
-  for (int q = 0; q < NL; ++q) s.k[q] = ~0ull;
-  s.idx = ~0u;
-  return s;
-}
-template <>
-__device__ inline Key<0> key_sentinel<0>() {
-  Key<0> s;
-  s.k = ~0ull;
-  return s;
-}
-
-template <int NL>
-__device__ inline uint32_t key_index(const Key<NL>& v) { return v.idx; }
-template <>
-__device__ inline uint32_t key_index<0>(const Key<0>& v) { return (uint32_t)v.k; }
-
-template <int NL>
-__device__ inline Key<NL> gload(const KeyBuf& b, size_t p) {
-  Key<NL> v;
-#pragma unroll
-  for (int q = 0; q < NL; ++q) v.k[q] = b.k[q][p];
-  v.idx = b.idx[p];
-  return v;
-}
-template <>
-__device__ inline Key<0> gload<0>(const KeyBuf& b, size_t p) {
-  Key<0> v;
-  v.k = b.k[0][p];
-  return v;
-}
-
-template <int NL>
-__device__ inline void gstore(const KeyBuf& b, size_t p, const Key<NL>& v) {
-#pragma unroll
-  for (int q = 0; q < NL; ++q) b.k[q][p] = v.k[q];
-  b.idx[p] = v.idx;
-}
-template <>
-__device__ inline void gstore<0>(const KeyBuf& b, size_t p, const Key<0>& v) {
-  b.k[0][p] = v.k;
-}
-
 // Streaming stores (nontemporal hint) for outputs that the next kernel reads
 // only after the whole level has been written.
 template <int NL>
@@ -276,21 +214,6 @@ __device__ inline void gstore_nt(const KeyBuf& b, size_t p, const Key<NL>& v) {
 template <>
 __device__ inline void gstore_nt<0>(const KeyBuf& b, size_t p, const Key<0>& v) {
   __builtin_nontemporal_store(v.k, b.k[0] + p);
-}
-
-template <int NL>
-__device__ inline Key<NL> key_select(bool c, const Key<NL>& x, const Key<NL>& y) {
-  Key<NL> r;
-#pragma unroll
-  for (int q = 0; q < NL; ++q) r.k[q] = c ? x.k[q] : y.k[q];
-  r.idx = c ? x.idx : y.idx;
-  return r;
-}
-template <>
-__device__ inline Key<0> key_select<0>(bool c, const Key<0>& x, const Key<0>& y) {
-  Key<0> r;
-  r.k = c ? x.k : y.k;
-  return r;
 }
 
 __device__ inline uint64_t shfl64(uint64_t v, int src) {

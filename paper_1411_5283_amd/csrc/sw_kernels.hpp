@@ -11,20 +11,24 @@
 //   k_seg_count / k_scan_rows / k_seg_scatter
 //                  segments ordered by (key class, merge levels descending) so
 //                  that the segments still merging at level l are a prefix
-//   k_tile_prefix  per class: tiles of the chunk sort and of a merge level
+//   k_tile_prefix  per class: tiles of the chunk sort and of a two-way merge
+//                  level, words of the four-way merge's ranges
 //   k_scatter_pack stable distribution of the words into their segment, as
 //                  big-endian key lanes + index (the sub-arrays of phase 2)
 //   k_sort_tiles   per tile: odd-even transposition on chunks (bubble sort's
 //                  parallel form), then merge-path merges in LDS up to the tile
-//   k_merge        one merge-path level over HBM (each workgroup places its
-//                  own tiles); the last level of a segment writes the output
-//                  permutation
+//   k_merge        one two-way merge-path level over HBM (each workgroup
+//                  places its own tiles); the last level of a segment writes
+//                  the output permutation
+//   k_merge4       one four-way merge level over HBM (two doublings of the
+//                  run length per pass, streamed through LDS)
 //   k_pack_full    the same words as one sequence of full keys (baseline
 //                  without length lists)
 // Every kernel after k_begin reads the run from the workspace, so the same
 // sequence runs eagerly or as one captured HIP graph.
 #pragma once
 #include "sw_device.hpp"
+#include "sw_merge4.hpp"
 
 namespace sw {
 
@@ -344,19 +348,21 @@ __global__ __launch_bounds__(NT) void k_seg_scatter(Ws w) {
   }
 }
 
-// Per class (blockIdx.x / 3) and kind (blockIdx.x % 3): exclusive prefix over
-// the class sublist of the chunk-sort tiles (kind 0) or the merge tiles
-// (kind 1) of its segments that are not packed, or of the sizes of its short
-// segments (kind 2, their positions in the packed tiles).
+// Per class (blockIdx.x / 4) and kind (blockIdx.x % 4): exclusive prefix over
+// the class sublist of the chunk-sort tiles (kind 0), the two-way merge tiles
+// (kind 1) or the words (kind 3, the four-way merge's ranges) of its segments
+// that are not packed, or of the sizes of its short segments (kind 2, their
+// positions in the packed tiles).
 template <int NT>
 __global__ __launch_bounds__(NT) void k_tile_prefix(Ws w) {
   __shared__ uint32_t s_tmp[NT / 64];
   Header* h = w.h;
   if (h->abort) return;
-  const uint32_t c = blockIdx.x / 3, kind = blockIdx.x % 3;
+  const uint32_t c = blockIdx.x / 4, kind = blockIdx.x % 4;
   const uint32_t cs = kind == 2 ? h->pack_start[c] : h->cls_start[c];
   const uint32_t ce = kind == 2 ? h->cls_start[c + 1] : h->pack_start[c];
-  uint32_t* out = (kind == 0 ? w.st : (kind == 1 ? w.mt : w.vpre)) + (kind == 2 ? cs : h->cls_start[c]) + c;
+  uint32_t* out = (kind == 0 ? w.st : (kind == 1 ? w.mt : (kind == 2 ? w.vpre : w.wpre))) +
+                  (kind == 2 ? cs : h->cls_start[c]) + c;
   const uint32_t div = kind == 0 ? w.T[c] : (kind == 1 ? w.P[c] : 1u);
   uint32_t carry = 0;
   for (uint32_t base = cs; base < ce; base += NT) {
@@ -1271,6 +1277,211 @@ __global__ __launch_bounds__(NT) void k_merge(Ws w, int cls, int level, TileWork
     }
     __syncthreads();
     cur = nxt;
+  }
+}
+
+// ---------------------------------------------------------------- k_merge4
+// Co-ranks sp[] of rank d in the four runs (start st[r], len[r]) by the
+// bracket search of sw_split.hpp: each round every slot of every run is
+// sampled by one thread, every interior sample judged by one thread, and the
+// brackets narrowed with LDS atomics.  False if the search did not close
+// (never expected; the caller then stops its work and flags the run).
+template <class M, int NL, int NT>
+__device__ __attribute__((always_inline)) inline bool split4(typename M::Lds& L, const KeyBuf& src, const uint64_t (&st)[4],
+                              const uint32_t (&len)[4], uint32_t d, uint32_t (&sp)[4]) {
+  SplitScratch<Key<NL>>& S = L.u.sp;
+  if (threadIdx.x == 0) {
+    split_init(S, len, d);
+#pragma unroll
+    for (int i = 0; i < 4; ++i) S.start[i] = st[i];
+  }
+  __syncthreads();
+  while (!S.done) {
+    if (S.rounds >= (uint32_t)kSplitMaxRounds) return false;   // the same in every thread
+    for (uint32_t slot = threadIdx.x; slot < (uint32_t)(kSplitRuns * kSplitSlots); slot += NT) {
+      const int i = (int)(slot / kSplitSlots), j = (int)(slot % kSplitSlots);
+      const uint32_t p = split_slot_pos(S, i, j);
+      S.pos[i][j] = p;
+      if (p != kSplitNone) S.key[i][j] = gload<NL>(src, (size_t)(S.start[i] + p));
+    }
+    if (threadIdx.x == 0) split_begin_round(S);
+    __syncthreads();
+    for (uint32_t slot = threadIdx.x; slot < (uint32_t)(kSplitRuns * kSplitSlots); slot += NT) {
+      const int i = (int)(slot / kSplitSlots), j = (int)(slot % kSplitSlots);
+      if (j == 0 || j == kSplitSlots - 1 || S.pos[i][j] == kSplitNone) continue;
+      const int v = split_decide(S, i, j, typename M::Less());
+      if (v < 0) atomicMax(&S.newlo[i], S.pos[i][j] + 1);
+      if (v > 0) atomicMin(&S.newhi[i], S.pos[i][j]);
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) split_finish_round(S);
+    __syncthreads();
+  }
+  uint32_t sum = 0;
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    sp[i] = S.lo[i];
+    sum += sp[i];
+  }
+  __syncthreads();   // the scratch shares LDS with the X and Y rings
+  return sum == d;
+}
+
+// A thread's n outputs at position o: indices to the output permutation on
+// a segment's last level (and the keys too for the sorted text), keys to the
+// next buffer otherwise.
+template <int NL, int E>
+__device__ __attribute__((always_inline)) inline void merge4_store(const Key<NL> (&out)[E], uint32_t n, size_t o,
+                                                                   bool final, bool keep, uint32_t* out_perm,
+                                                                   const KeyBuf& dst) {
+#pragma unroll
+  for (int j = 0; j < E; ++j) {
+    if ((uint32_t)j < n) {
+      if (final) __builtin_nontemporal_store(key_index<NL>(out[j]), out_perm + o + j);
+      if (!final || keep) gstore_nt<NL>(dst, o + j, out[j]);
+    }
+  }
+}
+
+// One four-way merge level of class cls (runs of R = T * 4^level items
+// merged four at a time into runs of 4R).  The level's output -- the active
+// segments of the class one after another, or the one segment given directly
+// -- is cut into one contiguous range per workgroup; the range is walked
+// group by group: a group entered at rank d > 0 starts from the co-ranks of
+// the split search, one entered at its start from zero, and each streams
+// through LDS (sw_merge4.hpp).  A segment's last level writes the indices to
+// the output permutation (and, for the sorted text, its keys as well).
+template <int NL, int NT, int E, int PS, int RC>
+__global__ __launch_bounds__(NT) void k_merge4(Ws w, int cls, int level, TileWork tw) {
+  using M = M4<NL, NT, E, PS, RC>;
+  using K = Key<NL>;
+  constexpr int FE = M::FE;
+  __shared__ typename M::Lds L;
+  Header* h = w.h;
+  if (h->abort) return;
+  const uint32_t Tc = w.T[cls];
+  const uint64_t R = (uint64_t)Tc << (2 * level);
+  uint64_t total;
+  const uint32_t* wp = nullptr;
+  uint32_t cstart = 0, cact = 0;
+  if (tw.direct) {
+    if ((uint32_t)level >= tw.m) return;
+    total = tw.n;
+  } else {
+    cstart = h->cls_start[cls];
+    cact = 2 * level < kMaxLev ? h->active[cls][2 * level] : 0u;
+    wp = w.wpre + cstart + cls;
+    total = cact ? wp[cact] : 0u;
+  }
+  const uint64_t r0 = total * blockIdx.x / gridDim.x, r1 = total * (blockIdx.x + 1) / gridDim.x;
+  if (r0 >= r1) return;
+  const KeyBuf src = (level & 1) ? w.b : w.a;
+  const KeyBuf dst = (level & 1) ? w.a : w.b;
+  uint32_t* out_perm = h->d.out_perm;
+  const bool keep = h->d.out_text != nullptr;
+  const uint32_t tid = threadIdx.x;
+  uint32_t k = 0;
+  if (!tw.direct) {
+    if (tid < 64) {
+      const uint32_t kk = wave_find(wp, cact, (uint32_t)r0);
+      if (tid == 0) L.seg = kk;
+    }
+    __syncthreads();
+    k = L.seg;
+  }
+  for (uint64_t pos = r0; pos < r1;) {
+    uint32_t base, n;
+    uint64_t segw = 0;
+    if (tw.direct) {
+      base = tw.base;
+      n = tw.n;
+    } else {
+      while (wp[k + 1] <= pos) ++k;
+      const uint32_t sg = w.sorted[cstart + k];
+      base = w.seg_base[sg];
+      n = w.seg_n[sg];
+      segw = wp[k];
+    }
+    const M4Group g = m4_group(n, pos - segw, R);
+    const uint64_t gend = segw + g.start + g.size;
+    const uint32_t count = (uint32_t)((gend < r1 ? gend : r1) - pos);
+    const bool final = merge_passes(n, Tc, 4) == (uint32_t)level + 1;
+    const size_t ob = (size_t)base + g.start + g.d;   // first output position of this piece
+    uint64_t st[4];
+#pragma unroll
+    for (int r = 0; r < 4; ++r) st[r] = (uint64_t)base + g.start + g.run_off[r];
+    uint32_t sp[4] = {0, 0, 0, 0};
+    if (g.d > 0 && !split4<M, NL, NT>(L, src, st, g.len, g.d, sp)) {
+      if (tid == 0) {
+        atomicOr(&h->status, ST_INVALID);
+        atomicOr(&h->abort, 1u);
+      }
+      return;
+    }
+    typename M::State s;
+    M::begin(s, st, g.len, sp);
+    // rings filled, X and Y topped up, rings refilled: all synchronously
+    M::fill_amounts(s, 4u * RC);
+    for (uint32_t q = tid; q < M::refill_total(s); q += NT) {
+      K v;
+      if (M::refill_load(s, src, q, v)) M::refill_put(L, s, q, v);
+    }
+    if (tid == 0) L.end[0][0] = L.end[0][1] = L.end[1][0] = L.end[1][1] = 0;
+    M::refill_done(s);
+    M::seal_runs(L, s, tid);
+    __syncthreads();
+    uint32_t wx = M::want(s, 0), wy = M::want(s, 1);
+    for (uint32_t wi = tid; wi < M::topup_items(s); wi += NT) M::topup(L, s, wi);
+    M::seal_xy(L, s, tid, wx, wy);
+    __syncthreads();
+    M::topup_done(s, L, wx, wy);
+    M::fill_amounts(s, 4u * RC);
+    for (uint32_t q = tid; q < M::refill_total(s); q += NT) {
+      K v;
+      if (M::refill_load(s, src, q, v)) M::refill_put(L, s, q, v);
+    }
+    M::refill_done(s);
+    M::seal_runs(L, s, tid);
+    __syncthreads();
+    K pf[FE];
+    // a step's outputs are stored in the next step, after that step has
+    // waited for its ring loads: the wait then never waits for them
+    K out[E];
+    uint32_t nout = 0;
+    size_t o = 0;
+    for (uint32_t done = 0; done < count;) {
+      // A: last step's loads into the rings; last step's outputs stored;
+      // loads for the ring slots now free
+#pragma unroll
+      for (int u = 0; u < FE; ++u) {
+        const uint32_t q = tid + (uint32_t)u * NT;
+        if (q < M::refill_total(s)) M::refill_put(L, s, q, pf[u]);
+      }
+      M::refill_done(s);
+      M::seal_runs(L, s, tid);
+      merge4_store<NL, E>(out, nout, o, final, keep, out_perm, dst);
+      M::fill_amounts(s, (uint32_t)(FE * NT));
+#pragma unroll
+      for (int u = 0; u < FE; ++u) M::refill_load(s, src, tid + (uint32_t)u * NT, pf[u]);
+      if (tid == 0) L.end[0][0] = L.end[0][1] = L.end[1][0] = L.end[1][1] = 0;
+      __syncthreads();
+      // B: X and Y topped up
+      wx = M::want(s, 0);
+      wy = M::want(s, 1);
+      for (uint32_t wi = tid; wi < M::topup_items(s); wi += NT) M::topup(L, s, wi);
+      M::seal_xy(L, s, tid, wx, wy);
+      __syncthreads();
+      M::topup_done(s, L, wx, wy);
+      // C: this step's outputs, into registers
+      const uint32_t cnt = count - done < (uint32_t)PS ? count - done : (uint32_t)PS;
+      nout = M::final_merge(L, s, tid, cnt, out);
+      o = ob + done + (size_t)tid * E;
+      __syncthreads();
+      M::final_done(s, L, cnt);
+      done += cnt;
+    }
+    merge4_store<NL, E>(out, nout, o, final, keep, out_perm, dst);
+    pos += count;
   }
 }
 

@@ -106,9 +106,36 @@ const Variant* variants(int c, int* count) {
   return all[c];
 }
 
+// Four-way merge configurations of a class: threads NT, outputs per thread E,
+// outputs per step PS, ring slots per run RC.
+struct Merge4 {
+  void (*merge)(const Ws&, int, int, TileWork, unsigned, hipStream_t);
+  const void* fn;
+  int nt;
+  uint32_t ps;
+};
+template <int NL, int NT, int E, int PS, int RC>
+struct V4 {
+  static void merge(const Ws& w, int c, int l, TileWork tw, unsigned grid, hipStream_t s) {
+    sw::k_merge4<NL, NT, E, PS, RC><<<grid, NT, 0, s>>>(w, c, l, tw);
+  }
+  static Merge4 get() { return Merge4{merge, (const void*)sw::k_merge4<NL, NT, E, PS, RC>, NT, (uint32_t)PS}; }
+};
+constexpr int kMaxMerge4 = 2;
+const Merge4* merges4(int c, int* count) {
+  static const Merge4 m0[] = {V4<0, 128, 2, 256, 512>::get(), V4<0, 128, 4, 512, 1024>::get()};
+  static const Merge4 m1[] = {V4<1, 128, 2, 256, 512>::get()};
+  static const Merge4 m2[] = {V4<2, 256, 1, 256, 512>::get()};
+  static const Merge4 m3[] = {V4<4, 128, 1, 128, 256>::get()};
+  static const Merge4* all[] = {m0, m1, m2, m3};
+  static const int counts[] = {2, 1, 1, 1};
+  *count = counts[c];
+  return all[c];
+}
+
 // ------------------------------------------------------------------ config
 std::mutex g_cfg_mu;
-sw_config g_cfg = {{16, 16, 16, 16}, {0, 0, 0, 0}, 0};
+sw_config g_cfg = {{16, 16, 16, 16}, {0, 0, 0, 0}, 0, {0, 0, 0, 0}};
 
 sw_config current_config() {
   std::lock_guard<std::mutex> lk(g_cfg_mu);
@@ -122,6 +149,7 @@ struct DevInfo {
   int occ_hist = 1, occ_scatter = 1, occ_text = 1;
   int occ_sort[sw::kNClass][kMaxVariants] = {};
   int occ_merge[sw::kNClass][kMaxVariants] = {};
+  int occ_merge4[sw::kNClass][kMaxMerge4] = {};
 };
 std::mutex g_dev_mu;
 DevInfo g_dev[64];
@@ -148,6 +176,12 @@ int device_info(DevInfo** out) {
         d.occ_sort[c][v] = std::max(d.occ_sort[c][v], 1);
         d.occ_merge[c][v] = std::max(d.occ_merge[c][v], 1);
       }
+      int nm;
+      const Merge4* ms = merges4(c, &nm);
+      for (int k = 0; k < nm; ++k) {
+        HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(&d.occ_merge4[c][k], ms[k].fn, ms[k].nt, 0));
+        d.occ_merge4[c][k] = std::max(d.occ_merge4[c][k], 1);
+      }
     }
     d.occ_hist = std::max(d.occ_hist, 1);
     d.occ_scatter = std::max(d.occ_scatter, 1);
@@ -161,7 +195,7 @@ int device_info(DevInfo** out) {
 // ------------------------------------------------------------------ layout
 struct Layout {
   uint64_t Nmax = 0, Dmax = 0, Bmax = 0, Smax = 0, SBmax = 0;
-  size_t o_hdr, o_doc_off, o_doc_blk, o_cnt, o_seg_n, o_seg_base, o_segcnt, o_sorted, o_st, o_mt, o_vpre;
+  size_t o_hdr, o_doc_off, o_doc_blk, o_cnt, o_seg_n, o_seg_base, o_segcnt, o_sorted, o_st, o_mt, o_vpre, o_wpre;
   size_t o_a[4], o_ai, o_b[4], o_bi;
   size_t total = 0;
 };
@@ -192,6 +226,7 @@ bool make_layout(uint64_t Nmax, uint64_t Dmax, Layout& L) {
   L.o_st = take(4 * (L.Smax + sw::kNClass));
   L.o_mt = take(4 * (L.Smax + sw::kNClass));
   L.o_vpre = take(4 * (L.Smax + sw::kNClass));
+  L.o_wpre = take(4 * (L.Smax + sw::kNClass));
   for (int q = 0; q < 4; ++q) L.o_a[q] = take(8 * N1);
   L.o_ai = take(4 * N1);
   for (int q = 0; q < 4; ++q) L.o_b[q] = take(8 * N1);
@@ -230,6 +265,7 @@ Ws make_ws(void* base, const Layout& L, const sw_config& cfg, uint64_t max_chars
   w.st = (uint32_t*)(p + L.o_st);
   w.mt = (uint32_t*)(p + L.o_mt);
   w.vpre = (uint32_t*)(p + L.o_vpre);
+  w.wpre = (uint32_t*)(p + L.o_wpre);
   for (int q = 0; q < 4; ++q) {
     w.a.k[q] = (uint64_t*)(p + L.o_a[q]);
     w.b.k[q] = (uint64_t*)(p + L.o_b[q]);
@@ -247,6 +283,7 @@ Ws make_ws(void* base, const Layout& L, const sw_config& cfg, uint64_t max_chars
     w.T[c] = v.T;
     w.P[c] = v.P;
     w.chunk[c] = cfg.chunk[c];
+    w.fan[c] = cfg.merge[c] ? 4u : 2u;
   }
   return w;
 }
@@ -312,8 +349,9 @@ struct Grids {
   uint32_t flags;
   unsigned words, scatter, docs, segs;
   unsigned sort[sw::kNClass], merge[sw::kNClass], packed, text;
-  int levels[sw::kNClass];
+  int passes[sw::kNClass];             // HBM merge passes of the longest possible segment
   const Variant* var[sw::kNClass];
+  const Merge4* m4[sw::kNClass];       // four-way merge, or null for two-way levels
 };
 
 int make_grids(const Ws& w, const sw_config& cfg, Grids& g) {
@@ -337,8 +375,16 @@ int make_grids(const Ws& w, const sw_config& cfg, Grids& g) {
     const uint64_t maxtiles_s = (uint64_t)w.Nmax / vs[v].T + w.Smax;
     const uint64_t maxtiles_m = (uint64_t)w.Nmax / vs[v].P + w.Smax;
     g.sort[c] = clampg(maxtiles_s, cus * (uint64_t)d->occ_sort[c][v]);
-    g.merge[c] = clampg(maxtiles_m, cus * (uint64_t)d->occ_merge[c][v]);
-    g.levels[c] = (int)sw::levels_for(w.Nmax, vs[v].T);
+    const int mk = (int)cfg.merge[c];
+    g.m4[c] = nullptr;
+    if (mk) {
+      int nm;
+      g.m4[c] = &merges4(c, &nm)[mk - 1];
+      g.merge[c] = clampg(((uint64_t)w.Nmax + 4095) / 4096, cus * (uint64_t)d->occ_merge4[c][mk - 1]);
+    } else {
+      g.merge[c] = clampg(maxtiles_m, cus * (uint64_t)d->occ_merge[c][v]);
+    }
+    g.passes[c] = (int)sw::merge_passes(w.Nmax, vs[v].T, mk ? 4u : 2u);
   }
   return SW_OK;
 }
@@ -454,7 +500,7 @@ int enqueue_body(const Ws& w, const Grids& g, hipStream_t s, bool capture, bool 
     }
     {
       ProfScope p(K_TILE_PREFIX, ss, capture);
-      sw::k_tile_prefix<1024><<<3 * sw::kNClass, 1024, 0, ss>>>(w);
+      sw::k_tile_prefix<1024><<<4 * sw::kNClass, 1024, 0, ss>>>(w);
     }
     if (beside) HIP_TRY(hipEventRecord(fork->seg_join, ss));
   }
@@ -492,15 +538,18 @@ int enqueue_body(const Ws& w, const Grids& g, hipStream_t s, bool capture, bool 
         g.var[c]->sort(w, c, none, g.sort[c], cs);
       }
     }
-    max_levels = std::max(max_levels, g.levels[c]);
+    max_levels = std::max(max_levels, g.passes[c]);
   }
   for (int l = 0; l < max_levels; ++l) {
     for (int k = 0; k < sw::kNClass; ++k) {
       const int c = order[k];
-      if (l >= g.levels[c]) continue;
+      if (l >= g.passes[c]) continue;
       hipStream_t cs = cstream(c);
       ProfScope p(K_MERGE0 + c, cs, capture);
-      g.var[c]->merge(w, c, l, none, g.merge[c], cs);
+      if (g.m4[c])
+        g.m4[c]->merge(w, c, l, none, g.merge[c], cs);
+      else
+        g.var[c]->merge(w, c, l, none, g.merge[c], cs);
     }
   }
   if (par) {
@@ -740,16 +789,18 @@ int sort_words_plain(const uint8_t* chars, const uint32_t* offsets, const uint32
     if (!n) continue;
     const int c = sw::class_of_len((uint32_t)(sidx % sw::kNB));
     const Variant& v = *g.var[c];
-    const uint32_t m = sw::levels_for(n, v.T);
+    const uint32_t m = sw::merge_passes(n, v.T, g.m4[c] ? 4u : 2u);
     const TileWork tw{1, seg_base[sidx], n, m, 0};
     {
       ProfScope p(K_SORT0 + c, s, false);
       v.sort(w, c, tw, (n + v.T - 1) / v.T, s);
     }
-    const uint32_t mtiles = (n + v.P - 1) / v.P;
     for (uint32_t l = 0; l < m; ++l) {
       ProfScope p(K_MERGE0 + c, s, false);
-      v.merge(w, c, (int)l, tw, mtiles, s);
+      if (g.m4[c])
+        g.m4[c]->merge(w, c, (int)l, tw, std::min<unsigned>((n + 4095) / 4096, g.merge[c]), s);
+      else
+        v.merge(w, c, (int)l, tw, (n + v.P - 1) / v.P, s);
     }
   }
   HIP_TRY(hipGetLastError());
@@ -821,12 +872,16 @@ int sort_words_unbucketed(const uint8_t* chars, const uint32_t* offsets, uint32_
     // one segment of n four-lane keys: chunk sort, then every merge level
     constexpr int c = sw::kNClass - 1;
     const Variant& v = *g.var[c];
-    const uint32_t m = sw::levels_for(n, v.T);
+    const uint32_t m = sw::merge_passes(n, v.T, g.m4[c] ? 4u : 2u);
     const TileWork tw{1, 0, n, m, 0};
     v.sort(w, c, tw, (n + v.T - 1) / v.T, s);
     const uint32_t mtiles = (n + v.P - 1) / v.P;
-    for (uint32_t l = 0; l < m; ++l)
-      v.merge(w, c, (int)l, tw, std::min<uint32_t>(mtiles, (uint32_t)(di->cus * di->occ_merge[c][cfg.variant[c]])), s);
+    for (uint32_t l = 0; l < m; ++l) {
+      if (g.m4[c])
+        g.m4[c]->merge(w, c, (int)l, tw, std::min<unsigned>((n + 4095) / 4096, g.merge[c]), s);
+      else
+        v.merge(w, c, (int)l, tw, std::min<uint32_t>(mtiles, (uint32_t)(di->cus * di->occ_merge[c][cfg.variant[c]])), s);
+    }
   }
   HIP_TRY(hipGetLastError());
   return SW_OK;
@@ -990,6 +1045,10 @@ int sw_set_config(const sw_config* cfg) {
     variants(c, &nv);
     if (cfg->variant[c] >= (uint32_t)nv)
       return fail(SW_ERR_INVALID_ARG, "sw_set_config: variant[%d]=%u out of range", c, cfg->variant[c]);
+    int nm;
+    merges4(c, &nm);
+    if (cfg->merge[c] > (uint32_t)nm)
+      return fail(SW_ERR_INVALID_ARG, "sw_set_config: merge[%d]=%u out of range", c, cfg->merge[c]);
   }
   if (cfg->flags &
       ~(SW_FLAG_SERIAL_CLASSES | SW_FLAG_PACKED_FIRST | SW_FLAG_SCHEDULE_BESIDE_SCATTER | SW_FLAG_ORDER_MASK))
@@ -1007,6 +1066,13 @@ int sw_num_variants(int cls) {
   int nv;
   variants(cls, &nv);
   return nv;
+}
+
+int sw_num_merges(int cls) {
+  if (cls < 0 || cls >= sw::kNClass) return 0;
+  int nm;
+  merges4(cls, &nm);
+  return nm + 1;
 }
 
 int sw_variant_tiles(int cls, int variant, uint32_t* sort_tile, uint32_t* merge_tile) {

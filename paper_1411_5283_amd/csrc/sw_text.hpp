@@ -435,7 +435,7 @@ __global__ __launch_bounds__(NT) void k_materialize(const uint8_t* chars, const 
 // at most 32 bytes, so its key lanes (big-endian, zero padded) hold all of its
 // bytes; when the run asks for text, every segment's chunk sort or last merge
 // level leaves its sorted keys in a key buffer besides writing the indices:
-// buffer A when the segment took an even number of merge levels (none
+// buffer A when the segment took an even number of merge passes (none
 // included), B when odd.  So the text is written from keys read in order, and
 // no word is read again from the input at a random place.
 //
@@ -557,7 +557,8 @@ __global__ __launch_bounds__(NT) void k_keys_text(Ws w) {
           if (e > a) {
             cnt = e - a;
             first = a - g0;
-            const uint32_t m = n <= kPackMax ? 0u : levels_for(n, w.T[class_of_len(L)]);
+            const int c = class_of_len(L);
+            const uint32_t m = n <= kPackMax ? 0u : merge_passes(n, w.T[c], w.fan[c]);
             info = L | ((m & 1u) << 8);
           }
         }

@@ -65,6 +65,34 @@ def test_long_segments_every_variant(gpu, oracle_mod, default_config, variant):
     _same(gpu.sort_wordlist(wl), _expect(oracle_mod, wl, bubble=False), "long variant %d" % variant)
 
 
+@pytest.mark.parametrize("merge", [0, 1, 2])
+def test_long_segments_every_merge(gpu, oracle_mod, default_config, merge):
+    # the two-way levels (0) and each four-way configuration (1..) of every
+    # class, on 1.5M words: many groups, workgroup ranges starting inside
+    # groups at every level, short last groups
+    wl = wordgen.single(1_500_000, 40_000, 1.1, 20, seed=9)
+    m = [min(merge, gpu.num_merges(c) - 1) for c in range(4)]
+    _say("case long segments merge=%s n=%d" % (m, wl.n))
+    gpu.set_config(merge=m)
+    _same(gpu.sort_wordlist(wl), _expect(oracle_mod, wl, bubble=False), "long merge %s" % m)
+
+
+@pytest.mark.parametrize("merge", [0, 1])
+def test_per_bucket_launch_every_merge(gpu, oracle_mod, default_config, merge):
+    # the per-bucket-launch form launches each segment's merge passes directly
+    import torch
+    wl = wordgen.config(3, 0.01)
+    gpu.set_config(merge=[merge] * 4)
+    _say("case per-bucket launch merge=%d docs=%d n=%d" % (merge, wl.n_docs, wl.n))
+    chars, offs, docs = gpu.device_words(wl)
+    ws = torch.empty(gpu.sort_words_workspace_size(wl.n, wl.n_docs), dtype=torch.uint8, device="cuda")
+    perm = torch.empty(wl.n, dtype=torch.int32, device="cuda")
+    boff = torch.empty(wl.n_docs * 34, dtype=torch.int32, device="cuda")
+    gpu.sort_words_plain(chars, offs, docs, wl.n_docs, perm, boff, ws)
+    _same((gpu.to_u32(perm), gpu.to_u32(boff).reshape(wl.n_docs, 34)), _expect(oracle_mod, wl, bubble=False),
+          "plain merge %d" % merge)
+
+
 def test_config1_bit_exact(gpu, oracle_mod):
     wl = wordgen.config(1)
     _say("case config1 n=%d" % wl.n)
