@@ -16,6 +16,8 @@ Functions (host numpy arrays in, numpy arrays out):
 * ``oracle_def``     -- the definition the method reaches: indices ordered by
   the total order (length, bytes unsigned, index).  Plain C over qsort.
 * ``oracle_sorted``  -- the same definition with Python's ``sorted``.
+* ``oracle_def_parallel`` -- oracle_def on each length list, lists on host
+  threads (for the CPU baseline on all cores).
 * ``oracle_rank``    -- rank of one word under that order (O(n), for sampling
   outputs of inputs too large to sort on the CPU).
 * ``paper_chunk_size`` -- chunk size = array size / number of processors
@@ -222,6 +224,42 @@ def oracle_batch(chars, offsets, doc_offsets, fn: str = "oracle_bubble", threads
     with ThreadPoolExecutor(max_workers=threads) as ex:
         list(ex.map(one, order))
     return perm[:N], boff[:nd]
+
+
+def oracle_def_parallel(chars, offsets, threads: int = 0):
+    """oracle_def with the length lists on host threads: the words are put
+    into one list per length (phase 2 of section 3), each list is sorted by
+    oracle_def on a thread of its own, and the lists are laid out shorter
+    first.  Returns (perm, bucket_offsets) equal to oracle_def's."""
+    chars, offsets = _prep(chars, offsets)
+    n = offsets.shape[0] - 1
+    offs = offsets.astype(np.int64)
+    lens = offs[1:] - offs[:-1]
+    if n and (lens.min() < 0 or lens.max() > MAX_LEN):
+        raise OracleError(INVALID_ARG if lens.min() < 0 else WORD_TOO_LONG)
+    order = np.argsort(lens, kind="stable")             # indices of each length, in input order
+    counts = np.bincount(lens, minlength=MAX_LEN + 1)[:MAX_LEN + 1] if n else np.zeros(MAX_LEN + 1, np.int64)
+    boff = np.zeros(N_OFFSETS, np.uint32)
+    boff[1:] = np.cumsum(counts)
+    perm = np.zeros(max(n, 1), np.uint32)
+
+    def one(L):
+        lo, hi = int(boff[L]), int(boff[L + 1])
+        if hi == lo:
+            return
+        idx = order[lo:hi]
+        # the list's words back to back: list word k is chars[sub[k] .. sub[k] + L)
+        starts = offs[idx]
+        sub_chars = chars[(starts[:, None] + np.arange(L)[None, :]).reshape(-1)] if L else np.zeros(1, np.uint8)
+        sub_offs = (np.arange(hi - lo + 1, dtype=np.int64) * L).astype(np.uint32)
+        p, _ = oracle_def(sub_chars, sub_offs)
+        perm[lo:hi] = idx[p.astype(np.int64)]
+
+    threads = threads or len(os.sched_getaffinity(0))
+    # longest lists first so the pool stays busy
+    with ThreadPoolExecutor(max_workers=threads) as ex:
+        list(ex.map(one, sorted(range(MAX_LEN + 1), key=lambda L: -int(counts[L]))))
+    return perm[:n], boff
 
 
 def paper_chunk_size(array_size: int, processors: int) -> int:

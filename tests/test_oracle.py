@@ -308,3 +308,22 @@ def test_chunk_step_pins(oracle_mod):
                 assert r == sorted(r)
             merged += [i for _, i in heapq.merge(*runs)]
         assert np.array_equal(np.asarray(merged, np.uint32), full), c
+
+
+def test_parallel_definition_equals_definition(oracle_mod):
+    # the per-length-list threads give oracle_def's result: tiny cases (against
+    # brute force), empty input, every length, generated text
+    for words in list(_tiny_cases())[::7]:
+        wl = wordgen.from_words(words)
+        exp_perm, exp_boff = brute_force(words)
+        perm, boff = oracle_mod.oracle_def_parallel(wl.chars, wl.offsets, threads=3)
+        assert np.array_equal(perm, exp_perm) and np.array_equal(boff, exp_boff), words
+    perm, boff = oracle_mod.oracle_def_parallel(np.zeros(0, np.uint8), np.zeros(1, np.uint32))
+    assert perm.shape[0] == 0 and np.all(boff == 0)
+    for cfg, scale in ((1, 1.0), (2, 0.2), (4, 0.002)):
+        wl = wordgen.config(cfg, scale)
+        p1, b1 = oracle_mod.oracle_def(wl.chars, wl.offsets)
+        p2, b2 = oracle_mod.oracle_def_parallel(wl.chars, wl.offsets)
+        assert np.array_equal(p1, p2) and np.array_equal(b1, b2)
+    with pytest.raises(oracle_mod.OracleError):
+        oracle_mod.oracle_def_parallel(np.zeros(40, np.uint8), np.array([0, 3, 40], np.uint32))
