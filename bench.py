@@ -39,7 +39,16 @@ WORKLOADS = {
 CSRC = [os.path.join(ROOT, "paper_1411_5283_amd", "csrc", f)
         for f in ("sw_device.hpp", "sw_keys.hpp", "sw_split.hpp", "sw_merge4.hpp", "sw_kernels.hpp", "sw_text.hpp",
                   "sw_bytes.hpp", "sw_runtime.hip")]
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "hbm_traffic.json")
+# VALU issue rate of the whole GPU: 256 CUs x 4 SIMDs x 16 lanes per clock
+# (a wave64 instruction occupies its SIMD for 4 clocks) x 2.4 GHz, in tera
+# lane-operations per second (the fp32 vector figure, 157.3 TFLOP/s, is this
+# rate x 2 for fused multiply-add x 2 for dual issue; a sort issues neither).
+VALU_PEAK_TOPS = 256 * 64 * 2.4e9 / 1e12
+
+
+def counter_file(kind: str, workload: str) -> str:
+    """profiles/hbm_traffic_<workload>.json or profiles/sq_counters_<workload>.json"""
+    return os.path.join(ROOT, "profiles", "%s_%s.json" % (kind, workload))
 
 
 def log(*a):
@@ -146,45 +155,65 @@ def light_check(wl, perm: np.ndarray, boff: np.ndarray, n_docs: int) -> dict:
             "ok": bool(ok)}
 
 
-def cpu_baseline(wl, budget_s: float = 12.0) -> dict:
-    """The oracle as it stands, single-threaded, on a bounded prefix sample."""
-    import oracle
-    oracle.build(force=False)
-    n = min(1 << 20, wl.n)
+def _grow_sample(wl, fn, budget_s: float, start: int):
+    """Time fn(chars, offsets) on ever longer prefixes of the word list until
+    one run takes about budget_s / 2.2 (or the whole list is used)."""
+    n = min(start, wl.n)
     while True:
         offs = np.ascontiguousarray(wl.offsets[:n + 1])
         t0 = time.perf_counter()
-        oracle.oracle_def(wl.chars, offs)
+        fn(wl.chars, offs)
         dt = time.perf_counter() - t0
         if dt * 2.2 > budget_s or n >= wl.n:
-            break
+            return n, dt
         n = min(n * 2, wl.n)
-    res = {"value": n / dt / 1e6, "unit": "Mwords/s", "cores": 1, "kind": "oracle",
-           "sample": "oracle_def (qsort by length, bytes, index) on the first %d words of the "
-                     "same workload, one thread, %.2f s" % (n, dt)}
-    # the paper's own method on a paper-sized text (Table 1 analog)
+
+
+def cpu_baseline(wl, workload: str, budget_s: float = 16.0) -> dict:
+    """The oracle as it stands on the host's cores, on bounded prefix samples
+    of the same workload: oracle_def (qsort by length, bytes, index) with
+    each length list on a thread of its own over every core the process may
+    use (the value), the same on one thread, and the paper's own method
+    (oracle_bubble, one thread) on the stand-in for its first dataset and, for
+    the 250k-word workload, on that whole list (Table 1's second dataset)."""
+    import oracle
+    oracle.build(force=False)
+    cores = len(os.sched_getaffinity(0))
+    n_all, dt_all = _grow_sample(wl, lambda c, o: oracle.oracle_def_parallel(c, o, threads=cores),
+                                 budget_s * 0.6, 1 << 21)
+    n_one, dt_one = _grow_sample(wl, oracle.oracle_def, budget_s * 0.4, 1 << 20)
+    res = {"value": n_all / dt_all / 1e6, "unit": "Mwords/s", "cores": cores, "kind": "oracle",
+           "sample": "oracle_def_parallel (each length list sorted by oracle_def on its own thread, %d threads) "
+                     "on the first %d words of the same workload, %.2f s" % (cores, n_all, dt_all),
+           "single_thread": {"value": n_one / dt_one / 1e6, "unit": "Mwords/s", "cores": 1,
+                             "sample": "oracle_def on the first %d words, %.2f s" % (n_one, dt_one)}}
     from paper_1411_5283_amd import wordgen
     c1 = wordgen.config(1)
     t0 = time.perf_counter()
     oracle.oracle_bubble(c1.chars, c1.offsets)
     res["oracle_bubble_35k_words_s"] = time.perf_counter() - t0
     res["paper_table1_dataset1_s"] = 6.639
+    if workload == "c2":
+        t0 = time.perf_counter()
+        oracle.oracle_bubble(wl.chars, wl.offsets)
+        res["oracle_bubble_250k_words_s"] = time.perf_counter() - t0
+        res["paper_table1_dataset2_s"] = 188.262
     res["paper_hardware"] = "Intel Core i7-3610QM 2.3 GHz (paper, Table 1)"
     try:
         with open("/proc/cpuinfo") as f:
             res["host_cpu"] = next((l.split(":", 1)[1].strip() for l in f if l.startswith("model name")), "?")
     except OSError:
         pass
-    res["host_cores_available"] = len(os.sched_getaffinity(0))
+    res["host_cores_available"] = cores
     return res
 
 
-def hbm_traffic(dominant_kernel: str, workload: str, tiles: dict):
-    """HBM bytes per launch of a kernel family from the committed rocprofv3
-    counter summary, if it was taken on the current kernel source, on the
-    same workload and with the same tile configuration."""
+def _counters(kind: str, kernel: str, workload: str, tiles: dict):
+    """The committed rocprofv3 counter summary of one kernel family, if it was
+    taken on the current kernel source, on the same workload and with the same
+    tile configuration (else None)."""
     try:
-        with open(TRAFFIC_FILE) as f:
+        with open(counter_file(kind, workload)) as f:
             t = json.load(f)
     except (OSError, ValueError):
         return None
@@ -194,8 +223,50 @@ def hbm_traffic(dominant_kernel: str, workload: str, tiles: dict):
         return None
     if t.get("tiles") != tiles:
         return None
-    k = t.get("kernels", {}).get(dominant_kernel)
+    return t.get("kernels", {}).get(kernel)
+
+
+def hbm_traffic(kernel: str, workload: str, tiles: dict):
+    """HBM bytes per launch of a kernel family (FETCH_SIZE + WRITE_SIZE, scaled
+    by a plain copy's reading), or None."""
+    k = _counters("hbm_traffic", kernel, workload, tiles)
     return None if k is None else k.get("bytes_per_launch")
+
+
+def alu_roofline(kernel: str, info: dict, workload: str, tiles: dict, fam_bytes: dict) -> dict:
+    """VALU view of a chunk-sort kernel: issued VALU lane-operations per launch
+    (SQ_INSTS_VALU x 64, from the committed counter summary of the same source,
+    workload and tiles) over the launch time measured live with HIP events."""
+    sq = _counters("sq_counters", kernel, workload, tiles)
+    us = info["avg_launch_us"]
+    launches = info["launches_per_step"]
+    r = {"bound": "alu", "kernel": kernel, "achieved": None, "peak": VALU_PEAK_TOPS, "unit": "TOP/s",
+         "frac": None, "traffic": hbm_traffic(kernel, workload, tiles), "avg_launch_us": us,
+         "algorithmic_bytes_per_launch": (fam_bytes.get(kernel, 0) / launches) if launches else None,
+         "what": "VALU lane-operations issued per second (wave instructions x 64 lanes); peak = 256 CUs x "
+                 "64 lanes x 2.4 GHz"}
+    if r["algorithmic_bytes_per_launch"]:
+        r["hbm_frac"] = r["algorithmic_bytes_per_launch"] / (us * 1e-6) / 1e9 / HBM_PEAK_GBS
+    if sq is None:
+        r["counters"] = None
+        return r
+    valu = sq.get("SQ_INSTS_VALU_per_dispatch")
+    if valu:
+        r["achieved"] = valu * 64 / (us * 1e-6) / 1e12
+        r["frac"] = r["achieved"] / VALU_PEAK_TOPS
+    cyc = sq.get("GRBM_GUI_ACTIVE_per_dispatch")
+    r["counters"] = {k: sq.get(k + "_per_dispatch") for k in
+                     ("SQ_INSTS_VALU", "SQ_ACTIVE_INST_VALU", "SQ_INSTS_LDS", "SQ_ACTIVE_INST_LDS",
+                      "SQ_LDS_BANK_CONFLICT", "SQ_WAVES", "SQ_BUSY_CYCLES", "SQ_INSTS_SALU", "GRBM_GUI_ACTIVE")}
+    if cyc and sq.get("SQ_ACTIVE_INST_VALU_per_dispatch"):
+        # quad-cycles summed over waves, over the 1024 SIMDs for the dispatch's clocks
+        r["valu_busy"] = sq["SQ_ACTIVE_INST_VALU_per_dispatch"] * 4 / (1024 * cyc)
+    if cyc and sq.get("SQ_ACTIVE_INST_LDS_per_dispatch"):
+        r["lds_busy"] = sq["SQ_ACTIVE_INST_LDS_per_dispatch"] * 4 / (1024 * cyc)
+    if sq.get("SQ_INSTS_LDS_per_dispatch"):
+        r["lds_conflict_cycles_per_lds_inst"] = sq.get("SQ_LDS_BANK_CONFLICT_per_dispatch", 0) / \
+            sq["SQ_INSTS_LDS_per_dispatch"]
+    return r
 
 
 # ------------------------------------------------------------------ serving
@@ -220,17 +291,22 @@ def serve_bench(args, sw, wordgen, torch):
     if not args.no_cpu_baseline:
         import oracle
         oracle.build(force=False)
+        from concurrent.futures import ThreadPoolExecutor
+        cores = len(os.sched_getaffinity(0))
         t0 = time.perf_counter()
         nw = 0
-        for r in meas:
-            oracle.oracle_def(r.chars, r.offsets)
-            nw += r.n
-            if time.perf_counter() - t0 > 10:
-                break
+        # requests in arrival order, each sorted by oracle_def on a thread of its own
+        with ThreadPoolExecutor(max_workers=cores) as ex:
+            for k0 in range(0, len(meas), cores):
+                part = meas[k0:k0 + cores]
+                list(ex.map(lambda r: oracle.oracle_def(r.chars, r.offsets), part))
+                nw += sum(r.n for r in part)
+                if time.perf_counter() - t0 > 10:
+                    break
         dt = time.perf_counter() - t0
-        cpu = {"value": nw / dt / 1e6, "unit": "Mwords/s", "cores": 1, "kind": "oracle",
-               "sample": "oracle_def on measured requests in arrival order until 10 s (%d words), "
-                         "one thread" % nw}
+        cpu = {"value": nw / dt / 1e6, "unit": "Mwords/s", "cores": cores, "kind": "oracle",
+               "sample": "oracle_def on the measured requests in arrival order, one request a thread on %d "
+                         "threads, until 10 s (%d words)" % (cores, nw)}
     sizes = np.array([r.n for r in meas])
     return {
         "metric": METRIC, "value": main_pt["mwords_s"], "unit": "Mwords/s", "n_gpus": 1,
@@ -493,7 +569,7 @@ def main():
                     help="merge choice per class, e.g. 0,0,0,0 (two-way levels) or 1,1,1,1 (four-way); "
                          "default: the tuned or built-in choice")
     ap.add_argument("--serve-warmup", type=int, default=200)
-    ap.add_argument("--serve-requests", type=int, default=1000)
+    ap.add_argument("--serve-requests", type=int, default=2000)
     ap.add_argument("--serve-slots", type=int, default=2)
     ap.add_argument("--serve-batch-words", type=int, default=1 << 21)
     ap.add_argument("--serve-batch-docs", type=int, default=64)
@@ -673,19 +749,28 @@ def main():
     tsum = sum(v["ms_per_step"] for v in kern.values())
     total_bytes = sum(fam_bytes.values())
     traffic = hbm_traffic(dom, args.workload, tile_cfg)
-    roof = {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": (achieved / HBM_PEAK_GBS) if achieved else None,
-            "traffic": traffic,
-            "algorithmic_bytes_per_launch": (fam_bytes.get(dom, 0) / dom_launches) if dom_launches else None,
-            "avg_launch_us": kern[dom]["avg_launch_us"],
-            "kernels": kern,
-            "whole_pass_algorithmic_GB": total_bytes / 1e9,
-            "whole_pass_GBs_at_plan_time": total_bytes / (ms_step / 1e3) / 1e9,
-            "eager_kernel_sum_ms": tsum}
+    chunk_fams = [k for k in kern if k.startswith("sort_tiles") or k.startswith("sort_packed")]
+    if dom in chunk_fams:
+        roof = alu_roofline(dom, kern[dom], args.workload, tile_cfg, fam_bytes)
+    else:
+        roof = {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": (achieved / HBM_PEAK_GBS) if achieved else None,
+                "traffic": traffic,
+                "algorithmic_bytes_per_launch": (fam_bytes.get(dom, 0) / dom_launches) if dom_launches else None,
+                "avg_launch_us": kern[dom]["avg_launch_us"]}
+    # the chunk sort (the paper's bubble-sort step) in its own bound, whichever kernel dominates
+    chunk_top = max(chunk_fams, key=lambda k: kern[k]["ms_per_step"]) if chunk_fams else None
+    roof.update({
+        "kernels": kern,
+        "chunk_sort": alu_roofline(chunk_top, kern[chunk_top], args.workload, tile_cfg, fam_bytes)
+        if chunk_top else None,
+        "whole_pass_algorithmic_GB": total_bytes / 1e9,
+        "whole_pass_GBs_at_plan_time": total_bytes / (ms_step / 1e3) / 1e9,
+        "eager_kernel_sum_ms": tsum})
 
     text = None if args.no_text else text_bench(args, sw, wordgen, torch, wl, chars, offs, docs, perm, boff,
                                                    perm_h, boff_h, stream, plan, ms_step, tile_cfg)
-    cpu = None if args.no_cpu_baseline else cpu_baseline(wl)
+    cpu = None if args.no_cpu_baseline else cpu_baseline(wl, args.workload)
     out = {
         "metric": METRIC, "value": value, "unit": "Mwords/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": ms_step, "higher_is_better": True, "scaling": "weak",

@@ -1,17 +1,21 @@
 """Summaries of rocprofv3 output for profiles/ (post-processing only).
 
     python -m paper_1411_5283_amd.profsum stats <kernel_stats.csv> "<command>" <out.txt>
-    python -m paper_1411_5283_amd.profsum traffic <fetch.csv> <write.csv> <copy_fetch.csv> \
+    python -m paper_1411_5283_amd.profsum traffic <workload> <fetch.csv> <write.csv> <copy_fetch.csv> \
         <copy_write.csv> <bench.json> <out.json> [<text_fetch.csv> <text_write.csv>]
+    python -m paper_1411_5283_amd.profsum valu <workload> <pmc.csv> <bench.json> <out.json>
 
 ``traffic`` averages FETCH_SIZE and WRITE_SIZE (KiB per dispatch) per kernel
 family and scales them by what the same counters read for a plain 1 GiB
 device copy (``bench.py --copy-calibration``), so that the result is HBM
-bytes per launch.
-The sort's kernels come from a run without the text steps (a run that writes
-text also keeps the sorted keys in the last merge level, which changes that
-level's traffic); the text kernels, found only in the second pair, from a run
-with them.
+bytes per launch.  The sort's kernels come from a run without the text steps
+(a run that writes text also keeps the sorted keys in the last merge level,
+which changes that level's traffic); the text kernels, found only in the
+second pair, from a run with them.
+
+``valu`` averages the SQ counters of one run (VALU and LDS instructions
+issued, the cycles waves spent in them, LDS bank conflicts, waves, busy
+cycles) per dispatch and kernel family.
 """
 from __future__ import annotations
 
@@ -22,20 +26,29 @@ import re
 import sys
 
 COPY_BYTES = 1 << 30
-COMMANDS = [
-    "rocprofv3 --pmc FETCH_SIZE --output-format csv -d gpurun_out/pmc_fetch -o f -- python3 bench.py "
-    "--serial --steps 1 --warmup 1 --profile-steps 1 --no-plain --no-cpu-baseline --no-check --no-text",
-    "rocprofv3 --pmc WRITE_SIZE --output-format csv -d gpurun_out/pmc_write -o w -- python3 bench.py "
-    "--serial --steps 1 --warmup 1 --profile-steps 1 --no-plain --no-cpu-baseline --no-check --no-text",
-    "rocprofv3 --pmc FETCH_SIZE --output-format csv -d gpurun_out/pmc_fetch_t -o f -- python3 bench.py "
-    "--serial --steps 1 --warmup 1 --profile-steps 1 --no-plain --no-cpu-baseline --no-check",
-    "rocprofv3 --pmc WRITE_SIZE --output-format csv -d gpurun_out/pmc_write_t -o w -- python3 bench.py "
-    "--serial --steps 1 --warmup 1 --profile-steps 1 --no-plain --no-cpu-baseline --no-check",
-    "rocprofv3 --pmc FETCH_SIZE --output-format csv -d gpurun_out/pmc_copyf -o cf -- python3 "
-    "bench.py --copy-calibration",
-    "rocprofv3 --pmc WRITE_SIZE --output-format csv -d gpurun_out/pmc_copyw -o cw -- python3 "
-    "bench.py --copy-calibration",
-]
+BENCH = ("python3 bench.py --workload {w} --serial --steps 1 --warmup 1 --profile-steps 1 --no-plain "
+         "--no-cpu-baseline --no-check")
+SQ_COUNTERS = ("SQ_INSTS_VALU SQ_ACTIVE_INST_VALU SQ_INSTS_LDS SQ_ACTIVE_INST_LDS SQ_LDS_BANK_CONFLICT SQ_WAVES "
+               "SQ_BUSY_CYCLES SQ_INSTS_SALU GRBM_GUI_ACTIVE")
+
+
+def traffic_commands(w: str) -> list:
+    b = BENCH.format(w=w)
+    return [
+        "rocprofv3 --pmc FETCH_SIZE --output-format csv -d gpurun_out/pmc_fetch_%s -o f -- %s --no-text" % (w, b),
+        "rocprofv3 --pmc WRITE_SIZE --output-format csv -d gpurun_out/pmc_write_%s -o w -- %s --no-text" % (w, b),
+        "rocprofv3 --pmc FETCH_SIZE --output-format csv -d gpurun_out/pmc_fetch_t_%s -o f -- %s" % (w, b),
+        "rocprofv3 --pmc WRITE_SIZE --output-format csv -d gpurun_out/pmc_write_t_%s -o w -- %s" % (w, b),
+        "rocprofv3 --pmc FETCH_SIZE --output-format csv -d gpurun_out/pmc_copyf -o cf -- python3 bench.py "
+        "--copy-calibration",
+        "rocprofv3 --pmc WRITE_SIZE --output-format csv -d gpurun_out/pmc_copyw -o cw -- python3 bench.py "
+        "--copy-calibration",
+    ]
+
+
+def valu_command(w: str) -> str:
+    return "rocprofv3 --pmc %s --output-format csv -d gpurun_out/pmc_sq_%s -o s -- %s --no-text" % (
+        SQ_COUNTERS, w, BENCH.format(w=w))
 
 
 def stats(src: str, cmd: str, out: str) -> None:
@@ -71,7 +84,17 @@ def _per_dispatch(path: str, counter: str) -> dict:
     return {k: (sum(v) / len(v), len(v)) for k, v in agg.items()}
 
 
-def traffic(fetch: str, write: str, cfetch: str, cwrite: str, bench_json: str, out: str,
+def _bench_line(bench_json: str) -> dict:
+    with open(bench_json) as fh:
+        return json.loads(fh.read().strip().splitlines()[-1])
+
+
+def _tiles(b: dict) -> dict:
+    c = b["config"]
+    return {"chunk": c.get("chunk"), "variant": c.get("variant"), "merge": c.get("merge")}
+
+
+def traffic(workload: str, fetch: str, write: str, cfetch: str, cwrite: str, bench_json: str, out: str,
             text_fetch: str | None = None, text_write: str | None = None) -> None:
     f = _per_dispatch(fetch, "FETCH_SIZE")
     w = _per_dispatch(write, "WRITE_SIZE")
@@ -86,8 +109,7 @@ def traffic(fetch: str, write: str, cfetch: str, cwrite: str, bench_json: str, o
     cf = _per_dispatch(cfetch, "FETCH_SIZE")["__amd_rocclr_copyBuffer"][0]
     cw = _per_dispatch(cwrite, "WRITE_SIZE")["__amd_rocclr_copyBuffer"][0]
     fs, wsc = COPY_BYTES / 1024 / cf, COPY_BYTES / 1024 / cw
-    with open(bench_json) as fh:
-        b = json.loads(fh.read().strip().splitlines()[-1])
+    b = _bench_line(bench_json)
     kern = {}
     for k, (fk, nd) in f.items():
         fam = _family(k)
@@ -97,11 +119,34 @@ def traffic(fetch: str, write: str, cfetch: str, cwrite: str, bench_json: str, o
         kern[fam] = {"kernel": k, "dispatches": nd, "fetch_kib_per_dispatch": fk, "write_kib_per_dispatch": wk,
                      "bytes_per_launch": fk * 1024 * fs + wk * 1024 * wsc}
     res = {"source_hash": b["kernel_source"], "workload": b["config"]["workload"] + " (bench.py --serial)",
-           "tiles": {"chunk": b["config"].get("chunk"), "variant": b["config"].get("variant")},
-           "fetch_scale": fs, "write_scale": wsc,
+           "tiles": _tiles(b), "fetch_scale": fs, "write_scale": wsc,
            "calibration": "plain device copy of 1 GiB (__amd_rocclr_copyBuffer): FETCH_SIZE %.0f KiB, "
                           "WRITE_SIZE %.0f KiB per dispatch" % (cf, cw),
-           "commands": COMMANDS, "kernels": kern}
+           "commands": traffic_commands(workload), "kernels": kern}
+    with open(out, "w") as fh:
+        json.dump(res, fh, indent=1, sort_keys=True)
+
+
+def valu(workload: str, pmc: str, bench_json: str, out: str) -> None:
+    agg = collections.defaultdict(lambda: collections.defaultdict(list))
+    for r in csv.DictReader(open(pmc)):
+        k = r["Kernel_Name"].split("(")[0].replace("void ", "")
+        agg[k][r["Counter_Name"]].append(float(r["Counter_Value"]))
+    b = _bench_line(bench_json)
+    kern = {}
+    for k, cs in agg.items():
+        fam = _family(k)
+        if fam is None:
+            continue
+        row = {"kernel": k, "dispatches": len(next(iter(cs.values())))}
+        for name, vals in cs.items():
+            row[name + "_per_dispatch"] = sum(vals) / len(vals)
+        kern[fam] = row
+    res = {"source_hash": b["kernel_source"], "workload": b["config"]["workload"] + " (bench.py --serial)",
+           "tiles": _tiles(b), "command": valu_command(workload), "kernels": kern,
+           "note": "SQ_INSTS_VALU counts wave instructions (each up to 64 lanes); SQ_ACTIVE_INST_VALU and "
+                   "SQ_ACTIVE_INST_LDS are quad-cycles summed over waves; values summed over every shader "
+                   "engine and XCD of the GPU"}
     with open(out, "w") as fh:
         json.dump(res, fh, indent=1, sort_keys=True)
 
@@ -110,6 +155,8 @@ if __name__ == "__main__":
     if sys.argv[1] == "stats":
         stats(*sys.argv[2:5])
     elif sys.argv[1] == "traffic":
-        traffic(*sys.argv[2:10])
+        traffic(*sys.argv[2:11])
+    elif sys.argv[1] == "valu":
+        valu(*sys.argv[2:6])
     else:
         raise SystemExit(__doc__)

@@ -1,4 +1,5 @@
 """Host-side logic that needs no GPU."""
+import json
 import sys
 import os
 
@@ -43,3 +44,30 @@ def test_levels_and_byte_model():
     assert fam["sort_tiles_c1"] == (12 + 4) * 3000 and "merge_c1" not in fam
     assert fam["hist"] == 4 * 13100
     assert fam["scatter_pack"] == (4 + 3 + 8) * 10000 + (4 + 6 + 12) * 100 + (4 + 7 + 12) * 3000
+
+
+def test_alu_roofline_from_counter_summary(tmp_path, monkeypatch):
+    """The chunk sort's VALU view: issued lane-operations (SQ_INSTS_VALU x 64)
+    per launch over the live launch time, against 256 CUs x 64 lanes x 2.4 GHz;
+    no counters for the current source, workload and tiles -> no fraction."""
+    assert abs(bench.VALU_PEAK_TOPS - 39.3216) < 1e-9
+    tiles = {"chunk": [16] * 4, "variant": [3, 3, 1, 0], "merge": [0] * 4}
+    info = {"avg_launch_us": 200.0, "launches_per_step": 1}
+    monkeypatch.setattr(bench, "counter_file", lambda kind, w: str(tmp_path / ("%s_%s.json" % (kind, w))))
+    r = bench.alu_roofline("sort_tiles_c0", info, "c3", tiles, {"sort_tiles_c0": 1.6e8})
+    assert r["bound"] == "alu" and r["achieved"] is None and r["frac"] is None and r["counters"] is None
+    assert abs(r["hbm_frac"] - 1.6e8 / 200e-6 / 1e9 / 8000) < 1e-12
+    row = {"SQ_INSTS_VALU_per_dispatch": 6.0e7, "SQ_ACTIVE_INST_VALU_per_dispatch": 1.2e8,
+           "GRBM_GUI_ACTIVE_per_dispatch": 480000.0, "SQ_INSTS_LDS_per_dispatch": 1e6,
+           "SQ_LDS_BANK_CONFLICT_per_dispatch": 5e5}
+    doc = {"source_hash": bench.kernel_source_hash(), "workload": "c3: docs (bench.py --serial)", "tiles": tiles,
+           "kernels": {"sort_tiles_c0": row}}
+    (tmp_path / "sq_counters_c3.json").write_text(json.dumps(doc))
+    r = bench.alu_roofline("sort_tiles_c0", info, "c3", tiles, {"sort_tiles_c0": 1.6e8})
+    assert abs(r["achieved"] - 6.0e7 * 64 / 200e-6 / 1e12) < 1e-9
+    assert abs(r["frac"] - r["achieved"] / bench.VALU_PEAK_TOPS) < 1e-12
+    assert abs(r["valu_busy"] - 1.2e8 * 4 / (1024 * 480000.0)) < 1e-12
+    assert r["lds_conflict_cycles_per_lds_inst"] == 0.5
+    # another tile configuration or workload: the summary does not apply
+    assert bench.alu_roofline("sort_tiles_c0", info, "c3", dict(tiles, chunk=[32] * 4), {})["frac"] is None
+    assert bench.alu_roofline("sort_tiles_c0", info, "c4", tiles, {})["frac"] is None
