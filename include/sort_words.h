@@ -52,7 +52,7 @@ extern "C" {
 
 #define SW_MAX_LEN 32
 #define SW_NUM_OFFSETS (SW_MAX_LEN + 2)
-#define SW_NUM_CLASSES 4   /* key classes: lengths 0-4, 5-8, 9-16, 17-32 */
+#define SW_NUM_CLASSES 5   /* key classes: lengths 0-4, 5-8, 9-16, 17-24, 25-32 */
 
 typedef enum {
     SW_OK = 0,
@@ -251,13 +251,14 @@ typedef struct {
  * and the batched entry points with parallel classes only. */
 #define SW_FLAG_SCHEDULE_BESIDE_SCATTER 4u
 /* Bits SW_FLAG_ORDER_SHIFT.. of flags: the order in which the key classes'
- * work is enqueued, as an index 0..23 into the 24 orders of the four classes
- * taken in lexicographic order (0: 0-1-2-3, 1: 0-1-3-2, ..., 23: 3-2-1-0).
+ * work is enqueued, as an index 0..119 into the 120 orders of the five
+ * classes taken in lexicographic order (0: 0-1-2-3-4, 1: 0-1-2-4-3, ...,
+ * 119: 4-3-2-1-0).
  * The classes' chains run concurrently either way; the order decides which
  * chunk sorts start first and hold the LDS.  Results are identical; the
  * autotuner chooses it per workload.  Larger indices are rejected. */
 #define SW_FLAG_ORDER_SHIFT 8
-#define SW_FLAG_ORDER_MASK (31u << SW_FLAG_ORDER_SHIFT)
+#define SW_FLAG_ORDER_MASK (127u << SW_FLAG_ORDER_SHIFT)
 int sw_get_config(sw_config *out);
 int sw_set_config(const sw_config *cfg);
 /* Number of compiled variants of class c, and the chunk-sort tile (words per

@@ -22,7 +22,7 @@ LIB_PATH = os.path.join(_HERE, "libsortwords.so")
 
 MAX_LEN = 32
 NUM_OFFSETS = MAX_LEN + 2
-NUM_CLASSES = 4
+NUM_CLASSES = 5           # key classes: lengths 0-4, 5-8, 9-16, 17-24, 25-32
 
 OK, ERR_INVALID_ARG, ERR_WORD_TOO_LONG, ERR_WORKSPACE, ERR_OOM, ERR_HIP = 0, -1, -2, -3, -4, -5
 _STATUS_NAMES = {0: "SW_OK", -1: "SW_ERR_INVALID_ARG", -2: "SW_ERR_WORD_TOO_LONG",
@@ -38,13 +38,14 @@ class SortWordsError(RuntimeError):
 FLAG_SERIAL_CLASSES = 1
 FLAG_PACKED_FIRST = 2
 FLAG_SCHEDULE_BESIDE_SCATTER = 4
-FLAG_ORDER_SHIFT = 8        # bits 8..12: index (0..23) of the classes' enqueue order
-FLAG_ORDER_MASK = 31 << FLAG_ORDER_SHIFT
+FLAG_ORDER_SHIFT = 8        # bits 8..14: index (0..119) of the classes' enqueue order
+FLAG_ORDER_MASK = 127 << FLAG_ORDER_SHIFT
+NUM_ORDERS = 120
 
 
 def class_order(index: int) -> list:
-    """The classes' enqueue order that order index 0..23 names (the orders of
-    0..3 in lexicographic order), for reporting a configuration."""
+    """The classes' enqueue order that order index 0..119 names (the orders of
+    0..4 in lexicographic order), for reporting a configuration."""
     import itertools
     return list(list(itertools.permutations(range(NUM_CLASSES)))[index])
 
@@ -288,6 +289,9 @@ def get_config() -> dict:
 
 def set_config(chunk=None, variant=None, flags=None, merge=None) -> dict:
     cur = get_config()
+    for name, v in (("chunk", chunk), ("variant", variant), ("merge", merge)):
+        if v is not None and len(v) != NUM_CLASSES:
+            raise ValueError("%s: one value per key class (%d), got %d" % (name, NUM_CLASSES, len(v)))
     c = sw_config()
     for k in range(NUM_CLASSES):
         c.chunk[k] = int((chunk if chunk is not None else cur["chunk"])[k])

@@ -13,7 +13,8 @@
 //   class 0: L 0..4    one u64 = (4 key bytes << 32) | index
 //   class 1: L 5..8    one lane + u32 index
 //   class 2: L 9..16   two lanes + u32 index
-//   class 3: L 17..32  four lanes + u32 index
+//   class 3: L 17..24  three lanes + u32 index
+//   class 4: L 25..32  four lanes + u32 index
 #pragma once
 #include <hip/hip_runtime.h>
 #include <stdint.h>
@@ -25,7 +26,7 @@ namespace sw {
 constexpr int kMaxLen = 32;
 constexpr int kNB = kMaxLen + 1;        // buckets L = 0..32
 constexpr int kNOff = kMaxLen + 2;      // bucket offsets per document
-constexpr int kNClass = 4;
+constexpr int kNClass = 5;
 constexpr int kMaxLev = 24;             // merge levels a segment may need
 constexpr uint32_t kWordsPerBlock = 4096;
 constexpr uint32_t kSegsPerBlock = 4096;
@@ -41,10 +42,11 @@ static_assert(kNKeys <= (1 << kKeyBits), "segment key bits");
 enum : uint32_t { ST_INVALID = 1u, ST_TOO_LONG = 2u, ST_WORKSPACE = 4u };
 
 __host__ __device__ inline int class_of_len(uint32_t L) {
-  return L <= 4 ? 0 : (L <= 8 ? 1 : (L <= 16 ? 2 : 3));
+  return L <= 4 ? 0 : (L <= 8 ? 1 : (L <= 16 ? 2 : (L <= 24 ? 3 : 4)));
 }
-// lanes stored per class (class 0 is packed with the index)
-__host__ __device__ constexpr int lanes_of_class(int c) { return c == 0 ? 0 : (c == 3 ? 4 : c); }
+// lanes stored per class (class 0 is packed with the index): the fewest
+// 8-byte lanes that hold the class's longest word
+__host__ __device__ constexpr int lanes_of_class(int c) { return c; }
 
 // Merge levels a segment of n items needs when tiles of T items come out of
 // the chunk sort already sorted: runs double each level until one run holds n.

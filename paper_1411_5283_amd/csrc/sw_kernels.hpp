@@ -563,6 +563,15 @@ __global__ __launch_bounds__(NT) void k_scatter_pack(Ws w) {
         w.a.k[0][dest] = ln[0];
         w.a.k[1][dest] = ln[1];
         w.a.idx[dest] = idx;
+      } else if (c == 3) {
+        uint64_t ln[3];
+        if (staged)
+          lds_be_lanes<3>(s_chr, pos, L, ln);
+        else
+          load_be_lanes<3>(chars + a, L, ln);
+#pragma unroll
+        for (int q = 0; q < 3; ++q) w.a.k[q][dest] = ln[q];
+        w.a.idx[dest] = idx;
       } else {
         uint64_t ln[4];
         if (staged)

@@ -98,10 +98,12 @@ const Variant* variants(int c, int* count) {
   static const Variant v2[] = {V<2, 256, 16, 256, 16, 0>::get(), V<2, 256, 8, 256, 8, 0>::get(),
                                V<2, 256, 8, 256, 16, 0>::get(), V<2, 256, 8, 256, 8, 1>::get(),
                                V<2, 512, 8, 256, 8, 1>::get(), V<2, 512, 8, 256, 16, 0>::get()};
-  static const Variant v3[] = {V<4, 256, 8, 256, 8, 0>::get(), V<4, 128, 16, 128, 16, 0>::get(),
+  static const Variant v3[] = {V<3, 256, 8, 256, 8, 0>::get(), V<3, 128, 16, 128, 16, 0>::get(),
+                               V<3, 128, 16, 256, 8, 0>::get()};
+  static const Variant v4[] = {V<4, 256, 8, 256, 8, 0>::get(), V<4, 128, 16, 128, 16, 0>::get(),
                                V<4, 128, 16, 256, 8, 0>::get()};
-  static const Variant* all[] = {v0, v1, v2, v3};
-  static const int counts[] = {7, 7, 6, 3};
+  static const Variant* all[] = {v0, v1, v2, v3, v4};
+  static const int counts[] = {7, 7, 6, 3, 3};
   *count = counts[c];
   return all[c];
 }
@@ -126,16 +128,17 @@ const Merge4* merges4(int c, int* count) {
   static const Merge4 m0[] = {V4<0, 128, 2, 256, 512>::get(), V4<0, 128, 4, 512, 1024>::get()};
   static const Merge4 m1[] = {V4<1, 128, 2, 256, 512>::get()};
   static const Merge4 m2[] = {V4<2, 256, 1, 256, 512>::get()};
-  static const Merge4 m3[] = {V4<4, 128, 1, 128, 256>::get()};
-  static const Merge4* all[] = {m0, m1, m2, m3};
-  static const int counts[] = {2, 1, 1, 1};
+  static const Merge4 m3[] = {V4<3, 128, 1, 128, 256>::get()};
+  static const Merge4 m4[] = {V4<4, 128, 1, 128, 256>::get()};
+  static const Merge4* all[] = {m0, m1, m2, m3, m4};
+  static const int counts[] = {2, 1, 1, 1, 1};
   *count = counts[c];
   return all[c];
 }
 
 // ------------------------------------------------------------------ config
 std::mutex g_cfg_mu;
-sw_config g_cfg = {{16, 16, 16, 16}, {0, 0, 0, 0}, 0, {0, 0, 0, 0}};
+sw_config g_cfg = {{16, 16, 16, 16, 16}, {0, 0, 0, 0, 0}, 0, {0, 0, 0, 0, 0}};
 
 sw_config current_config() {
   std::lock_guard<std::mutex> lk(g_cfg_mu);
@@ -291,14 +294,16 @@ Ws make_ws(void* base, const Layout& L, const sw_config& cfg, uint64_t max_chars
 // ------------------------------------------------------------------ profiling
 enum KernelId {
   K_BEGIN, K_DOC_PLAN, K_HIST, K_SCAN, K_SEGMENTS, K_SEG_COUNT, K_SEG_SCATTER, K_TILE_PREFIX, K_SCATTER,
-  K_SORT0, K_SORT1, K_SORT2, K_SORT3, K_MERGE0, K_MERGE1, K_MERGE2, K_MERGE3,
-  K_PACK0, K_PACK1, K_PACK2, K_PACK3, K_KEYS_TEXT, K_COUNT
+  K_SORT0, K_SORT1, K_SORT2, K_SORT3, K_SORT4, K_MERGE0, K_MERGE1, K_MERGE2, K_MERGE3, K_MERGE4,
+  K_PACK0, K_PACK1, K_PACK2, K_PACK3, K_PACK4, K_KEYS_TEXT, K_COUNT
 };
+static_assert(K_MERGE0 - K_SORT0 == sw::kNClass && K_PACK0 - K_MERGE0 == sw::kNClass &&
+              K_KEYS_TEXT - K_PACK0 == sw::kNClass, "one kernel id per class");
 const char* const kKernelNames[K_COUNT] = {
     "begin", "doc_plan", "hist", "scan_rows", "segments", "seg_count", "seg_scatter", "tile_prefix",
-    "scatter_pack", "sort_tiles_c0", "sort_tiles_c1", "sort_tiles_c2", "sort_tiles_c3",
-    "merge_c0", "merge_c1", "merge_c2", "merge_c3",
-    "sort_packed_c0", "sort_packed_c1", "sort_packed_c2", "sort_packed_c3", "keys_text"};
+    "scatter_pack", "sort_tiles_c0", "sort_tiles_c1", "sort_tiles_c2", "sort_tiles_c3", "sort_tiles_c4",
+    "merge_c0", "merge_c1", "merge_c2", "merge_c3", "merge_c4",
+    "sort_packed_c0", "sort_packed_c1", "sort_packed_c2", "sort_packed_c3", "sort_packed_c4", "keys_text"};
 
 struct ProfRec {
   int kid;
@@ -389,14 +394,15 @@ int make_grids(const Ws& w, const sw_config& cfg, Grids& g) {
   return SW_OK;
 }
 
-// The k-th order of the four classes in lexicographic order (k < 24): the
+// The k-th order of the five classes in lexicographic order (k < 120): the
 // factorial number system picks each position's class among those left.
+constexpr uint32_t kNOrders = 120;   // kNClass!
 void class_order(uint32_t k, int (&order)[sw::kNClass]) {
-  static_assert(sw::kNClass == 4, "24 orders of four classes");
+  static_assert(sw::kNClass == 5, "120 orders of five classes");
   int left[sw::kNClass];
   for (int c = 0; c < sw::kNClass; ++c) left[c] = c;
   int n = sw::kNClass;
-  uint32_t f = 6;   // (kNClass - 1)!
+  uint32_t f = 24;   // (kNClass - 1)!
   for (int i = 0; i < sw::kNClass; ++i) {
     const int j = (int)(k / f);
     order[i] = left[j];
@@ -407,24 +413,29 @@ void class_order(uint32_t k, int (&order)[sw::kNClass]) {
   }
 }
 
-// Side streams and events for running the four key classes concurrently:
-// after the scatter the classes share nothing, so each class's chain (chunk
-// sort, then one merge per level) goes on its own stream, forked
-// from and joined back into the caller's stream.  Under graph capture the
-// chains become parallel branches of the graph.
+// Side streams and events for running the key classes concurrently: after
+// the scatter the classes share nothing, so each class's chain (chunk sort,
+// then one merge per level) goes on a stream of its own, forked from and
+// joined back into the caller's stream; under graph capture the chains become
+// parallel branches of the graph.  The two long classes (17-24 and 25-32
+// bytes, the fewest words in text) share one stream, so that the chains fit
+// the four hardware queues a process gets by default: a fifth stream would
+// share a queue with another class and serialize behind it.
+constexpr int kNStreams = 4;
+inline int stream_of_class(int c) { return c < kNStreams ? c : kNStreams - 1; }
 struct Fork {
-  hipStream_t side[sw::kNClass] = {};   // side[0] unused: class 0 stays on the main stream
+  hipStream_t side[kNStreams] = {};   // side[0] unused: class 0 stays on the main stream
   hipEvent_t fork = nullptr;
-  hipEvent_t join[sw::kNClass] = {};
+  hipEvent_t join[kNStreams] = {};
   hipEvent_t seg_fork = nullptr, seg_join = nullptr;
   bool ready = false;
 };
 
 int fork_init(Fork& f) {
   if (f.ready) return SW_OK;
-  for (int c = 1; c < sw::kNClass; ++c) HIP_TRY(hipStreamCreateWithFlags(&f.side[c], hipStreamNonBlocking));
+  for (int c = 1; c < kNStreams; ++c) HIP_TRY(hipStreamCreateWithFlags(&f.side[c], hipStreamNonBlocking));
   HIP_TRY(hipEventCreateWithFlags(&f.fork, hipEventDisableTiming));
-  for (int c = 1; c < sw::kNClass; ++c) HIP_TRY(hipEventCreateWithFlags(&f.join[c], hipEventDisableTiming));
+  for (int c = 1; c < kNStreams; ++c) HIP_TRY(hipEventCreateWithFlags(&f.join[c], hipEventDisableTiming));
   HIP_TRY(hipEventCreateWithFlags(&f.seg_fork, hipEventDisableTiming));
   HIP_TRY(hipEventCreateWithFlags(&f.seg_join, hipEventDisableTiming));
   f.ready = true;
@@ -433,10 +444,10 @@ int fork_init(Fork& f) {
 
 void fork_free(Fork& f) {
   if (!f.ready) return;
-  for (int c = 1; c < sw::kNClass; ++c) {
+  for (int c = 1; c < kNStreams; ++c) {
     if (f.side[c]) (void)hipStreamSynchronize(f.side[c]);
   }
-  for (int c = 1; c < sw::kNClass; ++c) {
+  for (int c = 1; c < kNStreams; ++c) {
     if (f.side[c]) (void)hipStreamDestroy(f.side[c]);
     if (f.join[c]) (void)hipEventDestroy(f.join[c]);
   }
@@ -512,14 +523,14 @@ int enqueue_body(const Ws& w, const Grids& g, hipStream_t s, bool capture, bool 
   if (beside) HIP_TRY(hipStreamWaitEvent(s, fork->seg_join, 0));
   if (par) {
     HIP_TRY(hipEventRecord(fork->fork, s));
-    for (int c = 1; c < sw::kNClass; ++c) HIP_TRY(hipStreamWaitEvent(fork->side[c], fork->fork, 0));
+    for (int c = 1; c < kNStreams; ++c) HIP_TRY(hipStreamWaitEvent(fork->side[c], fork->fork, 0));
   }
   const TileWork none{0, 0, 0, 0, 0};
   // Each class keeps its own order on its own stream; across classes the work
   // is enqueued stage by stage (all chunk sorts, then merge level 0 of every
   // class, level 1, ...), so that a runtime which maps the parallel chains
   // onto fewer hardware queues still finds every class's next kernel early.
-  auto cstream = [&](int c) { return (par && c > 0) ? fork->side[c] : s; };
+  auto cstream = [&](int c) { return (par && c > 0) ? fork->side[stream_of_class(c)] : s; };
   int order[sw::kNClass];
   class_order((g.flags & SW_FLAG_ORDER_MASK) >> SW_FLAG_ORDER_SHIFT, order);
   int max_levels = 0;
@@ -553,7 +564,7 @@ int enqueue_body(const Ws& w, const Grids& g, hipStream_t s, bool capture, bool 
     }
   }
   if (par) {
-    for (int c = 1; c < sw::kNClass; ++c) {
+    for (int c = 1; c < kNStreams; ++c) {
       HIP_TRY(hipEventRecord(fork->join[c], fork->side[c]));
       HIP_TRY(hipStreamWaitEvent(s, fork->join[c], 0));
     }
@@ -653,7 +664,7 @@ int scratch_address(void** out) {
 extern "C" {
 
 const char* sort_words_last_error(void) { return g_err.c_str(); }
-const char* sort_words_version(void) { return "sortwords-gfx950 0.7"; }
+const char* sort_words_version(void) { return "sortwords-gfx950 0.8"; }
 
 size_t sort_words_workspace_size(uint32_t max_words, uint32_t max_docs) {
   Layout L;
@@ -1053,8 +1064,8 @@ int sw_set_config(const sw_config* cfg) {
   if (cfg->flags &
       ~(SW_FLAG_SERIAL_CLASSES | SW_FLAG_PACKED_FIRST | SW_FLAG_SCHEDULE_BESIDE_SCATTER | SW_FLAG_ORDER_MASK))
     return fail(SW_ERR_INVALID_ARG, "sw_set_config: unknown flags");
-  if (((cfg->flags & SW_FLAG_ORDER_MASK) >> SW_FLAG_ORDER_SHIFT) >= 24)
-    return fail(SW_ERR_INVALID_ARG, "sw_set_config: class order index %u is not below 24",
+  if (((cfg->flags & SW_FLAG_ORDER_MASK) >> SW_FLAG_ORDER_SHIFT) >= kNOrders)
+    return fail(SW_ERR_INVALID_ARG, "sw_set_config: class order index %u is not below 120",
                 (cfg->flags & SW_FLAG_ORDER_MASK) >> SW_FLAG_ORDER_SHIFT);
   std::lock_guard<std::mutex> lk(g_cfg_mu);
   g_cfg = *cfg;

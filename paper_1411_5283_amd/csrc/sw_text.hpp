@@ -605,10 +605,8 @@ __global__ __launch_bounds__(NT) void k_keys_text(Ws w) {
           wrel[r] = s_rel[lo] + (i - s_first[lo]) * (L + sw);
           ln[r][0] = (inb ? w.b.k[0] : w.a.k[0])[g];   // class 0: its index in the low half is masked off
           if (L > 8) ln[r][1] = (inb ? w.b.k[1] : w.a.k[1])[g];
-          if (L > 16) {
-            ln[r][2] = (inb ? w.b.k[2] : w.a.k[2])[g];
-            ln[r][3] = (inb ? w.b.k[3] : w.a.k[3])[g];
-          }
+          if (L > 16) ln[r][2] = (inb ? w.b.k[2] : w.a.k[2])[g];
+          if (L > 24) ln[r][3] = (inb ? w.b.k[3] : w.a.k[3])[g];
         }
       }
 #pragma unroll

@@ -3,7 +3,7 @@
     python -m paper_1411_5283_amd.profsum stats <kernel_stats.csv> "<command>" <out.txt>
     python -m paper_1411_5283_amd.profsum traffic <workload> <fetch.csv> <write.csv> <copy_fetch.csv> \
         <copy_write.csv> <bench.json> <out.json> [<text_fetch.csv> <text_write.csv>]
-    python -m paper_1411_5283_amd.profsum valu <workload> <pmc.csv> <bench.json> <out.json>
+    python -m paper_1411_5283_amd.profsum valu <workload> <pmc_a.csv>,<pmc_b.csv> <bench.json> <out.json>
 
 ``traffic`` averages FETCH_SIZE and WRITE_SIZE (KiB per dispatch) per kernel
 family and scales them by what the same counters read for a plain 1 GiB
@@ -13,9 +13,11 @@ bytes per launch.  The sort's kernels come from a run without the text steps
 which changes that level's traffic); the text kernels, found only in the
 second pair, from a run with them.
 
-``valu`` averages the SQ counters of one run (VALU and LDS instructions
-issued, the cycles waves spent in them, LDS bank conflicts, waves, busy
-cycles) per dispatch and kernel family.
+``valu`` averages the SQ counters of two runs (VALU and LDS instructions
+issued, the cycles waves spent in them, lane-cycles, LDS bank conflicts,
+waves, busy cycles) per dispatch and kernel family.  Every value is summed
+over the GPU's 8 XCDs and their shader engines; GRBM_GUI_ACTIVE too, so the
+dispatch's clock count is that counter / 8.
 """
 from __future__ import annotations
 
@@ -29,7 +31,9 @@ COPY_BYTES = 1 << 30
 BENCH = ("python3 bench.py --workload {w} --serial --steps 1 --warmup 1 --profile-steps 1 --no-plain "
          "--no-cpu-baseline --no-check")
 SQ_COUNTERS = ("SQ_INSTS_VALU SQ_ACTIVE_INST_VALU SQ_INSTS_LDS SQ_ACTIVE_INST_LDS SQ_LDS_BANK_CONFLICT SQ_WAVES "
-               "SQ_BUSY_CYCLES SQ_INSTS_SALU GRBM_GUI_ACTIVE")
+               "SQ_BUSY_CYCLES SQ_INSTS_SALU GRBM_GUI_ACTIVE",
+               "SQ_THREAD_CYCLES_VALU SQ_LDS_IDX_ACTIVE SQ_WAVE_CYCLES SQ_WAIT_INST_LDS SQ_ACTIVE_INST_VALU2 "
+               "GRBM_GUI_ACTIVE")
 
 
 def traffic_commands(w: str) -> list:
@@ -46,9 +50,9 @@ def traffic_commands(w: str) -> list:
     ]
 
 
-def valu_command(w: str) -> str:
-    return "rocprofv3 --pmc %s --output-format csv -d gpurun_out/pmc_sq_%s -o s -- %s --no-text" % (
-        SQ_COUNTERS, w, BENCH.format(w=w))
+def valu_commands(w: str) -> list:
+    return ["rocprofv3 --pmc %s --output-format csv -d gpurun_out/pmc_sq%d_%s -o s -- %s --no-text" % (
+        c, i, w, BENCH.format(w=w)) for i, c in enumerate(SQ_COUNTERS)]
 
 
 def stats(src: str, cmd: str, out: str) -> None:
@@ -64,7 +68,8 @@ def stats(src: str, cmd: str, out: str) -> None:
 
 
 def _family(kernel: str) -> str | None:
-    """Kernel name -> the bench's family name (class = template's first argument)."""
+    """Kernel name -> the bench's family name (the template's first argument,
+    the key lanes, is the class: lanes 0-4 for classes 0-4)."""
     m = re.match(r"(?:void )?sw::k_(\w+?)<(\d+)", kernel)
     if not m:
         m2 = re.match(r"(?:void )?sw::k_(\w+?)(?:[<(]|$)", kernel)
@@ -72,8 +77,7 @@ def _family(kernel: str) -> str | None:
     name, nl = m.group(1), int(m.group(2))
     if name in ("scatter_pack", "hist", "tok_scan", "materialize", "pack_full", "keys_text"):
         return name
-    cls = {0: 0, 1: 1, 2: 2, 4: 3}.get(nl)
-    return None if cls is None else "%s_c%d" % (name, cls)
+    return "%s_c%d" % (name, nl) if 0 <= nl <= 4 else None
 
 
 def _per_dispatch(path: str, counter: str) -> dict:
@@ -127,26 +131,27 @@ def traffic(workload: str, fetch: str, write: str, cfetch: str, cwrite: str, ben
         json.dump(res, fh, indent=1, sort_keys=True)
 
 
-def valu(workload: str, pmc: str, bench_json: str, out: str) -> None:
+def valu(workload: str, pmcs: str, bench_json: str, out: str) -> None:
     agg = collections.defaultdict(lambda: collections.defaultdict(list))
-    for r in csv.DictReader(open(pmc)):
-        k = r["Kernel_Name"].split("(")[0].replace("void ", "")
-        agg[k][r["Counter_Name"]].append(float(r["Counter_Value"]))
+    for pmc in pmcs.split(","):
+        for r in csv.DictReader(open(pmc)):
+            k = r["Kernel_Name"].split("(")[0].replace("void ", "")
+            agg[k][r["Counter_Name"]].append(float(r["Counter_Value"]))
     b = _bench_line(bench_json)
     kern = {}
     for k, cs in agg.items():
         fam = _family(k)
         if fam is None:
             continue
-        row = {"kernel": k, "dispatches": len(next(iter(cs.values())))}
+        row = {"kernel": k, "dispatches": len(cs["SQ_INSTS_VALU"]) if "SQ_INSTS_VALU" in cs else None}
         for name, vals in cs.items():
             row[name + "_per_dispatch"] = sum(vals) / len(vals)
         kern[fam] = row
     res = {"source_hash": b["kernel_source"], "workload": b["config"]["workload"] + " (bench.py --serial)",
-           "tiles": _tiles(b), "command": valu_command(workload), "kernels": kern,
+           "tiles": _tiles(b), "commands": valu_commands(workload), "kernels": kern,
            "note": "SQ_INSTS_VALU counts wave instructions (each up to 64 lanes); SQ_ACTIVE_INST_VALU and "
-                   "SQ_ACTIVE_INST_LDS are quad-cycles summed over waves; values summed over every shader "
-                   "engine and XCD of the GPU"}
+                   "SQ_ACTIVE_INST_LDS are quad-cycles summed over waves; every value is summed over the "
+                   "shader engines and the 8 XCDs (GRBM_GUI_ACTIVE / 8 = the dispatch's clocks)"}
     with open(out, "w") as fh:
         json.dump(res, fh, indent=1, sort_keys=True)
 

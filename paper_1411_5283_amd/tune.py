@@ -184,8 +184,11 @@ def refine_on_plan(wl, cfg: dict, rounds: int = 3, log=print, variants: bool = T
     if med[bf] < 0.995 * med.get(cur, float("inf")):
         cur = bf
     order = (best["flags"] & sw.FLAG_ORDER_MASK) >> sw.FLAG_ORDER_SHIFT
-    # then the classes' enqueue order (the 24 orders), with those flags
-    times = {k: [] for k in range(24)}
+    # then the classes' enqueue order, with those flags: the 24 orders of
+    # classes 0-3 with class 4 (lengths 25-32, rare in text) last
+    import itertools
+    perms = list(itertools.permutations(range(NUM_CLASSES)))
+    times = {perms.index(p + (NUM_CLASSES - 1,)): [] for p in itertools.permutations(range(NUM_CLASSES - 1))}
     for _ in range(rounds):
         for k in times:
             times[k].append(_plan_ms(sw, torch, dict(best, flags=cur | (k << sw.FLAG_ORDER_SHIFT)), words, ref))

@@ -65,7 +65,7 @@ def test_host_side_calls_without_gpu():
     cfg = sw.sw_config()
     assert L.sw_get_config(ctypes.byref(cfg)) == 0
     bad = sw.sw_config()
-    for k in range(4):
+    for k in range(sw.NUM_CLASSES):
         bad.chunk[k] = 48            # not a power of two
     assert L.sw_set_config(ctypes.byref(bad)) == sw.ERR_INVALID_ARG
     flagged = sw.sw_config()
@@ -75,12 +75,14 @@ def test_host_side_calls_without_gpu():
     flagged.flags = sw.FLAG_SERIAL_CLASSES | sw.FLAG_PACKED_FIRST | sw.FLAG_SCHEDULE_BESIDE_SCATTER
     assert L.sw_set_config(ctypes.byref(flagged)) == 0
     assert sw.get_config()["flags"] == 7
-    flagged.flags = 24 << sw.FLAG_ORDER_SHIFT     # only 24 class orders
+    flagged.flags = 120 << sw.FLAG_ORDER_SHIFT    # only 120 class orders
     assert L.sw_set_config(ctypes.byref(flagged)) == sw.ERR_INVALID_ARG
-    flagged.flags = 23 << sw.FLAG_ORDER_SHIFT
+    flagged.flags = 119 << sw.FLAG_ORDER_SHIFT
     assert L.sw_set_config(ctypes.byref(flagged)) == 0
-    assert sw.class_order(0) == [0, 1, 2, 3] and sw.class_order(1) == [0, 1, 3, 2]
-    assert sw.class_order(23) == [3, 2, 1, 0]
+    assert sw.class_order(0) == [0, 1, 2, 3, 4] and sw.class_order(1) == [0, 1, 2, 4, 3]
+    assert sw.class_order(119) == [4, 3, 2, 1, 0]
+    with pytest.raises(ValueError):
+        sw.set_config(chunk=[16] * 4)              # one value per class
     assert L.sw_set_config(ctypes.byref(cfg)) == 0
     assert sw.num_variants(0) >= 1 and sw.num_variants(7) == 0
     t, p = sw.variant_tiles(0, 0)

@@ -60,8 +60,8 @@ def test_long_segments_every_variant(gpu, oracle_mod, default_config, variant):
     # 1.5M words over few lengths: many merge levels and many tiles per workgroup
     wl = wordgen.single(1_500_000, 40_000, 1.1, 20, seed=5)
     _say("case long segments variant=%d n=%d" % (variant, wl.n))
-    gpu.set_config(chunk=[16, 32, 64, 16],
-                   variant=[min(variant, gpu.num_variants(c) - 1) for c in range(4)])
+    gpu.set_config(chunk=[16, 32, 64, 16, 32],
+                   variant=[min(variant, gpu.num_variants(c) - 1) for c in range(gpu.NUM_CLASSES)])
     _same(gpu.sort_wordlist(wl), _expect(oracle_mod, wl, bubble=False), "long variant %d" % variant)
 
 
@@ -71,7 +71,7 @@ def test_long_segments_every_merge(gpu, oracle_mod, default_config, merge):
     # class, on 1.5M words: many groups, workgroup ranges starting inside
     # groups at every level, short last groups
     wl = wordgen.single(1_500_000, 40_000, 1.1, 20, seed=9)
-    m = [min(merge, gpu.num_merges(c) - 1) for c in range(4)]
+    m = [min(merge, gpu.num_merges(c) - 1) for c in range(gpu.NUM_CLASSES)]
     _say("case long segments merge=%s n=%d" % (m, wl.n))
     gpu.set_config(merge=m)
     _same(gpu.sort_wordlist(wl), _expect(oracle_mod, wl, bubble=False), "long merge %s" % m)
@@ -82,7 +82,7 @@ def test_per_bucket_launch_every_merge(gpu, oracle_mod, default_config, merge):
     # the per-bucket-launch form launches each segment's merge passes directly
     import torch
     wl = wordgen.config(3, 0.01)
-    gpu.set_config(merge=[merge] * 4)
+    gpu.set_config(merge=[merge] * gpu.NUM_CLASSES)
     _say("case per-bucket launch merge=%d docs=%d n=%d" % (merge, wl.n_docs, wl.n))
     chars, offs, docs = gpu.device_words(wl)
     ws = torch.empty(gpu.sort_words_workspace_size(wl.n, wl.n_docs), dtype=torch.uint8, device="cuda")
@@ -102,13 +102,13 @@ def test_config1_bit_exact(gpu, oracle_mod):
 @pytest.mark.parametrize("variant", [0, 1])
 def test_config2_chunk1024_bit_exact(gpu, oracle_mod, default_config, variant):
     # 1024-word odd-even chunks in every class, as configured: variant 0 holds
-    # 8 items per thread in classes 2 and 3 (a chunk spans two waves), variant 1
-    # 8 in classes 0-2 and 16 in class 3 (a chunk spans one wave); the short
-    # segments' tiles always hold 8 per thread
+    # 8 items per thread in classes 2-4 (a chunk spans two waves), variant 1
+    # 8 in classes 0-2 and 16 in classes 3-4 (a chunk spans one wave); the
+    # short segments' tiles always hold 8 per thread
     wl = wordgen.config(2)
     _say("case config2 n=%d chunk=1024 variant=%d" % (wl.n, variant))
-    cfg = gpu.set_config(chunk=[1024] * 4, variant=[variant] * 4)
-    assert cfg["chunk"] == [1024] * 4
+    cfg = gpu.set_config(chunk=[1024] * gpu.NUM_CLASSES, variant=[variant] * gpu.NUM_CLASSES)
+    assert cfg["chunk"] == [1024] * gpu.NUM_CLASSES
     _same(gpu.sort_wordlist(wl), _expect(oracle_mod, wl, bubble=False), "config2")
 
 
@@ -132,7 +132,7 @@ def test_chunk_step_bit_exact(gpu, oracle_mod, default_config, chunk, variant):
     if CHUNK_WL is None:
         CHUNK_WL = _chunk_step_words()
     wl = CHUNK_WL
-    var = [min(variant, gpu.num_variants(c) - 1) for c in range(4)]
+    var = [min(variant, gpu.num_variants(c) - 1) for c in range(gpu.NUM_CLASSES)]
     _say("case chunk step chunk=%d variant=%s n=%d" % (chunk, var, wl.n))
     gpu.set_config(variant=var)
     chars, offs, _ = gpu.device_words(wl, "cuda")
@@ -150,8 +150,8 @@ def test_chunk_and_variant_sweep(gpu, oracle_mod, default_config, chunk, variant
     # several tiles, merge levels and a ragged tail in every class
     wl = wordgen.single(41_000, 3000, 1.0, 32, seed=77)
     _say("case sweep chunk=%d variant=%d" % (chunk, variant))
-    gpu.set_config(chunk=[chunk] * 4,
-                   variant=[min(variant, gpu.num_variants(c) - 1) for c in range(4)])
+    gpu.set_config(chunk=[chunk] * gpu.NUM_CLASSES,
+                   variant=[min(variant, gpu.num_variants(c) - 1) for c in range(gpu.NUM_CLASSES)])
     _same(gpu.sort_wordlist(wl), _expect(oracle_mod, wl, bubble=False),
           "chunk %d variant %d" % (chunk, variant))
 
@@ -169,6 +169,11 @@ def _edge_lists():
         "all_lengths": [bytes(rng.integers(0, 256, L, dtype=np.uint8)) for L in rng.integers(0, 33, 20000)],
         "unsigned_bytes": [bytes([b]) * L for b in (0, 1, 127, 128, 254, 255) for L in (1, 4, 5, 8, 9, 16, 17, 32)] * 50,
         "lane_edges": [bytes(rng.integers(97, 100, L, dtype=np.uint8)) for L in (8, 9, 16, 17, 24, 25, 32) for _ in range(1500)],
+        # every word of a length shares all bytes but the last: the order is
+        # decided in the class's last lane (lengths 16/17 and 24/25 sit on the
+        # edges of the three-lane class)
+        "last_byte_decides": [b"p" * (L - 1) + bytes([int(rng.integers(0, 256))])
+                              for L in (8, 9, 16, 17, 23, 24, 25, 31, 32) for _ in range(3000)],
     }
     for n in (4095, 4096, 4097, 8193, 2 * 4096 * 4 + 3):
         out["n=%d" % n] = [bytes(rng.integers(97, 99, 3, dtype=np.uint8)) for _ in range(n)]
@@ -183,6 +188,27 @@ def test_edge_cases(gpu, oracle_mod, name):
     wl = wordgen.from_words(EDGES[name])
     _say("case edge %s n=%d" % (name, wl.n))
     _same(gpu.sort_wordlist(wl), _expect(oracle_mod, wl, bubble=False), name)
+
+
+def _three_lane_words(n, seed):
+    # lengths 17-24 (three lanes) and 25-26 (four), a shared 16-byte prefix so
+    # that lanes 0-1 tie and lane 2 (or 3) decides, plenty of equal words
+    rng = np.random.default_rng(seed)
+    Ls = rng.choice(np.array([17, 18, 20, 23, 24, 25, 26]), n, p=[.3, .15, .15, .1, .2, .05, .05])
+    tails = rng.integers(97, 101, (n, 10), dtype=np.uint8)
+    return [b"0123456789abcdef" + tails[i, :L - 16].tobytes() for i, L in enumerate(Ls)]
+
+
+@pytest.mark.parametrize("variant,merge", [(0, 0), (1, 0), (2, 0), (0, 1)])
+def test_three_lane_class_long_segments(gpu, oracle_mod, default_config, variant, merge):
+    # long segments of the three-lane class: many tiles and merge levels
+    # (two-way, or four-way), every tile variant of classes 3 and 4
+    wl = wordgen.from_words(_three_lane_words(400_000, 17 + variant))
+    _say("case three-lane class variant=%d merge=%d n=%d" % (variant, merge, wl.n))
+    gpu.set_config(chunk=[16, 16, 16, 32, 64],
+                   variant=[min(variant, gpu.num_variants(c) - 1) for c in range(gpu.NUM_CLASSES)],
+                   merge=[min(merge, gpu.num_merges(c) - 1) for c in range(gpu.NUM_CLASSES)])
+    _same(gpu.sort_wordlist(wl), _expect(oracle_mod, wl, bubble=False), "three-lane v%d m%d" % (variant, merge))
 
 
 def test_nonzero_first_offset_and_unaligned_chars(gpu, oracle_mod):
@@ -360,7 +386,7 @@ def test_short_segment_order_flag(gpu, oracle_mod, default_config, flags):
 
 
 def test_every_class_order(gpu, oracle_mod, default_config):
-    # the 24 enqueue orders of the classes (with both launch-order flags and
+    # the 120 enqueue orders of the classes (with both launch-order flags and
     # without): the same result, eager and in a plan
     import torch
     docs = [wordgen.config(1, 0.1), _doc_with_segment_sizes([1023, 1024, 1025, 5, 2048], seed=5)]
@@ -370,7 +396,7 @@ def test_every_class_order(gpu, oracle_mod, default_config):
     chars, offs, ddocs = gpu.device_words(wl)
     perm = torch.empty(wl.n, dtype=torch.int32, device="cuda")
     boff = torch.empty(wl.n_docs * 34, dtype=torch.int32, device="cuda")
-    for k in range(24):
+    for k in range(gpu.NUM_ORDERS):
         flags = (k << gpu.FLAG_ORDER_SHIFT) | (6 if k % 2 else 0)
         _say("case class order %d flags=%d n=%d" % (k, flags, wl.n))
         gpu.set_config(flags=flags)

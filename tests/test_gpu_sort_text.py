@@ -175,7 +175,8 @@ def test_plan_alternates_sort_and_text(gpu, oracle_mod):
 def test_every_variant(gpu, oracle_mod, default_config, variant):
     wl = wordgen.single(400_000, 30_000, 1.1, 24, seed=7)
     _say("case text variant=%d n=%d" % (variant, wl.n))
-    gpu.set_config(chunk=[16, 32, 64, 16], variant=[min(variant, gpu.num_variants(c) - 1) for c in range(4)])
+    gpu.set_config(chunk=[16, 32, 64, 16, 32],
+                   variant=[min(variant, gpu.num_variants(c) - 1) for c in range(gpu.NUM_CLASSES)])
     plan = gpu.Plan(wl.n, 1)
     try:
         _check(gpu, oracle_mod, plan, wl, 10, "variant %d" % variant)

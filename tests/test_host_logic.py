@@ -26,15 +26,15 @@ def test_big_endian_lanes_order_equals_byte_order():
 
 
 def test_class_of_length_and_element_bytes():
-    assert [bench.class_of_len(L) for L in (0, 4, 5, 8, 9, 16, 17, 32)] == [0, 0, 1, 1, 2, 2, 3, 3]
-    assert [bench.element_bytes(c) for c in range(4)] == [8, 12, 20, 36]
+    assert [bench.class_of_len(L) for L in (0, 4, 5, 8, 9, 16, 17, 24, 25, 32)] == [0, 0, 1, 1, 2, 2, 3, 3, 4, 4]
+    assert [bench.element_bytes(c) for c in range(5)] == [8, 12, 20, 28, 36]
 
 
 def test_levels_and_byte_model():
     assert bench.levels_for(1, 4096) == 0 and bench.levels_for(4096, 4096) == 0
     assert bench.levels_for(4097, 4096) == 1 and bench.levels_for(8192, 4096) == 1
     assert bench.levels_for(8193, 4096) == 2
-    fam = bench.algorithmic_bytes([(3, 10000), (6, 100), (7, 3000)], [4096] * 4)
+    fam = bench.algorithmic_bytes([(3, 10000), (6, 100), (7, 3000)], [4096] * 5)
     # class 0 segment of 10000: m = 2 levels; chunk sort reads 8 and writes 8
     assert fam["sort_tiles_c0"] == 16 * 10000
     assert fam["merge_c0"] == (8 + 8) * 10000 + (8 + 4) * 10000
@@ -51,7 +51,7 @@ def test_alu_roofline_from_counter_summary(tmp_path, monkeypatch):
     per launch over the live launch time, against 256 CUs x 64 lanes x 2.4 GHz;
     no counters for the current source, workload and tiles -> no fraction."""
     assert abs(bench.VALU_PEAK_TOPS - 39.3216) < 1e-9
-    tiles = {"chunk": [16] * 4, "variant": [3, 3, 1, 0], "merge": [0] * 4}
+    tiles = {"chunk": [16] * 5, "variant": [3, 3, 1, 0, 0], "merge": [0] * 5}
     info = {"avg_launch_us": 200.0, "launches_per_step": 1}
     monkeypatch.setattr(bench, "counter_file", lambda kind, w: str(tmp_path / ("%s_%s.json" % (kind, w))))
     r = bench.alu_roofline("sort_tiles_c0", info, "c3", tiles, {"sort_tiles_c0": 1.6e8})
@@ -66,8 +66,9 @@ def test_alu_roofline_from_counter_summary(tmp_path, monkeypatch):
     r = bench.alu_roofline("sort_tiles_c0", info, "c3", tiles, {"sort_tiles_c0": 1.6e8})
     assert abs(r["achieved"] - 6.0e7 * 64 / 200e-6 / 1e12) < 1e-9
     assert abs(r["frac"] - r["achieved"] / bench.VALU_PEAK_TOPS) < 1e-12
-    assert abs(r["valu_busy"] - 1.2e8 * 4 / (1024 * 480000.0)) < 1e-12
+    assert abs(r["valu_busy"] - 1.2e8 * 4 / (1024 * 480000.0 / 8)) < 1e-12
+    assert abs(r["clock_GHz"] - 480000.0 / 8 / 200e-6 / 1e9) < 1e-12
     assert r["lds_conflict_cycles_per_lds_inst"] == 0.5
     # another tile configuration or workload: the summary does not apply
-    assert bench.alu_roofline("sort_tiles_c0", info, "c3", dict(tiles, chunk=[32] * 4), {})["frac"] is None
+    assert bench.alu_roofline("sort_tiles_c0", info, "c3", dict(tiles, chunk=[32] * 5), {})["frac"] is None
     assert bench.alu_roofline("sort_tiles_c0", info, "c4", tiles, {})["frac"] is None
