@@ -38,7 +38,7 @@ WORKLOADS = {
 }
 CSRC = [os.path.join(ROOT, "paper_1411_5283_amd", "csrc", f)
         for f in ("sw_device.hpp", "sw_keys.hpp", "sw_split.hpp", "sw_merge4.hpp", "sw_kernels.hpp", "sw_text.hpp",
-                  "sw_bytes.hpp", "sw_runtime.hip")]
+                  "sw_bytes.hpp", "sw_gather.hpp", "sw_runtime.hip")]
 # VALU issue rate of the whole GPU: 256 CUs x 4 SIMDs x 16 lanes per clock
 # (a wave64 instruction occupies its SIMD for 4 clocks) x 2.4 GHz, in tera
 # lane-operations per second (the fp32 vector figure, 157.3 TFLOP/s, is this
@@ -593,8 +593,8 @@ def main():
     ap.add_argument("--serve-warmup", type=int, default=200)
     ap.add_argument("--serve-requests", type=int, default=2000)
     ap.add_argument("--serve-slots", type=int, default=2)
-    ap.add_argument("--serve-batch-words", type=int, default=1 << 21)
-    ap.add_argument("--serve-batch-docs", type=int, default=64)
+    ap.add_argument("--serve-batch-words", type=int, default=1 << 22)
+    ap.add_argument("--serve-batch-docs", type=int, default=128)
     ap.add_argument("--serve-min-words", type=int, default=1 << 18)
     ap.add_argument("--serve-max-wait-ms", type=float, default=1.0)
     ap.add_argument("--serve-copy-threads", type=int, default=10)

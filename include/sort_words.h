@@ -324,17 +324,24 @@ int sort_words_materialize(const uint8_t *chars, const uint32_t *offsets,
 
 /* ------------------------------------------------------------ serving
  * Continuous batching of sort requests (not in the paper; the serving form of
- * the batched sort).  A host thread admits requests in arrival order while
- * the device bytes of all admitted requests (characters, offsets,
- * permutation, bucket offsets) stay within budget_bytes, packs every admitted
- * request that is not running into one batch (up to the batch limits), and
- * runs it as one sw_plan_run on a free slot (each slot: its own stream, plan
- * and pinned staging), so batches on different slots overlap on the device.
- * While a batch runs, the next one starts once it holds min_batch_words
- * words or max_batch_docs requests, or its oldest request has waited
- * max_wait_us.  copy_threads extra host threads help pack requests and copy
- * results out.  Device memory taken by the server itself (plans and staging)
- * is sw_server_fixed_bytes(cfg), outside the budget. */
+ * the batched sort).  sw_server_create allocates budget_bytes of device
+ * memory.  A host thread admits requests in arrival order while a block of
+ * that memory is free for each (its characters and offsets, each part
+ * rounded up to 256 bytes: swsrv::footprint); an admitted request is copied
+ * into its block at once by the upload threads (copy_threads of them, at
+ * least one; pinned staging, one upload stream), so requests wait for their
+ * batch on the device and their uploads overlap the batches running.  Every
+ * admitted, uploaded request that is not running is packed into the next
+ * batch (up to the batch limits) on the device, from the blocks into the
+ * slot's word list, and the batch runs as one sw_plan_run on a free slot
+ * (each slot: its own stream, plan and buffers), so batches on different
+ * slots overlap on the device.  While a batch runs, the next one starts once
+ * it holds min_batch_words words or max_batch_docs requests, or its oldest
+ * request has waited max_wait_us.  A request's block is freed when its batch
+ * completes; its results are copied out to the caller's buffers by the
+ * calling thread and copy_threads helpers.  Device memory taken by the
+ * server beside the budget (plans and slot buffers) is
+ * sw_server_fixed_bytes(cfg). */
 typedef struct sw_server sw_server;
 typedef struct {
     uint32_t slots;             /* 1..8 concurrent batches */
@@ -366,6 +373,10 @@ int sw_server_submit(sw_server *srv, const uint8_t *chars, const uint32_t *offse
 int sw_server_wait(sw_server *srv, uint64_t ticket, double *latency_s);
 int sw_server_stats(sw_server *srv, sw_server_counts *out);
 size_t sw_server_fixed_bytes(const sw_server_config *cfg);
+/* Bytes of the budget a request of n_words words and n_chars characters
+ * holds from its admission until its batch completes (characters, then the
+ * n_words+1 offsets, each rounded up to 256 bytes). */
+uint64_t sw_server_request_bytes(uint32_t n_words, uint64_t n_chars);
 /* Finishes every submitted request, then frees the server. */
 void sw_server_destroy(sw_server *srv);
 

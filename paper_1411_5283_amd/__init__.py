@@ -115,6 +115,7 @@ def lib() -> ctypes.CDLL:
         "sw_server_wait": ([vp, ctypes.c_uint64, ctypes.POINTER(ctypes.c_double)], i32),
         "sw_server_stats": ([vp, ctypes.POINTER(sw_server_counts)], i32),
         "sw_server_fixed_bytes": ([ctypes.POINTER(sw_server_config)], sz),
+        "sw_server_request_bytes": ([u32, ctypes.c_uint64], ctypes.c_uint64),
         "sw_server_destroy": ([vp], None),
         "sort_words_last_error": ([], ctypes.c_char_p),
         "sort_words_version": ([], ctypes.c_char_p),
@@ -135,7 +136,8 @@ EXPORTED = ("sort_words", "sort_words_workspace_size", "sort_words_ex", "sort_wo
             "sw_num_variants", "sw_num_merges", "sw_variant_tiles", "sw_profile_enable", "sw_profile_reset",
             "sw_profile_read", "sort_words_tokenize_workspace_size", "sort_words_tokenize",
             "sort_words_materialize", "sw_server_create", "sw_server_submit", "sw_server_wait",
-            "sw_server_stats", "sw_server_fixed_bytes", "sw_server_destroy", "sort_words_last_error",
+            "sw_server_stats", "sw_server_fixed_bytes", "sw_server_request_bytes", "sw_server_destroy",
+            "sort_words_last_error",
             "sort_words_version")
 
 
@@ -389,6 +391,11 @@ class NativeServer:
 
     def fixed_bytes(self) -> int:
         return int(lib().sw_server_fixed_bytes(ctypes.byref(self.cfg)))
+
+    @staticmethod
+    def request_bytes(n_words: int, n_chars: int) -> int:
+        """Bytes of the budget a request holds from admission until its batch completes."""
+        return int(lib().sw_server_request_bytes(int(n_words), int(n_chars)))
 
     def submit(self, chars, offsets) -> int:
         """Queue one request; returns its ticket (raises at once if it is refused)."""

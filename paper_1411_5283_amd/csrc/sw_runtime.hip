@@ -20,6 +20,7 @@
 #include "sort_words.h"
 #include "sw_kernels.hpp"
 #include "sw_text.hpp"
+#include "sw_gather.hpp"
 #include "sw_sched.hpp"
 
 namespace {
@@ -1197,9 +1198,11 @@ int sort_words_materialize(const uint8_t* chars, const uint32_t* offsets, const 
 
 // ------------------------------------------------------------------ serving
 // The serving loop (continuous batching): the scheduling rules are in
-// sw_sched.hpp; here are the GPU executor (one stream, one graph-captured
-// plan and pinned staging per slot), the host threads that pack requests
-// into staging and copy results out, and the scheduler thread.
+// sw_sched.hpp; here are the GPU executor (a device pool of the budget's
+// size that holds every admitted request, upload threads that copy each
+// request into its block as soon as it is admitted, and per slot a stream, a
+// graph-captured plan and the batch's buffers, packed on the device), the
+// host threads that copy results out, and the scheduler thread.
 namespace {
 
 // A few host threads for the copies of a batch; the calling thread takes the
@@ -1266,30 +1269,211 @@ class CopyPool {
   bool stop_ = false;
 };
 
+// Upload of admitted requests into their device blocks: worker threads copy
+// requests through two pinned staging buffers of their own and issue the
+// device copies on one upload stream, in one order for all workers (so the
+// upload event of the latest request of a batch covers the whole batch).
+// Requests admitted one after another usually get neighbouring blocks (the
+// pool hands out the lowest free block), so a worker takes as many queued
+// requests as lie back to back in device memory and fit its staging buffer,
+// lays them out there as in the pool, and moves them with one copy: a copy
+// has a fixed cost of its own that per-request copies of small requests
+// would pay thousands of times.  A request larger than the staging buffer
+// goes alone, in pieces.  A request's upload event is its staging buffer's;
+// the buffer's next use records it again, later on the same stream, so a
+// wait on it may wait longer but never too little.
+class Uploader {
+ public:
+  static constexpr uint64_t kStage = 4u << 20;
+
+  int init(unsigned workers, uint8_t* base, std::function<void()> notify) {
+    base_ = base;
+    notify_ = std::move(notify);
+    if (hipStreamCreateWithFlags(&s_, hipStreamNonBlocking) != hipSuccess) return SW_ERR_HIP;
+    stage_.resize(std::max(1u, workers));
+    for (Stage& st : stage_) {
+      for (int b = 0; b < 2; ++b) {
+        if (hipHostMalloc(&st.buf[b], kStage, 0) != hipSuccess) return SW_ERR_OOM;
+        if (hipEventCreateWithFlags(&st.ev[b], hipEventDisableTiming) != hipSuccess) return SW_ERR_HIP;
+      }
+    }
+    for (Stage& st : stage_) th_.emplace_back([this, &st] { loop(st); });
+    return SW_OK;
+  }
+  void stop() {
+    {
+      std::lock_guard<std::mutex> lk(mu_);
+      stop_ = true;
+    }
+    cv_.notify_all();
+    for (auto& t : th_) t.join();
+    th_.clear();
+    if (s_) (void)hipStreamSynchronize(s_);
+  }
+  void free_all() {
+    for (Stage& st : stage_)
+      for (int b = 0; b < 2; ++b) {
+        if (st.buf[b]) (void)hipHostFree(st.buf[b]);
+        if (st.ev[b]) (void)hipEventDestroy(st.ev[b]);
+      }
+    stage_.clear();
+    if (s_) (void)hipStreamDestroy(s_);
+    s_ = nullptr;
+  }
+  void push(swsrv::Request* r) {
+    {
+      std::lock_guard<std::mutex> lk(mu_);
+      q_.push_back(r);
+    }
+    cv_.notify_one();
+  }
+
+ private:
+  struct Stage {
+    uint8_t* buf[2] = {nullptr, nullptr};
+    hipEvent_t ev[2] = {nullptr, nullptr};
+    int next = 0;
+  };
+
+  void loop(Stage& st) {
+    std::vector<swsrv::Request*> group;
+    for (;;) {
+      {
+        std::unique_lock<std::mutex> lk(mu_);
+        cv_.wait(lk, [this] { return stop_ || !q_.empty(); });
+        if (q_.empty()) return;
+        // the queue's head and the requests right behind it in device memory
+        group.assign(1, q_.front());
+        q_.pop_front();
+        uint64_t end = group[0]->dev_off + group[0]->bytes;
+        while (group[0]->bytes <= kStage && !q_.empty() && q_.front()->dev_off == end &&
+               end + q_.front()->bytes - group[0]->dev_off <= kStage) {
+          end += q_.front()->bytes;
+          group.push_back(q_.front());
+          q_.pop_front();
+        }
+      }
+      const int rc = group[0]->bytes > kStage ? upload_large(st, group[0]) : upload_group(st, group);
+      for (swsrv::Request* r : group) {
+        r->upload_error = rc;
+        r->uploaded.store(true, std::memory_order_release);
+      }
+      notify_();
+    }
+  }
+
+  // the requests' blocks as laid out in the pool: characters, then the
+  // offsets at the next 256-byte boundary
+  static void layout(const swsrv::Request* r, const uint8_t** src, uint64_t* len, uint64_t* at) {
+    src[0] = r->nchars ? r->chars + r->offsets[0] : nullptr;
+    src[1] = (const uint8_t*)r->offsets;
+    len[0] = r->nchars;
+    len[1] = 4ull * (r->n + 1);
+    at[0] = 0;
+    at[1] = swsrv::DevicePool::rounded(r->nchars);
+  }
+
+  int next_buffer(Stage& st, int* b) {
+    *b = st.next;
+    st.next ^= 1;
+    return hipEventSynchronize(st.ev[*b]) == hipSuccess ? SW_OK : SW_ERR_HIP;   // its previous copy is done
+  }
+
+  int upload_group(Stage& st, const std::vector<swsrv::Request*>& group) {
+    const uint64_t start = group[0]->dev_off;
+    const uint64_t total = group.back()->dev_off + group.back()->bytes - start;
+    int b;
+    if (next_buffer(st, &b)) return SW_ERR_HIP;
+    for (const swsrv::Request* r : group) {
+      const uint8_t* src[2];
+      uint64_t len[2], at[2];
+      layout(r, src, len, at);
+      for (int part = 0; part < 2; ++part)
+        if (len[part]) memcpy(st.buf[b] + (r->dev_off - start) + at[part], src[part], len[part]);
+    }
+    std::lock_guard<std::mutex> lk(issue_mu_);
+    if (hipMemcpyAsync(base_ + start, st.buf[b], total, hipMemcpyHostToDevice, s_) != hipSuccess ||
+        hipEventRecord(st.ev[b], s_) != hipSuccess)
+      return SW_ERR_HIP;
+    ++seq_;
+    for (swsrv::Request* r : group) {
+      r->upload_event = st.ev[b];
+      r->upload_seq = seq_;
+    }
+    return SW_OK;
+  }
+
+  int upload_large(Stage& st, swsrv::Request* r) {
+    const uint8_t* src[2];
+    uint64_t len[2], at[2];
+    layout(r, src, len, at);
+    uint8_t* dst = base_ + r->dev_off;
+    for (int part = 0; part < 2; ++part) {
+      for (uint64_t pos = 0; pos < len[part]; pos += kStage) {
+        const uint64_t n = std::min(kStage, len[part] - pos);
+        int b;
+        if (next_buffer(st, &b)) return SW_ERR_HIP;
+        memcpy(st.buf[b], src[part] + pos, n);
+        std::lock_guard<std::mutex> lk(issue_mu_);
+        if (hipMemcpyAsync(dst + at[part] + pos, st.buf[b], n, hipMemcpyHostToDevice, s_) != hipSuccess ||
+            hipEventRecord(st.ev[b], s_) != hipSuccess)
+          return SW_ERR_HIP;
+        r->upload_event = st.ev[b];
+        r->upload_seq = ++seq_;
+      }
+    }
+    return SW_OK;
+  }
+
+  hipStream_t s_ = nullptr;
+  uint8_t* base_ = nullptr;
+  std::function<void()> notify_;
+  std::vector<Stage> stage_;
+  std::vector<std::thread> th_;
+  std::mutex mu_, issue_mu_;
+  std::condition_variable cv_;
+  std::deque<swsrv::Request*> q_;
+  uint64_t seq_ = 0;
+  bool stop_ = false;
+};
+
 struct SrvSlot {
   hipStream_t s = nullptr;
   sw_plan* plan = nullptr;
   uint8_t* d_chars = nullptr;
   uint32_t *d_offsets = nullptr, *d_docs = nullptr, *d_perm = nullptr, *d_boff = nullptr;
-  uint8_t* h_chars = nullptr;
-  uint32_t *h_offsets = nullptr, *h_docs = nullptr, *h_perm = nullptr, *h_boff = nullptr, *h_status = nullptr;
+  sw::GatherPiece *d_pieces = nullptr, *h_pieces = nullptr;
+  uint32_t *h_docs = nullptr, *h_perm = nullptr, *h_boff = nullptr, *h_status = nullptr;
   hipEvent_t ev = nullptr;
   std::vector<uint64_t> wpos, cpos;   // per request: first word and first char in the batch
 };
 
 class HipExec {
  public:
-  uint64_t max_words = 0, max_docs = 0, max_chars = 0;
+  uint64_t max_words = 0, max_docs = 0, max_chars = 0, max_pieces = 0;
   std::vector<SrvSlot> slot;
   CopyPool* pool = nullptr;
+  // the budget: one device allocation, handed out in blocks
+  uint8_t* d_pool = nullptr;
+  swsrv::DevicePool blocks;
+  Uploader up;
 
   uint32_t slots() const { return (uint32_t)slot.size(); }
   bool capacity(uint64_t words, uint64_t docs, uint64_t chars) const {
     return words <= max_words && docs <= max_docs && chars <= max_chars;
   }
 
-  // On an error the slot's stream is drained first, so the slot's staging is
-  // free again when the batch is closed.
+  // Called by the scheduler thread only.
+  bool reserve(swsrv::Request& r) {
+    if (!blocks.alloc(r.bytes, &r.dev_off)) return false;
+    up.push(&r);
+    return true;
+  }
+  bool uploaded(const swsrv::Request& r) { return r.uploaded.load(std::memory_order_acquire); }
+  void release(swsrv::Request& r) { blocks.release(r.dev_off, r.bytes); }
+
+  // On an error the slot's stream is drained first, so the slot's buffers
+  // are free again when the batch is closed.
   int launch(swsrv::Batch& b) {
     const int rc = enqueue(b);
     if (rc) (void)hipStreamSynchronize(slot[(size_t)b.slot].s);
@@ -1302,31 +1486,31 @@ class HipExec {
     sl.wpos.resize(nr + 1);
     sl.cpos.resize(nr + 1);
     sl.wpos[0] = sl.cpos[0] = 0;
-    for (size_t i = 0; i < nr; ++i) {
-      sl.wpos[i + 1] = sl.wpos[i] + b.reqs[i]->n;
-      sl.cpos[i + 1] = sl.cpos[i] + b.reqs[i]->nchars;
-    }
-    const uint64_t W = sl.wpos[nr], C = sl.cpos[nr];
-    // pack: characters back to back, offsets rebased onto the batch, document starts
-    sl.h_offsets[0] = 0;
     sl.h_docs[0] = 0;
-    const unsigned parts = std::min<unsigned>(pool->threads(), (unsigned)nr);
-    auto pack = [&](unsigned part) {
-      const size_t lo = nr * part / parts, hi = nr * (part + 1) / parts;
-      for (size_t i = lo; i < hi; ++i) {
-        const swsrv::Request* r = b.reqs[i];
-        const uint32_t o0 = r->offsets[0];
-        if (r->nchars) memcpy(sl.h_chars + sl.cpos[i], r->chars + o0, r->nchars);
-        uint32_t* dst = sl.h_offsets + sl.wpos[i] + 1;
-        const uint32_t base = (uint32_t)sl.cpos[i];
-        for (uint32_t k = 0; k < r->n; ++k) dst[k] = r->offsets[k + 1] - o0 + base;
-        sl.h_docs[i + 1] = (uint32_t)sl.wpos[i + 1];
+    const swsrv::Request* latest = b.reqs[0];
+    uint32_t np = 0;
+    for (size_t i = 0; i < nr; ++i) {
+      const swsrv::Request* r = b.reqs[i];
+      if (r->upload_error) return r->upload_error;
+      if (r->upload_seq > latest->upload_seq) latest = r;
+      sl.wpos[i + 1] = sl.wpos[i] + r->n;
+      sl.cpos[i + 1] = sl.cpos[i] + r->nchars;
+      sl.h_docs[i + 1] = (uint32_t)sl.wpos[i + 1];
+      const uint8_t* blk = d_pool + r->dev_off;
+      for (uint32_t k0 = 0; k0 == 0 || k0 < r->n; k0 += sw::kGatherWords) {
+        if (np >= max_pieces) return fail(SW_ERR_WORKSPACE, "server: batch pieces over capacity");
+        sl.h_pieces[np++] = sw::GatherPiece{blk, (const uint32_t*)(blk + swsrv::DevicePool::rounded(r->nchars)), k0,
+                                            std::min(r->n, k0 + sw::kGatherWords), r->n, (uint32_t)sl.wpos[i],
+                                            (uint32_t)sl.cpos[i]};
       }
-    };
-    pool->run(parts, pack);
-    HIP_TRY(hipMemcpyAsync(sl.d_chars, sl.h_chars, std::max<uint64_t>(C, 1), hipMemcpyHostToDevice, sl.s));
-    HIP_TRY(hipMemcpyAsync(sl.d_offsets, sl.h_offsets, 4 * (W + 1), hipMemcpyHostToDevice, sl.s));
+    }
+    const uint64_t W = sl.wpos[nr];
+    HIP_TRY(hipMemcpyAsync(sl.d_pieces, sl.h_pieces, sizeof(sw::GatherPiece) * np, hipMemcpyHostToDevice, sl.s));
     HIP_TRY(hipMemcpyAsync(sl.d_docs, sl.h_docs, 4 * (nr + 1), hipMemcpyHostToDevice, sl.s));
+    // the uploads are issued in one order on one stream: the batch's latest covers all
+    HIP_TRY(hipStreamWaitEvent(sl.s, (hipEvent_t)latest->upload_event, 0));
+    sw::k_gather<256><<<np, 256, 0, sl.s>>>(sl.d_pieces, sl.d_chars, sl.d_offsets);
+    HIP_TRY(hipGetLastError());
     int rc = sw_plan_run(sl.plan, sl.d_chars, sl.d_offsets, sl.d_docs, (uint32_t)nr, (uint32_t)W, sl.d_perm,
                          sl.d_boff);
     if (rc) return rc;
@@ -1359,6 +1543,12 @@ class HipExec {
   }
 };
 
+// Pieces of k_gather a batch can need: every request at least one, and one
+// more per kGatherWords words.
+uint64_t max_gather_pieces(uint64_t max_words, uint64_t max_docs) {
+  return max_words / sw::kGatherWords + max_docs + 1;
+}
+
 double srv_now() {
   using namespace std::chrono;
   return duration<double>(steady_clock::now().time_since_epoch()).count();
@@ -1380,6 +1570,7 @@ struct sw_server {
   swsrv::Counters counters;
   uint64_t next_ticket = 1;
   bool stop = false;
+  bool wake = false;        // an upload was issued: the scheduler looks again
   int thread_error = 0;
 };
 
@@ -1409,10 +1600,12 @@ static void server_loop(sw_server* sv) {
       for (swsrv::Request* r : done) r->finished = true;
       if (!done.empty()) sv->cv_done.notify_all();
     }
-    if (done.empty() && !launched && sv->sched->running()) {
-      // batches on the device and nothing to do: look again shortly
+    if (done.empty() && !launched) {
+      // batches on the device or uploads in flight, nothing to do: look again
+      // on the next submission or issued upload, or shortly
       std::unique_lock<std::mutex> lk(sv->mu);
-      sv->cv_in.wait_for(lk, std::chrono::microseconds(20), [sv] { return !sv->intake.empty(); });
+      sv->cv_in.wait_for(lk, std::chrono::microseconds(20), [sv] { return !sv->intake.empty() || sv->wake; });
+      sv->wake = false;
     }
   }
 }
@@ -1420,17 +1613,20 @@ static void server_loop(sw_server* sv) {
 static void server_free(sw_server* sv) {
   if (!sv) return;
   (void)hipSetDevice(sv->device);
+  sv->ex.up.stop();
   for (SrvSlot& sl : sv->ex.slot) {
     if (sl.s) (void)hipStreamSynchronize(sl.s);
     if (sl.plan) sw_plan_destroy(sl.plan);
     if (sl.ev) (void)hipEventDestroy(sl.ev);
-    for (void* d : {(void*)sl.d_chars, (void*)sl.d_offsets, (void*)sl.d_docs, (void*)sl.d_perm, (void*)sl.d_boff})
+    for (void* d : {(void*)sl.d_chars, (void*)sl.d_offsets, (void*)sl.d_docs, (void*)sl.d_perm, (void*)sl.d_boff,
+                    (void*)sl.d_pieces})
       if (d) (void)hipFree(d);
-    for (void* h : {(void*)sl.h_chars, (void*)sl.h_offsets, (void*)sl.h_docs, (void*)sl.h_perm, (void*)sl.h_boff,
-                    (void*)sl.h_status})
+    for (void* h : {(void*)sl.h_pieces, (void*)sl.h_docs, (void*)sl.h_perm, (void*)sl.h_boff, (void*)sl.h_status})
       if (h) (void)hipHostFree(h);
     if (sl.s) (void)hipStreamDestroy(sl.s);
   }
+  sv->ex.up.free_all();
+  if (sv->ex.d_pool) (void)hipFree(sv->ex.d_pool);
   delete sv;   // the ticket book frees the requests never waited for
 }
 
@@ -1458,6 +1654,7 @@ int sw_server_create(const sw_server_config* cfg, sw_server** out) {
   ex.max_words = cfg->max_batch_words;
   ex.max_docs = cfg->max_batch_docs;
   ex.max_chars = cfg->max_batch_chars;
+  ex.max_pieces = max_gather_pieces(cfg->max_batch_words, cfg->max_batch_docs);
   sv->pool.reset(new CopyPool(cfg->copy_threads));
   ex.pool = sv->pool.get();
   ex.slot.resize(cfg->slots);
@@ -1466,6 +1663,11 @@ int sw_server_create(const sw_server_config* cfg, sw_server** out) {
     server_free(sv);
     return rc;
   };
+  // the budget is device memory held from the start; admitted requests live in it
+  ex.blocks.reset(cfg->budget_bytes);
+  if (ex.blocks.capacity() && hipMalloc(&ex.d_pool, ex.blocks.capacity()) != hipSuccess)
+    return cleanup(fail(SW_ERR_OOM, "sw_server_create: device pool of %llu bytes",
+                        (unsigned long long)ex.blocks.capacity()));
   for (SrvSlot& sl : ex.slot) {
     if (hipStreamCreateWithFlags(&sl.s, hipStreamNonBlocking) != hipSuccess ||
         hipEventCreateWithFlags(&sl.ev, hipEventDisableTiming) != hipSuccess)
@@ -1474,13 +1676,24 @@ int sw_server_create(const sw_server_config* cfg, sw_server** out) {
     if (rc) return cleanup(rc);
     if (hipMalloc(&sl.d_chars, C) != hipSuccess || hipMalloc(&sl.d_offsets, 4 * (W + 1)) != hipSuccess ||
         hipMalloc(&sl.d_docs, 4 * (D + 1)) != hipSuccess || hipMalloc(&sl.d_perm, 4 * W) != hipSuccess ||
-        hipMalloc(&sl.d_boff, 4 * D * SW_NUM_OFFSETS) != hipSuccess)
+        hipMalloc(&sl.d_boff, 4 * D * SW_NUM_OFFSETS) != hipSuccess ||
+        hipMalloc(&sl.d_pieces, sizeof(sw::GatherPiece) * ex.max_pieces) != hipSuccess)
       return cleanup(fail(SW_ERR_OOM, "sw_server_create: device buffers"));
-    if (hipHostMalloc(&sl.h_chars, C, 0) != hipSuccess || hipHostMalloc(&sl.h_offsets, 4 * (W + 1), 0) != hipSuccess ||
+    if (hipHostMalloc(&sl.h_pieces, sizeof(sw::GatherPiece) * ex.max_pieces, 0) != hipSuccess ||
         hipHostMalloc(&sl.h_docs, 4 * (D + 1), 0) != hipSuccess || hipHostMalloc(&sl.h_perm, 4 * W, 0) != hipSuccess ||
         hipHostMalloc(&sl.h_boff, 4 * D * SW_NUM_OFFSETS, 0) != hipSuccess ||
         hipHostMalloc(&sl.h_status, 4, 0) != hipSuccess)
       return cleanup(fail(SW_ERR_OOM, "sw_server_create: pinned staging"));
+  }
+  {
+    const int rc = ex.up.init(std::max(1u, cfg->copy_threads), ex.d_pool, [sv] {
+      {
+        std::lock_guard<std::mutex> lk(sv->mu);
+        sv->wake = true;
+      }
+      sv->cv_in.notify_one();
+    });
+    if (rc) return cleanup(fail(rc, "sw_server_create: upload threads"));
   }
   sv->sched.reset(new swsrv::Scheduler<HipExec>(ex, sv->lim));
   sv->th = std::thread(server_loop, sv);
@@ -1551,8 +1764,11 @@ size_t sw_server_fixed_bytes(const sw_server_config* cfg) {
   if (!cfg) return 0;
   const uint64_t W = cfg->max_batch_words, D = cfg->max_batch_docs;
   return (size_t)cfg->slots * (sort_words_workspace_size((uint32_t)W, (uint32_t)D) + cfg->max_batch_chars +
-                               8 * (W + 1) + 4 * (D + 1) + 4 * D * SW_NUM_OFFSETS);
+                               8 * (W + 1) + 4 * (D + 1) + 4 * D * SW_NUM_OFFSETS +
+                               sizeof(sw::GatherPiece) * max_gather_pieces(W, D));
 }
+
+uint64_t sw_server_request_bytes(uint32_t n_words, uint64_t n_chars) { return swsrv::footprint(n_words, n_chars); }
 
 void sw_server_destroy(sw_server* sv) {
   if (!sv) return;

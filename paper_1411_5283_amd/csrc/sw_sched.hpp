@@ -2,6 +2,10 @@
 // code only (no HIP): the device side is an executor type with
 //   uint32_t slots() const;                       concurrent batches
 //   bool capacity(uint64_t words, uint64_t docs, uint64_t chars) const;
+//   bool reserve(Request&);                       device memory for an admitted request
+//                                                 (its upload starts); false: none free yet
+//   bool uploaded(const Request&);                its upload has been issued
+//   void release(Request&);                       its device memory is free again
 //   int  launch(Batch&);                          0, or an sw_status for the whole batch
 //   bool poll(const Batch&);                      true once the batch has completed
 //   int  finish(Batch&);                          results into the requests' buffers; 0 or an sw_status
@@ -9,19 +13,24 @@
 // a stand-in executor in a CPU test.
 //
 // Rules: requests are admitted in arrival order while the device bytes of
-// every admitted request stay within the budget (the head of the queue is
-// never overtaken); every admitted request that is not running is packed,
-// in order, into the next batch up to the batch limits; while another batch
-// is running, a new one starts only once it holds min_batch_words words, or
-// max_batch_docs documents, or its oldest request has waited max_wait_s; a
-// request's bytes are released when its batch completes.  A batch that fails
-// on the device fails all its requests; a request rejected at intake fails
-// alone.
+// every admitted request stay within the budget and the executor finds them
+// a block of device memory (the head of the queue is never overtaken); an
+// admitted request is uploaded into its block at once, so queued requests
+// wait on the device; every admitted request whose upload has been issued
+// and that is not running is packed, in order, into the next batch up to the
+// batch limits; while another batch is running, a new one starts only once
+// it holds min_batch_words words, or max_batch_docs documents, or its oldest
+// request has waited max_wait_s; a request's device memory is released when
+// its batch completes.  A batch that fails on the device fails all its
+// requests; a request rejected at intake fails alone.
 #pragma once
 
 #include <algorithm>
+#include <atomic>
 #include <cstdint>
 #include <deque>
+#include <iterator>
+#include <map>
 #include <unordered_map>
 #include <vector>
 
@@ -40,6 +49,75 @@ struct Request {
   int status = 0;
   bool finished = false;            // set by the serving thread under its lock
   bool claimed = false;             // a caller is waiting for it
+  // the executor's: where the request lies in device memory, and its upload
+  uint64_t dev_off = 0;
+  std::atomic<bool> uploaded{false};
+  uint64_t upload_seq = 0;          // issue order of the upload (valid once uploaded)
+  int upload_error = 0;
+  void* upload_event = nullptr;
+};
+
+// Device memory of the admitted requests: one region of `capacity` bytes
+// handed out first fit in 256-byte units; a freed block merges with its free
+// neighbours.  Bookkeeping only (offsets into the region).
+class DevicePool {
+ public:
+  static constexpr uint64_t kAlign = 256;
+  static uint64_t rounded(uint64_t bytes) { return (std::max<uint64_t>(bytes, 1) + kAlign - 1) / kAlign * kAlign; }
+
+  explicit DevicePool(uint64_t capacity = 0) { reset(capacity); }
+  void reset(uint64_t capacity) {
+    cap_ = capacity / kAlign * kAlign;
+    used_ = 0;
+    free_.clear();
+    if (cap_) free_[0] = cap_;
+  }
+  // the lowest free block that holds `bytes` (rounded up), or false
+  bool alloc(uint64_t bytes, uint64_t* off) {
+    const uint64_t b = rounded(bytes);
+    for (auto it = free_.begin(); it != free_.end(); ++it) {
+      if (it->second < b) continue;
+      *off = it->first;
+      const uint64_t at = it->first + b, rest = it->second - b;
+      free_.erase(it);
+      if (rest) free_[at] = rest;
+      used_ += b;
+      return true;
+    }
+    return false;
+  }
+  // a block handed out by alloc(bytes), back to the free list
+  void release(uint64_t off, uint64_t bytes) {
+    const uint64_t b = rounded(bytes);
+    used_ -= b;
+    uint64_t start = off, len = b;
+    auto next = free_.lower_bound(off);
+    if (next != free_.end() && next->first == off + b) {
+      len += next->second;
+      next = free_.erase(next);
+    }
+    if (next != free_.begin()) {
+      auto prev = std::prev(next);
+      if (prev->first + prev->second == off) {
+        start = prev->first;
+        len += prev->second;
+        free_.erase(prev);
+      }
+    }
+    free_[start] = len;
+  }
+  uint64_t capacity() const { return cap_; }
+  uint64_t used() const { return used_; }
+  size_t free_blocks() const { return free_.size(); }
+  uint64_t largest_free() const {
+    uint64_t m = 0;
+    for (const auto& kv : free_) m = std::max(m, kv.second);
+    return m;
+  }
+
+ private:
+  std::map<uint64_t, uint64_t> free_;   // offset -> length of every free block
+  uint64_t cap_ = 0, used_ = 0;
 };
 
 // The requests that have a ticket and have not been waited for.  A ticket is
@@ -93,10 +171,11 @@ struct Counters {
   uint64_t in_use = 0, max_in_use = 0;
 };
 
-// Device bytes a request holds while admitted: characters, offsets, the
-// output permutation and its bucket-offset row.
+// Device bytes a request holds from admission until its batch completes:
+// its characters, then its n+1 offsets, each part in whole 256-byte units
+// (the results go to the batch slot's own buffers).
 inline uint64_t footprint(uint64_t n_words, uint64_t n_chars) {
-  return n_chars + 4 * (n_words + 1) + 4 * n_words + 4 * 34;
+  return DevicePool::rounded(n_chars) + DevicePool::rounded(4 * (n_words + 1));
 }
 
 template <class Exec>
@@ -145,6 +224,7 @@ class Scheduler {
     while (!queue_.empty()) {
       Request* r = queue_.front();
       if (c_.in_use + r->bytes > lim_.budget_bytes) break;
+      if (!ex_.reserve(*r)) break;   // no free block large enough until a batch completes
       queue_.pop_front();
       c_.in_use += r->bytes;
       c_.max_in_use = std::max(c_.max_in_use, c_.in_use);
@@ -152,19 +232,22 @@ class Scheduler {
     }
   }
 
-  bool worth_launching(double now) const {
+  // the first `up` ready requests (those uploaded) make a batch worth starting
+  bool worth_launching(double now, size_t up) const {
     if (running_.empty()) return true;
     uint64_t words = 0;
-    for (const Request* r : ready_) words += r->n;
-    if (words >= lim_.min_batch_words || ready_.size() >= lim_.max_batch_docs) return true;
+    for (size_t i = 0; i < up; ++i) words += ready_[i]->n;
+    if (words >= lim_.min_batch_words || up >= lim_.max_batch_docs) return true;
     return now - ready_.front()->arrival >= lim_.max_wait_s;
   }
 
   void launch(double now, std::vector<Request*>& done) {
-    while (!ready_.empty() && !free_slots_.empty() && worth_launching(now)) {
+    size_t up = 0;   // ready requests, in order, whose upload has been issued
+    while (up < ready_.size() && ex_.uploaded(*ready_[up])) ++up;
+    while (up > 0 && !free_slots_.empty() && worth_launching(now, up)) {
       Batch b;
       size_t k = 0;
-      for (; k < ready_.size(); ++k) {
+      for (; k < up; ++k) {
         Request* r = ready_[k];
         if (k && (b.words + r->n > lim_.max_batch_words || b.reqs.size() >= lim_.max_batch_docs ||
                   b.chars + r->nchars > lim_.max_batch_chars ||
@@ -175,6 +258,7 @@ class Scheduler {
         b.chars += r->nchars;
       }
       ready_.erase(ready_.begin(), ready_.begin() + (long)k);
+      up -= k;
       b.slot = free_slots_.back();
       free_slots_.pop_back();
       b.launched = now;
@@ -194,6 +278,7 @@ class Scheduler {
     for (Request* r : b.reqs) {
       r->done = now;
       r->status = st;
+      ex_.release(*r);
       c_.in_use -= r->bytes;
       if (st) {
         ++c_.failed;

@@ -3,6 +3,8 @@
 // broken rule and exits 1.
 #include <cstdio>
 #include <cstdlib>
+#include <map>
+#include <random>
 #include <set>
 #include <vector>
 
@@ -31,12 +33,30 @@ struct FakeExec {
   std::vector<double> finish_at;
   std::vector<int> running_per_launch;
   int running = 0, max_running = 0;
+  // device memory: a pool as large as the budget; uploads take upload_s
+  swsrv::DevicePool pool{1ull << 40};
+  double upload_s = 0;
+  std::map<uint64_t, double> upload_done;   // ticket -> when its upload is issued
+  uint64_t reserve_refused = 0, seq = 0;
 
   uint32_t slots() const { return nslots; }
   bool capacity(uint64_t w, uint64_t d, uint64_t c) const { return w <= max_words && d <= max_docs && c <= max_chars; }
+  bool reserve(Request& r) {
+    if (!pool.alloc(r.bytes, &r.dev_off)) {
+      ++reserve_refused;
+      return false;
+    }
+    upload_done[r.ticket] = *clock + upload_s;
+    return true;
+  }
+  bool uploaded(const Request& r) { return *clock >= upload_done.at(r.ticket); }
+  void release(Request& r) { pool.release(r.dev_off, r.bytes); }
   int launch(Batch& b) {
     std::vector<uint64_t> t;
-    for (Request* r : b.reqs) t.push_back(r->ticket);
+    for (Request* r : b.reqs) {
+      t.push_back(r->ticket);
+      CHECK(uploaded(*r), "request %llu launched before its upload", (unsigned long long)r->ticket);
+    }
     launched.push_back(t);
     finish_at.resize((size_t)b.slot + 1 > finish_at.size() ? (size_t)b.slot + 1 : finish_at.size());
     finish_at[(size_t)b.slot] = *clock + 1e-5 + per_word * (double)b.words;
@@ -200,6 +220,104 @@ int main() {
     for (uint64_t t = 10; t < 2000; ++t) book.add(make(t, 1, 0, st));
     CHECK(r->ticket == 3 && r->claimed, "claimed request changed");
     book.release(3);
+  }
+  // 6. the device pool: first fit, no overlap, freed neighbours merge;
+  // random allocations and frees against a map of every 256-byte unit
+  {
+    const uint64_t units = 4096;
+    swsrv::DevicePool pool(units * 256 + 100);   // the odd tail is not used
+    CHECK(pool.capacity() == units * 256, "capacity %llu", (unsigned long long)pool.capacity());
+    std::vector<int> owner(units, -1);
+    std::map<int, std::pair<uint64_t, uint64_t>> live;   // id -> (offset, bytes)
+    std::mt19937_64 rng(5);
+    int next_id = 0;
+    uint64_t refused = 0;
+    for (int it = 0; it < 200000; ++it) {
+      if (live.empty() || rng() % 100 < 55) {
+        const uint64_t bytes = rng() % 4 == 0 ? rng() % 300 : rng() % 40000;
+        uint64_t off = 0;
+        const uint64_t need = swsrv::DevicePool::rounded(bytes) / 256;
+        // the lowest run of `need` free units, from the map
+        uint64_t want = ~0ull;
+        for (uint64_t u = 0, run = 0; u < units; ++u) {
+          run = owner[u] < 0 ? run + 1 : 0;
+          if (run == need) {
+            want = u + 1 - need;
+            break;
+          }
+        }
+        const bool ok = pool.alloc(bytes, &off);
+        CHECK(ok == (want != ~0ull), "alloc of %llu bytes: pool says %d, map says %d", (unsigned long long)bytes,
+              (int)ok, (int)(want != ~0ull));
+        if (!ok) {
+          ++refused;
+          continue;
+        }
+        CHECK(off == want * 256, "first fit: got %llu, lowest fit %llu", (unsigned long long)off,
+              (unsigned long long)(want * 256));
+        for (uint64_t u = off / 256; u < off / 256 + need; ++u) owner[u] = next_id;
+        live[next_id++] = {off, bytes};
+      } else {
+        auto itl = live.begin();
+        std::advance(itl, (long)(rng() % live.size()));
+        const uint64_t off = itl->second.first, bytes = itl->second.second;
+        pool.release(off, bytes);
+        for (uint64_t u = off / 256; u < off / 256 + swsrv::DevicePool::rounded(bytes) / 256; ++u) owner[u] = -1;
+        live.erase(itl);
+      }
+      uint64_t used = 0;
+      for (int o : owner) used += o >= 0 ? 256 : 0;
+      CHECK(pool.used() == used, "used %llu, map %llu", (unsigned long long)pool.used(), (unsigned long long)used);
+    }
+    CHECK(refused > 0, "the pool never filled up");
+    for (auto& kv : live) pool.release(kv.second.first, kv.second.second);
+    CHECK(pool.used() == 0 && pool.free_blocks() == 1 && pool.largest_free() == pool.capacity(),
+          "free blocks did not merge back into one");
+  }
+  // 7. admission on real blocks: a small pool, requests of mixed sizes,
+  // uploads that take time; the budget binds, nothing overlaps, no request
+  // runs before its upload, all finish in order
+  {
+    double clock = 0;
+    FakeExec ex;
+    ex.clock = &clock;
+    ex.upload_s = 3e-5;
+    ex.max_words = 4000;
+    ex.max_chars = 1 << 20;
+    swsrv::Limits lim;
+    lim.budget_bytes = 60 * 1024;
+    lim.max_batch_words = 4000;
+    lim.max_batch_docs = 8;
+    ex.pool.reset(lim.budget_bytes);
+    swsrv::Scheduler<FakeExec> s(ex, lim);
+    std::mt19937_64 rng(9);
+    const int N = 400;
+    std::vector<std::vector<uint32_t>> store(N);
+    std::vector<Request*> reqs, done;
+    uint64_t total = 0;
+    for (int i = 0; i < N; ++i) {
+      reqs.push_back(make((uint64_t)i + 1, (uint32_t)(rng() % 3 ? rng() % 300 : 1000 + rng() % 2000), clock,
+                          store[(size_t)i]));
+      CHECK(s.acceptable(*reqs.back()), "request %d refused", i);
+      total += reqs.back()->bytes;
+      s.enqueue(reqs.back());
+    }
+    uint64_t max_used = 0;
+    for (int it = 0; it < 1000000 && s.busy(); ++it) {
+      s.step(clock, done);
+      CHECK(ex.pool.used() <= lim.budget_bytes && s.counters().in_use == ex.pool.used(),
+            "pool %llu, counted %llu", (unsigned long long)ex.pool.used(), (unsigned long long)s.counters().in_use);
+      max_used = std::max(max_used, ex.pool.used());
+      clock += 1e-5;
+    }
+    CHECK(!s.busy() && done.size() == (size_t)N, "did not drain (%zu of %d)", done.size(), N);
+    CHECK(total > 10 * lim.budget_bytes && max_used > lim.budget_bytes / 2, "the budget never bound");
+    CHECK(ex.pool.used() == 0 && ex.pool.free_blocks() == 1, "device memory not returned");
+    uint64_t expect = 1;
+    for (const auto& b : ex.launched)
+      for (uint64_t t : b) CHECK(t == expect++, "request %llu out of order", (unsigned long long)t);
+    std::printf("pool refusals under the budget (fragmentation): %llu\n", (unsigned long long)ex.reserve_refused);
+    for (Request* r : reqs) delete r;
   }
   std::printf("OK\n");
   return 0;

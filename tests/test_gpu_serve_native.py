@@ -1,6 +1,7 @@
 """GPU tests of the library's native serving loop (sw_server_*): every
 request's result equals the oracle's and the result of sorting it alone;
-malformed and oversized requests are refused alone; the HBM budget holds;
+malformed and oversized requests are refused alone; the HBM budget holds
+and binds on the device pool requests wait in;
 two client threads submit at once."""
 import sys
 import threading
@@ -95,7 +96,7 @@ def test_native_server_budget_and_slices(gpu, oracle_mod):
     # a budget that holds about three requests: admission must wait for
     # completions, and the budget is never exceeded
     reqs = [wordgen.single(40_000, 5000, 1.0, 16, seed=20 + r) for r in range(12)]
-    per = max(w.offsets[-1] + 8 * w.n + 4 + 136 for w in reqs)
+    per = max(gpu.NativeServer.request_bytes(w.n, int(w.offsets[-1] - w.offsets[0])) for w in reqs)
     budget = int(3 * per)
     # requests given as slices of a bigger buffer (first offset not 0)
     big = wordgen.concat_docs(reqs)
@@ -139,3 +140,36 @@ def test_native_server_two_client_threads(gpu, oracle_mod):
     for i, w in enumerate(reqs):
         ep, eb = oracle_mod.oracle_def(w.chars, w.offsets)
         assert np.array_equal(got[i][0], ep) and np.array_equal(got[i][1], eb)
+
+
+def test_native_server_budget_binds_on_device_memory(gpu, oracle_mod):
+    # requests wait in blocks of a device pool as large as the budget: a
+    # budget of 1.5 times the largest request, requests of very mixed sizes
+    # (one larger than a staging buffer, so its upload goes in pieces, and
+    # empty ones) submitted at once; the pool fills and fragments, admission
+    # waits for completions, the budget holds and every result is exact
+    rng = np.random.default_rng(44)
+    sizes = [700_000, 0, 1, 90_000] + [int(rng.choice([5, 3000, 60_000, 250_000])) for _ in range(36)]
+    reqs = [wordgen.single(n, 4000, 1.0, 24, seed=300 + i) if n else wordgen.from_words([])
+            for i, n in enumerate(sizes)]
+    fp = [gpu.NativeServer.request_bytes(w.n, int(w.offsets[-1] - w.offsets[0])) for w in reqs]
+    budget = int(1.5 * max(fp))
+    assert sum(fp) > 3 * budget
+    _say("case native server binding budget %d bytes, %d requests" % (budget, len(reqs)))
+    srv = gpu.NativeServer(slots=2, max_batch_words=1 << 20, max_batch_docs=8, budget_bytes=budget,
+                           copy_threads=0)
+    try:
+        too_big = wordgen.single(int(budget / 4), 4000, 1.0, 24, seed=9)   # more bytes than the budget
+        with pytest.raises(gpu.SortWordsError) as e:
+            srv.submit(too_big.chars, too_big.offsets)
+        assert e.value.code == gpu.ERR_WORKSPACE
+        tickets = [srv.submit(w.chars, w.offsets) for w in reqs]
+        out = [srv.wait(t) for t in tickets]
+        st = srv.stats()
+    finally:
+        srv.close()
+    assert st["completed"] == len(reqs) and st["failed"] == 0
+    assert max(fp) <= st["max_bytes_in_use"] <= budget and st["bytes_in_use"] == 0
+    for w, (perm, boff, _) in zip(reqs, out):
+        ep, eb = oracle_mod.oracle_def(w.chars, w.offsets)
+        assert np.array_equal(perm, ep) and np.array_equal(boff, eb)
