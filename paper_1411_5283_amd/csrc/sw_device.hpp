@@ -20,6 +20,7 @@
 #include <stdint.h>
 
 #include "sw_keys.hpp"
+#include "sw_tiles.hpp"
 
 namespace sw {
 
@@ -67,13 +68,6 @@ __host__ __device__ inline uint32_t merge_passes(uint32_t n, uint32_t T, uint32_
   return fan == 4 ? (m + 1) / 2 : m;
 }
 
-// The same for a power-of-two tile T = 2^lt: the smallest m with T*2^m >= n is
-// ceil(log2 n) - lt (at least 0), and ceil(log2 n) is the bit length of n-1.
-__device__ inline uint32_t levels_pow2(uint32_t n, uint32_t lt) {
-  if (n <= 1) return 0;
-  const uint32_t bits = 32u - (uint32_t)__clz(n - 1);
-  return bits > lt ? bits - lt : 0u;
-}
 
 // ---------------------------------------------------------------- run state
 struct RunDesc {

@@ -1068,31 +1068,8 @@ __global__ __launch_bounds__(kPackTile / E) void k_sort_packed(Ws w, int cls) {
 }
 
 // ---------------------------------------------------------------- merge levels
-// Geometry of merge tile j (P outputs) of a segment of n items at a level
-// whose runs hold R items: the pair of runs it reads and its diagonal range.
-struct MergeTile {
-  uint64_t o0, ps;
-  uint32_t la, lb, d0, d1;
-};
-// R and P are powers of two, so the pair start is a mask, not a division.
-__device__ inline MergeTile merge_tile(uint32_t n, uint32_t j, uint64_t R, uint32_t P) {
-  MergeTile m;
-  m.o0 = (uint64_t)j * P;
-  m.ps = m.o0 & ~(2 * R - 1);
-  const uint32_t rem = n - (uint32_t)m.ps;
-  m.la = (uint32_t)min((uint64_t)rem, R);
-  m.lb = rem - m.la < R ? rem - m.la : (uint32_t)R;
-  m.d0 = (uint32_t)(m.o0 - m.ps);
-  m.d1 = min(m.d0 + P, m.la + m.lb);
-  return m;
-}
-
-// Placement of a merge tile: its segment (first position, size), its index in
-// the segment, and the merge-path split at its first output (A items before
-// it).
-struct TileRec {
-  uint32_t base, n, j, split;
-};
+// The tiles' geometry (merge_tile, TileRec, tile_io, the placement
+// bookkeeping) is in sw_tiles.hpp.
 
 // Merge tiles are placed by groups of kPartLanes lanes (kPartLanes probes per
 // round of the merge-path search): fewer lanes touch fewer cache lines in
@@ -1100,32 +1077,6 @@ struct TileRec {
 // rounds.  The rounds' latency hides behind the other classes' kernels, so
 // 8 lanes beat 16 (and 16 beat 32 and 64).
 constexpr int kPartLanes = 8;
-
-// Where a merge tile reads and writes, from its placement and the split at
-// its last output.
-struct TileIO {
-  size_t apos, bpos, ob;
-  int na, cnt;
-  int final;   // nonzero on the segment's last level
-};
-__device__ inline TileIO tile_io(const TileRec& r, uint32_t end_split, uint64_t R, uint32_t P, uint32_t Tc,
-                                 int level) {
-  const MergeTile m = merge_tile(r.n, r.j, R, P);
-  const uint32_t a1 = m.d1 == m.la + m.lb ? m.la : end_split;
-  TileIO io;
-  io.apos = (size_t)r.base + m.ps + r.split;
-  io.bpos = (size_t)r.base + m.ps + m.la + (m.d0 - r.split);
-  io.ob = (size_t)r.base + m.o0;
-  // A items [split, a1) and B items from d0 - split: both inside their runs
-  // whenever the two splits come from the same sorted pair, as they do.  The
-  // clamps only keep a tile's loads inside its runs should they not.
-  const int cnt = (int)(m.d1 - m.d0);
-  const int a_left = (int)m.la - (int)r.split, b_left = (int)m.lb - (int)(m.d0 - r.split);
-  io.na = min(max((int)a1 - (int)r.split, 0), min(cnt, max(a_left, 0)));
-  io.cnt = io.na + min(cnt - io.na, max(b_left, 0));
-  io.final = levels_pow2(r.n, (uint32_t)__ffs(Tc) - 1) == (uint32_t)level + 1;
-  return io;
-}
 
 template <int NL, int NT, int E>
 __device__ inline void load_tile_regs(const KeyBuf& src, const TileIO& io, Key<NL> (&pf)[E]) {
@@ -1165,7 +1116,7 @@ __device__ inline void place_tiles(const Ws& w, int cls, int level, const TileWo
   const uint32_t lane = __lane_id();
   const uint32_t g = threadIdx.x / kPartLanes;
   const uint32_t t = t0 + g;
-  const bool active = t < ntiles && t <= t_end;   // past t_end no split is needed
+  const bool active = place_group_active(t0, g, ntiles, t_end);
   TileSeg sg{0, 0, 0};
   if (tw.direct) {
     sg.base = tw.base;
@@ -1179,23 +1130,18 @@ __device__ inline void place_tiles(const Ws& w, int cls, int level, const TileWo
     const uint32_t* mt = w.mt + cstart + cls;
     const uint32_t gl = lane % kPartLanes;
     const uint64_t gmask = (((1ull << kPartLanes) - 1) << (lane - gl));
-    uint32_t lo = 0, hi = active ? cact : 1u;
-    while (__any(hi - lo > 1)) {
-      const uint32_t step = (hi - lo + kPartLanes - 1) / kPartLanes;
-      const uint32_t k = lo + gl * step;
-      const bool p = hi - lo > 1 && k < hi && mt[k] <= t;
+    KarySearch ks{0, active ? cact : 1u};
+    while (__any(ks.open())) {
+      const uint32_t k = ks.probe(gl, kPartLanes);
+      const bool p = ks.open() && k < ks.hi && mt[k] <= t;
       const uint32_t c = __popcll(__ballot(p) & gmask);
-      if (hi - lo > 1) {
-        const uint32_t nlo = lo + (c - 1) * step;   // mt[lo] <= t, so c >= 1
-        hi = min(nlo + step, hi);
-        lo = nlo;
-      }
+      if (ks.open()) ks.narrow(c, kPartLanes);   // mt[lo] <= t, so c >= 1
     }
     if (active) {
-      const uint32_t s = w.sorted[cstart + lo];
+      const uint32_t s = w.sorted[cstart + ks.lo];
       sg.base = w.seg_base[s];
       sg.n = w.seg_n[s];
-      sg.j = t - mt[lo];
+      sg.j = t - mt[ks.lo];
     }
   }
   MergeTile m{};
@@ -1254,7 +1200,7 @@ __global__ __launch_bounds__(NT) void k_merge(Ws w, int cls, int level, TileWork
       tile.put(cur.cnt + 1, key_sentinel<NL>());
     }
     const bool has_next = k + 1 < nb;
-    const uint32_t kn = (k + 1) % TB;   // the next tile's slot in its batch
+    const uint32_t kn = place_slot(k + 1, TB);   // the next tile's slot in its batch
     if (has_next && kn == 0) place_tiles<NL, NT>(w, cls, level, tw, P, ntiles, tb + k + 1, tb + nb, s_rec, s_split);
     __syncthreads();
     TileIO nxt = cur;
