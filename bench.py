@@ -206,13 +206,15 @@ def cpu_baseline(wl, workload: str, budget_s: float = 16.0) -> dict:
     c1 = wordgen.config(1)
     t0 = time.perf_counter()
     oracle.oracle_bubble(c1.chars, c1.offsets)
-    res["oracle_bubble_35k_words_s"] = time.perf_counter() - t0
+    res["oracle_bubble_35k_words_s"] = t1 = time.perf_counter() - t0
     res["paper_table1_dataset1_s"] = 6.639
+    res["table3_analog_35k_words"] = table3_analog(oracle, c1, t1, [p for p in (2, 4, 8, 16) if p <= cores])
     if workload == "c2":
         t0 = time.perf_counter()
         oracle.oracle_bubble(wl.chars, wl.offsets)
-        res["oracle_bubble_250k_words_s"] = time.perf_counter() - t0
+        res["oracle_bubble_250k_words_s"] = t1 = time.perf_counter() - t0
         res["paper_table1_dataset2_s"] = 188.262
+        res["table3_analog_250k_words"] = table3_analog(oracle, wl, t1, [p for p in (4, 8, 16) if p <= cores])
     res["paper_hardware"] = "Intel Core i7-3610QM 2.3 GHz (paper, Table 1)"
     try:
         with open("/proc/cpuinfo") as f:
@@ -239,6 +241,62 @@ def _counters(kind: str, kernel: str, workload: str, tiles: dict):
     if t.get("tiles") != tiles:
         return None
     return t.get("kernels", {}).get(kernel)
+
+
+def table3_analog(oracle, wl, t1: float, ps) -> dict:
+    """The paper's parallel method on p host threads, timed like the results
+    table of section 5: the words are put into length lists; each list is cut
+    into p chunks of ceil(list size / p) words (chunk = array size /
+    processors); worker i bubble-sorts chunk i of every list (oracle_bubble
+    on the words of its chunks, one thread each), then one thread merges
+    every list's chunks.  The merge is timed as oracle_chunked minus
+    oracle_chunks at a chunk of ceil(longest list / p) (the same bubble-sorted
+    chunks with and without the master's merge).  T_p = the slowest worker +
+    the merge; speedup = T_1 / T_p with T_1 = oracle_bubble on the whole list,
+    efficiency = 100 * speedup / p (report.py)."""
+    from concurrent.futures import ThreadPoolExecutor
+    from paper_1411_5283_amd import report
+    offs = wl.offsets.astype(np.int64)
+    lens = offs[1:] - offs[:-1]
+    order = np.argsort(lens, kind="stable")
+    counts = np.bincount(lens, minlength=33)
+    starts = np.concatenate([[0], np.cumsum(counts)])
+    rows = []
+    for p in ps:
+        parts = []
+        for i in range(p):
+            idx = []
+            for L in range(33):
+                n_l = int(counts[L])
+                if n_l == 0:
+                    continue
+                c = oracle.paper_chunk_size(n_l, p)
+                idx.append(order[starts[L] + min(i * c, n_l):starts[L] + min((i + 1) * c, n_l)])
+            idx = np.concatenate(idx) if idx else np.zeros(0, np.int64)
+            sub_l = lens[idx]
+            sub_o = np.concatenate([[0], np.cumsum(sub_l)]).astype(np.uint32)
+            pos = (offs[idx][:, None] + np.arange(33)[None, :])
+            keep = np.arange(33)[None, :] < sub_l[:, None]
+            sub_c = wl.chars[np.minimum(pos[keep], max(len(wl.chars) - 1, 0))] if keep.any() else \
+                np.zeros(1, np.uint8)
+            parts.append((np.ascontiguousarray(sub_c), sub_o))
+        t0 = time.perf_counter()
+        with ThreadPoolExecutor(max_workers=p) as ex:
+            list(ex.map(lambda a: oracle.oracle_bubble(*a), parts))
+        t_chunks = time.perf_counter() - t0
+        c = oracle.paper_chunk_size(int(counts.max()), p)
+        t0 = time.perf_counter()
+        oracle.oracle_chunked(wl.chars, wl.offsets, c)
+        t_whole = time.perf_counter() - t0
+        t0 = time.perf_counter()
+        oracle.oracle_chunks(wl.chars, wl.offsets, c)
+        t_merge = max(t_whole - (time.perf_counter() - t0), 0.0)
+        tp = t_chunks + t_merge
+        rows.append({"p": p, "chunk_step_s": t_chunks, "merge_s": t_merge, "T_p_s": tp,
+                     "speedup": report.speedup(t1, tp), "efficiency_pct": report.efficiency(t1, tp, p)})
+    return {"T_1_s": t1, "rows": rows,
+            "method": "chunk step on p threads (chunk i of every length list on thread i, chunk = "
+                      "ceil(list size / p)), then the merge on one thread; T_1 = oracle_bubble"}
 
 
 def hbm_traffic(kernel: str, workload: str, tiles: dict):
