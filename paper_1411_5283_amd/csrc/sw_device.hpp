@@ -199,6 +199,22 @@ __device__ inline uint32_t wave_find(const uint32_t* prefix, uint32_t count, uin
   return lo;
 }
 
+// Streaming loads (nontemporal hint) for inputs read once.
+template <int NL>
+__device__ inline Key<NL> gload_nt(const KeyBuf& b, size_t p) {
+  Key<NL> v;
+#pragma unroll
+  for (int q = 0; q < NL; ++q) v.k[q] = __builtin_nontemporal_load(b.k[q] + p);
+  v.idx = __builtin_nontemporal_load(b.idx + p);
+  return v;
+}
+template <>
+__device__ inline Key<0> gload_nt<0>(const KeyBuf& b, size_t p) {
+  Key<0> v;
+  v.k = __builtin_nontemporal_load(b.k[0] + p);
+  return v;
+}
+
 // Streaming stores (nontemporal hint) for outputs that the next kernel reads
 // only after the whole level has been written.
 template <int NL>

@@ -1075,18 +1075,21 @@ __global__ __launch_bounds__(kPackTile / E) void k_sort_packed(Ws w, int cls) {
 // round of the merge-path search): fewer lanes touch fewer cache lines in
 // all (a probe is a cache line until the last rounds), more lanes need fewer
 // rounds.  The rounds' latency hides behind the other classes' kernels, so
-// 8 lanes beat 16 (and 16 beat 32 and 64).
+// 8 lanes beat 16 (and 16 beat 32 and 64); 4 lanes ran the c4 pass in the
+// same time.
 constexpr int kPartLanes = 8;
 
+// A tile's inputs are read once per level: nontemporal loads (measured 2 %
+// faster on the c4 merge levels than plain loads).
 template <int NL, int NT, int E>
 __device__ inline void load_tile_regs(const KeyBuf& src, const TileIO& io, Key<NL> (&pf)[E]) {
 #pragma unroll
   for (int r = 0; r < E; ++r) {
     const int i = threadIdx.x + r * NT;
     if (i < io.na)
-      pf[r] = gload<NL>(src, io.apos + i);
+      pf[r] = gload_nt<NL>(src, io.apos + i);
     else if (i < io.cnt)
-      pf[r] = gload<NL>(src, io.bpos + (i - io.na));
+      pf[r] = gload_nt<NL>(src, io.bpos + (i - io.na));
   }
 }
 
