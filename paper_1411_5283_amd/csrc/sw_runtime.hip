@@ -89,7 +89,7 @@ struct V {
 constexpr int kMaxVariants = 8;
 const Variant* variants(int c, int* count) {
   static const Variant v0[] = {V<0, 256, 16, 256, 16, 0>::get(), V<0, 256, 8, 256, 8, 0>::get(),
-                               V<0, 512, 16, 256, 16, 0>::get(), V<0, 512, 16, 256, 8, 0>::get(),
+                               V<0, 512, 16, 256, 16, 0>::get(), V<0, 512, 16, 512, 4, 0>::get(),
                                V<0, 512, 16, 256, 16, 1>::get(), V<0, 512, 16, 256, 8, 1>::get(),
                                V<0, 1024, 16, 256, 16, 0>::get()};
   static const Variant v1[] = {V<1, 256, 16, 256, 16, 0>::get(), V<1, 256, 8, 256, 8, 0>::get(),
