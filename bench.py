@@ -698,11 +698,14 @@ def main():
     wl = wordgen.config(cfg_no)
     log("generated %d words in %.1f s" % (wl.n, time.perf_counter() - t0))
     tuned = None
-    if "chunk" in wl.meta:
-        sw.set_config(chunk=[wl.meta["chunk"]] * sw.NUM_CLASSES, variant=[0] * sw.NUM_CLASSES)
-    elif not args.untuned:
+    if not args.untuned:
         from paper_1411_5283_amd import tune
         tuned = tune.apply(args.workload)
+    if "chunk" in wl.meta:
+        # the workload fixes the chunk size (section 5's chunk of the 250k-word
+        # list); tiles and launch order as tuned with that chunk, if they were
+        sw.set_config(chunk=[wl.meta["chunk"]] * sw.NUM_CLASSES,
+                      **({} if tuned else {"variant": [0] * sw.NUM_CLASSES}))
     if args.serial:
         sw.set_config(flags=sw.get_config()["flags"] | sw.FLAG_SERIAL_CLASSES)
     if args.merge:

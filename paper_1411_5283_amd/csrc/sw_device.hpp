@@ -249,6 +249,35 @@ __device__ inline Key<0> key_shfl<0>(const Key<0>& v, int src) {
   return r;
 }
 
+// Neighbour exchange across the whole wave with DPP wavefront shifts (GFX9
+// data-parallel primitives, a VALU move, no LDS round trip): kDppNext gives
+// lane i the value of lane i+1, kDppPrev that of lane i-1; the lane with no
+// such neighbour (63, resp. 0) keeps its own value.
+constexpr int kDppNext = 0x130;   // wavefront shift left by one lane
+constexpr int kDppPrev = 0x138;   // wavefront shift right by one lane
+template <int CTRL>
+__device__ inline uint32_t dpp32(uint32_t v) {
+  return (uint32_t)__builtin_amdgcn_update_dpp((int)v, (int)v, CTRL, 0xF, 0xF, false);
+}
+template <int CTRL>
+__device__ inline uint64_t dpp64(uint64_t v) {
+  return ((uint64_t)dpp32<CTRL>((uint32_t)(v >> 32)) << 32) | dpp32<CTRL>((uint32_t)v);
+}
+template <int CTRL, int NL>
+__device__ inline Key<NL> key_dpp(const Key<NL>& v) {
+  Key<NL> r;
+#pragma unroll
+  for (int q = 0; q < NL; ++q) r.k[q] = dpp64<CTRL>(v.k[q]);
+  r.idx = dpp32<CTRL>(v.idx);
+  return r;
+}
+template <int CTRL>
+__device__ inline Key<0> key_dpp(const Key<0>& v) {
+  Key<0> r;
+  r.k = dpp64<CTRL>(v.k);
+  return r;
+}
+
 // ---------------------------------------------------------------- LDS tile
 // Structure-of-arrays tile of CAP keys.  One pad slot every 2^PADSH items
 // keeps a thread's consecutive items (blocked layout) off its neighbours'
@@ -354,6 +383,15 @@ __device__ inline TKey<NL> e_shfl(const TKey<NL>& v, int src) {
   TKey<NL> r;
   r.k = key_shfl<NL>(v.k, src);
   r.tag = __shfl(v.tag, src);
+  return r;
+}
+template <int CTRL, int NL>
+__device__ inline Key<NL> e_dpp(const Key<NL>& v) { return key_dpp<CTRL>(v); }
+template <int CTRL, int NL>
+__device__ inline TKey<NL> e_dpp(const TKey<NL>& v) {
+  TKey<NL> r;
+  r.k = key_dpp<CTRL>(v.k);
+  r.tag = dpp32<CTRL>(v.tag);
   return r;
 }
 // Compare-exchange: afterwards a <= b.  Returns whether they were exchanged.

@@ -658,8 +658,8 @@ __device__ inline void oddeven_chunks(K (&e)[E], uint32_t C) {
     for (int j = 1; j + 1 < E; j += 2)
       if (cross || ((uint32_t)(j + 1) & (C - 1)) != 0) sw |= e_cmp_xchg(e[j], e[j + 1]);
     if (cross) {
-      K nx = e_shfl(e[0], (int)min(lane + 1, 63u));
-      K pv = e_shfl(e[E - 1], (int)(lane ? lane - 1 : 0u));
+      K nx = e_dpp<kDppNext>(e[0]);
+      K pv = e_dpp<kDppPrev>(e[E - 1]);
       if (waves) {
         if (lane == 0) s_first[wave] = e[0];
         if (lane == 63) s_last[wave] = e[E - 1];

@@ -245,6 +245,8 @@ def main():
     ap.add_argument("--plan-rounds", type=int, default=3, help="interleaved timing rounds per variant")
     ap.add_argument("--order-only", action="store_true",
                     help="with --plan-only: keep the cached variants, time only the launch-order flags")
+    ap.add_argument("--chunk", type=int, default=None,
+                    help="a workload that fixes the chunk size (the 250k-word list: 1024): tune the rest")
     args = ap.parse_args()
     from . import wordgen
     cfg = int(args.workload.lstrip("c"))
@@ -256,7 +258,7 @@ def main():
         if not res:
             raise SystemExit("no cached configuration for %s" % args.workload)
     else:
-        res = tune(wl, args.workload, reps=args.reps, log=say)
+        res = tune(wl, args.workload, reps=args.reps, chunks=(args.chunk,) if args.chunk else CHUNKS, log=say)
     res.update(refine_on_plan(wl, res["config"], rounds=args.plan_rounds, log=say,
                               variants=not (args.plan_only and args.order_only)))
     save(res, args.out)
