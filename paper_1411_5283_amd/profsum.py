@@ -39,19 +39,19 @@ SQ_COUNTERS = ("SQ_INSTS_VALU SQ_ACTIVE_INST_VALU SQ_INSTS_LDS SQ_ACTIVE_INST_LD
 def traffic_commands(w: str) -> list:
     b = BENCH.format(w=w)
     return [
-        "rocprofv3 --pmc FETCH_SIZE --output-format csv -d gpurun_out/pmc_fetch_%s -o f -- %s --no-text" % (w, b),
-        "rocprofv3 --pmc WRITE_SIZE --output-format csv -d gpurun_out/pmc_write_%s -o w -- %s --no-text" % (w, b),
-        "rocprofv3 --pmc FETCH_SIZE --output-format csv -d gpurun_out/pmc_fetch_t_%s -o f -- %s" % (w, b),
-        "rocprofv3 --pmc WRITE_SIZE --output-format csv -d gpurun_out/pmc_write_t_%s -o w -- %s" % (w, b),
-        "rocprofv3 --pmc FETCH_SIZE --output-format csv -d gpurun_out/pmc_copyf -o cf -- python3 bench.py "
+        "rocprofv3 --pmc FETCH_SIZE --output-format csv -d gpurun_out/ctr/f_%s -o f -- %s --no-text" % (w, b),
+        "rocprofv3 --pmc WRITE_SIZE --output-format csv -d gpurun_out/ctr/w_%s -o w -- %s --no-text" % (w, b),
+        "rocprofv3 --pmc FETCH_SIZE --output-format csv -d gpurun_out/ctr/ft_%s -o f -- %s" % (w, b),
+        "rocprofv3 --pmc WRITE_SIZE --output-format csv -d gpurun_out/ctr/wt_%s -o w -- %s" % (w, b),
+        "rocprofv3 --pmc FETCH_SIZE --output-format csv -d gpurun_out/ctr/cf -o cf -- python3 bench.py "
         "--copy-calibration",
-        "rocprofv3 --pmc WRITE_SIZE --output-format csv -d gpurun_out/pmc_copyw -o cw -- python3 bench.py "
+        "rocprofv3 --pmc WRITE_SIZE --output-format csv -d gpurun_out/ctr/cw -o cw -- python3 bench.py "
         "--copy-calibration",
     ]
 
 
 def valu_commands(w: str) -> list:
-    return ["rocprofv3 --pmc %s --output-format csv -d gpurun_out/pmc_sq%d_%s -o s -- %s --no-text" % (
+    return ["rocprofv3 --pmc %s --output-format csv -d gpurun_out/ctr/sq%d_%s -o s -- %s --no-text" % (
         c, i, w, BENCH.format(w=w)) for i, c in enumerate(SQ_COUNTERS)]
 
 
