@@ -7,9 +7,10 @@
   the oracle's definitional rank of a word (perm[rank(i)] == i).
 * 4096 documents (about 31M words): every document against the oracle.
 * The sorted text written in the sort's own pass (sw_plan_run_text): for the
-  documents, byte for byte against the oracle's text; for 64M words, equal
-  to the permutation-based writer's output and, at sampled words, to the
-  word the oracle ranks there.
+  documents, byte for byte against the oracle's text; for 64M words, byte for
+  byte against the oracle's writer applied to the order the invariants prove,
+  equal to the permutation-based writer's output, and at sampled words equal
+  to the word the oracle ranks there.
 """
 import numpy as np
 import pytest
@@ -79,6 +80,10 @@ def test_config4_full_invariants_and_sampled_ranks(gpu, oracle_mod):
     assert np.array_equal(np.diff(boff.astype(np.int64)), counts.astype(np.int64))
     check_invariants(wl.chars, wl.offsets, perm, boff)
     assert np.array_equal(text, ref), "text from the keys differs from the text from the permutation"
+    # the invariants make perm the one sorted order; the oracle's writer lays
+    # its words out on the host: the whole text, byte for byte
+    etext = oracle_mod.oracle_materialize(wl.chars, wl.offsets, perm, 10)
+    assert text.tobytes() == etext, "sorted text differs from the oracle's text of the verified order"
     # text position of sorted position k: the lengths before its bucket, then its rank in the bucket
     bo = boff.astype(np.int64)
     bucket_start = np.concatenate([[0], np.cumsum(np.diff(bo) * (np.arange(33) + 1))])
