@@ -2,8 +2,12 @@
 
     python -m paper_1411_5283_amd.profsum stats <kernel_stats.csv> "<command>" <out.txt>
     python -m paper_1411_5283_amd.profsum traffic <workload> <fetch.csv> <write.csv> <copy_fetch.csv> \
-        <copy_write.csv> <bench.json> <out.json> [<text_fetch.csv> <text_write.csv>]
-    python -m paper_1411_5283_amd.profsum valu <workload> <pmc_a.csv>,<pmc_b.csv> <bench.json> <out.json>
+        <copy_write.csv> <bench.json> <out.json> [<text_fetch.csv> <text_write.csv>] [--outdir <dir>]
+    python -m paper_1411_5283_amd.profsum valu <workload> <pmc_a.csv>,<pmc_b.csv> <bench.json> <out.json> \
+        [--outdir <dir>]
+
+--outdir names the folder the counter runs wrote to (it appears in the
+commands each summary records).
 
 ``traffic`` averages FETCH_SIZE and WRITE_SIZE (KiB per dispatch) per kernel
 family and scales them by what the same counters read for a plain 1 GiB
@@ -36,23 +40,22 @@ SQ_COUNTERS = ("SQ_INSTS_VALU SQ_ACTIVE_INST_VALU SQ_INSTS_LDS SQ_ACTIVE_INST_LD
                "GRBM_GUI_ACTIVE")
 
 
-def traffic_commands(w: str) -> list:
+def traffic_commands(w: str, d: str) -> list:
+    """The runs a traffic summary is made from; d: the folder they wrote to."""
     b = BENCH.format(w=w)
     return [
-        "rocprofv3 --pmc FETCH_SIZE --output-format csv -d gpurun_out/ctr/f_%s -o f -- %s --no-text" % (w, b),
-        "rocprofv3 --pmc WRITE_SIZE --output-format csv -d gpurun_out/ctr/w_%s -o w -- %s --no-text" % (w, b),
-        "rocprofv3 --pmc FETCH_SIZE --output-format csv -d gpurun_out/ctr/ft_%s -o f -- %s" % (w, b),
-        "rocprofv3 --pmc WRITE_SIZE --output-format csv -d gpurun_out/ctr/wt_%s -o w -- %s" % (w, b),
-        "rocprofv3 --pmc FETCH_SIZE --output-format csv -d gpurun_out/ctr/cf -o cf -- python3 bench.py "
-        "--copy-calibration",
-        "rocprofv3 --pmc WRITE_SIZE --output-format csv -d gpurun_out/ctr/cw -o cw -- python3 bench.py "
-        "--copy-calibration",
+        "rocprofv3 --pmc FETCH_SIZE --output-format csv -d %s/f_%s -o f -- %s --no-text" % (d, w, b),
+        "rocprofv3 --pmc WRITE_SIZE --output-format csv -d %s/w_%s -o w -- %s --no-text" % (d, w, b),
+        "rocprofv3 --pmc FETCH_SIZE --output-format csv -d %s/ft_%s -o f -- %s" % (d, w, b),
+        "rocprofv3 --pmc WRITE_SIZE --output-format csv -d %s/wt_%s -o w -- %s" % (d, w, b),
+        "rocprofv3 --pmc FETCH_SIZE --output-format csv -d %s/cf -o cf -- python3 bench.py --copy-calibration" % d,
+        "rocprofv3 --pmc WRITE_SIZE --output-format csv -d %s/cw -o cw -- python3 bench.py --copy-calibration" % d,
     ]
 
 
-def valu_commands(w: str) -> list:
-    return ["rocprofv3 --pmc %s --output-format csv -d gpurun_out/ctr/sq%d_%s -o s -- %s --no-text" % (
-        c, i, w, BENCH.format(w=w)) for i, c in enumerate(SQ_COUNTERS)]
+def valu_commands(w: str, d: str) -> list:
+    return ["rocprofv3 --pmc %s --output-format csv -d %s/sq%d_%s -o s -- %s --no-text" % (
+        c, d, i, w, BENCH.format(w=w)) for i, c in enumerate(SQ_COUNTERS)]
 
 
 def stats(src: str, cmd: str, out: str) -> None:
@@ -99,7 +102,7 @@ def _tiles(b: dict) -> dict:
 
 
 def traffic(workload: str, fetch: str, write: str, cfetch: str, cwrite: str, bench_json: str, out: str,
-            text_fetch: str | None = None, text_write: str | None = None) -> None:
+            text_fetch: str | None = None, text_write: str | None = None, outdir: str = "out") -> None:
     f = _per_dispatch(fetch, "FETCH_SIZE")
     w = _per_dispatch(write, "WRITE_SIZE")
     if text_fetch and text_write:
@@ -126,12 +129,12 @@ def traffic(workload: str, fetch: str, write: str, cfetch: str, cwrite: str, ben
            "tiles": _tiles(b), "fetch_scale": fs, "write_scale": wsc,
            "calibration": "plain device copy of 1 GiB (__amd_rocclr_copyBuffer): FETCH_SIZE %.0f KiB, "
                           "WRITE_SIZE %.0f KiB per dispatch" % (cf, cw),
-           "commands": traffic_commands(workload), "kernels": kern}
+           "commands": traffic_commands(workload, outdir), "kernels": kern}
     with open(out, "w") as fh:
         json.dump(res, fh, indent=1, sort_keys=True)
 
 
-def valu(workload: str, pmcs: str, bench_json: str, out: str) -> None:
+def valu(workload: str, pmcs: str, bench_json: str, out: str, outdir: str = "out") -> None:
     agg = collections.defaultdict(lambda: collections.defaultdict(list))
     for pmc in pmcs.split(","):
         for r in csv.DictReader(open(pmc)):
@@ -148,7 +151,7 @@ def valu(workload: str, pmcs: str, bench_json: str, out: str) -> None:
             row[name + "_per_dispatch"] = sum(vals) / len(vals)
         kern[fam] = row
     res = {"source_hash": b["kernel_source"], "workload": b["config"]["workload"] + " (bench.py --serial)",
-           "tiles": _tiles(b), "commands": valu_commands(workload), "kernels": kern,
+           "tiles": _tiles(b), "commands": valu_commands(workload, outdir), "kernels": kern,
            "note": "SQ_INSTS_VALU counts wave instructions (each up to 64 lanes); SQ_ACTIVE_INST_VALU and "
                    "SQ_ACTIVE_INST_LDS are quad-cycles summed over waves; every value is summed over the "
                    "shader engines and the 8 XCDs (GRBM_GUI_ACTIVE / 8 = the dispatch's clocks)"}
@@ -157,11 +160,17 @@ def valu(workload: str, pmcs: str, bench_json: str, out: str) -> None:
 
 
 if __name__ == "__main__":
-    if sys.argv[1] == "stats":
-        stats(*sys.argv[2:5])
-    elif sys.argv[1] == "traffic":
-        traffic(*sys.argv[2:11])
-    elif sys.argv[1] == "valu":
-        valu(*sys.argv[2:6])
+    argv = list(sys.argv[1:])
+    outdir = "out"
+    if "--outdir" in argv:   # the folder the counter runs wrote to, for the recorded commands
+        k = argv.index("--outdir")
+        outdir = argv[k + 1]
+        del argv[k:k + 2]
+    if argv[0] == "stats":
+        stats(*argv[1:4])
+    elif argv[0] == "traffic":
+        traffic(*argv[1:10], outdir=outdir)
+    elif argv[0] == "valu":
+        valu(*argv[1:5], outdir=outdir)
     else:
         raise SystemExit(__doc__)
