@@ -181,9 +181,11 @@ def cpu_baseline(wl, workload: str, budget_s: float = 16.0) -> dict:
     """The oracle as it stands on the host's cores, on bounded prefix samples
     of the same workload: oracle_def (qsort by length, bytes, index) with
     each length list on a thread of its own over every core the process may
-    use (the value), the same on one thread, and the paper's own method
+    use (the value), the same on one thread, the paper's own method
     (oracle_bubble, one thread) on the stand-in for its first dataset and, for
-    the 250k-word workload, on that whole list (Table 1's second dataset)."""
+    the 250k-word workload, on that whole list (Table 1's second dataset), the
+    results-table analog, and for a batch of documents both oracles with a
+    document a thread."""
     import oracle
     oracle.build(force=False)
     cores = len(os.sched_getaffinity(0))
@@ -208,13 +210,16 @@ def cpu_baseline(wl, workload: str, budget_s: float = 16.0) -> dict:
     oracle.oracle_bubble(c1.chars, c1.offsets)
     res["oracle_bubble_35k_words_s"] = t1 = time.perf_counter() - t0
     res["paper_table1_dataset1_s"] = 6.639
-    res["table3_analog_35k_words"] = table3_analog(oracle, c1, t1, [p for p in (2, 4, 8, 16) if p <= cores])
+    res["table3_analog_35k_words"] = table3_analog(oracle, c1, t1, [p for p in (2, 4, 6, 8, 10, 16) if p <= cores])
+    if wl.doc_offsets is not None:
+        res["doc_parallel"] = doc_parallel_baseline(oracle, wl, cores, budget_s)
     if workload == "c2":
         t0 = time.perf_counter()
         oracle.oracle_bubble(wl.chars, wl.offsets)
         res["oracle_bubble_250k_words_s"] = t1 = time.perf_counter() - t0
         res["paper_table1_dataset2_s"] = 188.262
-        res["table3_analog_250k_words"] = table3_analog(oracle, wl, t1, [p for p in (4, 8, 16) if p <= cores])
+        res["table3_analog_250k_words"] = table3_analog(oracle, wl, t1,
+                                                        [p for p in (4, 6, 8, 10, 16) if p <= cores])
     res["paper_hardware"] = "Intel Core i7-3610QM 2.3 GHz (paper, Table 1)"
     try:
         with open("/proc/cpuinfo") as f:
@@ -241,6 +246,30 @@ def _counters(kind: str, kernel: str, workload: str, tiles: dict):
     if t.get("tiles") != tiles:
         return None
     return t.get("kernels", {}).get(kernel)
+
+
+def doc_parallel_baseline(oracle, wl, cores: int, budget_s: float) -> dict:
+    """Documents on host threads (oracle_batch: each document sorted alone, one
+    a thread): oracle_def and the paper's method oracle_bubble, each on the
+    first documents of the batch that take about budget_s / 4."""
+    docs = wl.doc_offsets.astype(np.int64)
+    out = {}
+    for fn in ("oracle_def", "oracle_bubble"):
+        nd = 16
+        while True:
+            nd = min(nd, wl.n_docs)
+            d = docs[:nd + 1]
+            offs = np.ascontiguousarray(wl.offsets[:int(d[-1]) + 1])
+            t0 = time.perf_counter()
+            oracle.oracle_batch(wl.chars, offs, d.astype(np.uint32), fn=fn, threads=cores)
+            dt = time.perf_counter() - t0
+            if dt * 2.2 > budget_s / 4 or nd >= wl.n_docs:
+                break
+            nd *= 2
+        out[fn] = {"value": int(d[-1]) / dt / 1e6, "unit": "Mwords/s", "cores": cores,
+                   "sample": "%s on the first %d documents (%d words), a document a thread, %.2f s" %
+                             (fn, nd, int(d[-1]), dt)}
+    return out
 
 
 def table3_analog(oracle, wl, t1: float, ps) -> dict:
@@ -865,7 +894,18 @@ def main():
         if chunk_top else None,
         "whole_pass_algorithmic_GB": total_bytes / 1e9,
         "whole_pass_GBs_at_plan_time": total_bytes / (ms_step / 1e3) / 1e9,
+        "whole_pass_frac": total_bytes / (ms_step / 1e3) / 1e9 / HBM_PEAK_GBS,
         "eager_kernel_sum_ms": tsum})
+    # the compulsory floor of any method (read the offsets and the characters,
+    # write the permutation) and the counters' bytes over the whole pass
+    floor = 8 * n + int(wl.offsets[-1]) - int(wl.offsets[0])
+    roof["floor_GB"] = floor / 1e9
+    roof["floor_frac_at_plan_time"] = floor / (ms_step / 1e3) / 1e9 / HBM_PEAK_GBS
+    per_launch = {k: hbm_traffic(k, args.workload, tile_cfg) for k in kern}
+    if kern and all(v is not None for k, v in per_launch.items() if kern[k]["ms_per_step"] > 0.02):
+        counted = sum(v * kern[k]["launches_per_step"] for k, v in per_launch.items() if v is not None)
+        roof["whole_pass_counter_GB"] = counted / 1e9
+        roof["whole_pass_counter_GBs_at_plan_time"] = counted / (ms_step / 1e3) / 1e9
 
     text = None if args.no_text else text_bench(args, sw, wordgen, torch, wl, chars, offs, docs, perm, boff,
                                                    perm_h, boff_h, stream, plan, ms_step, tile_cfg)
