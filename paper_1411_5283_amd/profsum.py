@@ -71,16 +71,17 @@ def stats(src: str, cmd: str, out: str) -> None:
 
 
 def _family(kernel: str) -> str | None:
-    """Kernel name -> the bench's family name (the template's first argument,
-    the key lanes, is the class: lanes 0-4 for classes 0-4)."""
-    m = re.match(r"(?:void )?sw::k_(\w+?)<(\d+)", kernel)
+    """Kernel name -> the bench's family name: the per-class kernels (chunk
+    sorts and merges, whose first template argument is the key lanes, 0-4 for
+    classes 0-4) get the class as a suffix, every other kernel its own name."""
+    m = re.match(r"(?:void )?sw::k_(\w+?)(?:<(\d+)|[<(]|$)", kernel)
     if not m:
-        m2 = re.match(r"(?:void )?sw::k_(\w+?)(?:[<(]|$)", kernel)
-        return m2.group(1) if m2 else None
-    name, nl = m.group(1), int(m.group(2))
-    if name in ("scatter_pack", "hist", "tok_scan", "materialize", "pack_full", "keys_text"):
-        return name
-    return "%s_c%d" % (name, nl) if 0 <= nl <= 4 else None
+        return None
+    name = m.group(1)
+    if name in ("sort_tiles", "sort_packed", "merge", "merge4"):
+        nl = int(m.group(2)) if m.group(2) else -1
+        return "%s_c%d" % ("merge" if name == "merge4" else name, nl) if 0 <= nl <= 4 else None
+    return name
 
 
 def _per_dispatch(path: str, counter: str) -> dict:
