@@ -473,3 +473,45 @@ def sort_wordlist(wl, device="cuda"):
     sort_words_batch(chars, offsets, docs, nd, perm, boff, ws)
     sort_words_status(ws)
     return to_u32(perm)[:n], to_u32(boff)[:nd * NUM_OFFSETS].reshape(nd, NUM_OFFSETS)
+
+
+# ------------------------------------------------------------------ conveniences
+def sort_strings(words, device="cuda"):
+    """Sort a list of words (str or bytes, at most MAX_LEN bytes each) on the
+    GPU by (length, bytes unsigned, position); returns (the sorted list,
+    the permutation as uint32)."""
+    from . import wordgen
+    words = list(words)
+    perm, _ = sort_wordlist(wordgen.from_words(words), device)
+    return [words[i] for i in perm], perm
+
+
+def sort_text(text, lower: bool = False, sep: int = 10, device="cuda") -> bytes:
+    """Raw text in, sorted words out, every step on the GPU: the words are the
+    runs between ASCII whitespace with their letters kept (sort_words_tokenize,
+    lower case on request), sorted by (length, bytes, position) (sort_words),
+    and written each followed by byte `sep`, or back to back when sep < 0
+    (sort_words_materialize)."""
+    import torch
+    raw = np.frombuffer(bytes(text), np.uint8)
+    nb = int(raw.size)
+    t = torch.from_numpy(raw.copy() if nb else np.zeros(1, np.uint8)).to(device)
+    max_words = (nb + 1) // 2
+    chars = torch.empty(max(nb, 1), dtype=torch.uint8, device=device)
+    offs = torch.empty(max_words + 1, dtype=torch.int32, device=device)
+    nw = torch.zeros(1, dtype=torch.int32, device=device)
+    ws = torch.empty(tokenize_workspace_size(nb), dtype=torch.uint8, device=device)
+    tokenize(t, nb, TOK_LOWER if lower else 0, chars, offs, max_words, nw, ws)
+    sort_words_status(ws)
+    n = int(nw.cpu()[0])
+    perm = torch.empty(max(n, 1), dtype=torch.int32, device=device)
+    boff = torch.empty(NUM_OFFSETS, dtype=torch.int32, device=device)
+    sort_words(chars, offs, n, perm, boff)
+    size = int(offs[n].item()) + (n if sep >= 0 else 0) if n else 0
+    out = torch.empty(max(size, 1), dtype=torch.uint8, device=device)
+    st = torch.zeros(1, dtype=torch.int32, device=device)
+    materialize(chars, offs, None, 1, n, perm, boff, sep, out, st)
+    torch.cuda.synchronize()
+    if int(st.cpu()[0]):
+        raise SortWordsError(ERR_INVALID_ARG, "sort_text: the text writer's checks failed")
+    return out[:size].cpu().numpy().tobytes()

@@ -197,3 +197,27 @@ def test_text_sort_text_chain(gpu, oracle_mod):
     ec, eo = oracle_mod.oracle_tokenize(text, oracle_mod.TOK_LOWER)
     eperm, _ = oracle_mod.oracle_def(ec, eo)
     assert out == oracle_mod.oracle_materialize(ec, eo, eperm, 10)
+
+
+@pytest.mark.parametrize("lower,sep", [(True, 10), (False, 32), (False, -1)])
+def test_sort_text_convenience(gpu, oracle_mod, lower, sep):
+    # the one-call form (text in, sorted words out) against the oracle's chain
+    wl = wordgen.single(120_000, 8_000, 1.0, 24, seed=52)
+    text = wordgen.render_text(wl, 3).tobytes()
+    _say("case sort_text lower=%s sep=%d bytes=%d" % (lower, sep, len(text)))
+    got = gpu.sort_text(text, lower=lower, sep=sep)
+    ec, eo = oracle_mod.oracle_tokenize(text, oracle_mod.TOK_LOWER if lower else 0)
+    eperm, _ = oracle_mod.oracle_def(ec, eo)
+    assert got == oracle_mod.oracle_materialize(ec, eo, eperm, sep)
+    assert gpu.sort_text(b"", sep=sep) == b"" and gpu.sort_text(b" \n\t. ,", sep=sep) == b""
+
+
+def test_sort_strings_convenience(gpu, oracle_mod):
+    rng = np.random.default_rng(8)
+    words = [bytes(rng.integers(97, 100, int(L), dtype=np.uint8)) for L in rng.integers(0, 33, 5000)]
+    words += ["été".encode(), b"\xff\x00", b""]
+    got, perm = gpu.sort_strings(words)
+    assert got == [w for _, w in sorted(enumerate(words), key=lambda t: (len(t[1]), t[1], t[0]))]
+    wl = wordgen.from_words(words)
+    eperm, _ = oracle_mod.oracle_def(wl.chars, wl.offsets)
+    assert np.array_equal(perm, eperm)
