@@ -228,27 +228,6 @@ __device__ inline void gstore_nt<0>(const KeyBuf& b, size_t p, const Key<0>& v) 
   __builtin_nontemporal_store(v.k, b.k[0] + p);
 }
 
-__device__ inline uint64_t shfl64(uint64_t v, int src) {
-  const uint32_t lo = __shfl((uint32_t)v, src);
-  const uint32_t hi = __shfl((uint32_t)(v >> 32), src);
-  return ((uint64_t)hi << 32) | lo;
-}
-
-template <int NL>
-__device__ inline Key<NL> key_shfl(const Key<NL>& v, int src) {
-  Key<NL> r;
-#pragma unroll
-  for (int q = 0; q < NL; ++q) r.k[q] = shfl64(v.k[q], src);
-  r.idx = __shfl(v.idx, src);
-  return r;
-}
-template <>
-__device__ inline Key<0> key_shfl<0>(const Key<0>& v, int src) {
-  Key<0> r;
-  r.k = shfl64(v.k, src);
-  return r;
-}
-
 // Neighbour exchange across the whole wave with DPP wavefront shifts (GFX9
 // data-parallel primitives, a VALU move, no LDS round trip): kDppNext gives
 // lane i the value of lane i+1, kDppPrev that of lane i-1; the lane with no
@@ -375,15 +354,6 @@ __device__ inline K e_sentinel() {
   K v;
   e_set_sentinel(v);
   return v;
-}
-template <int NL>
-__device__ inline Key<NL> e_shfl(const Key<NL>& v, int src) { return key_shfl<NL>(v, src); }
-template <int NL>
-__device__ inline TKey<NL> e_shfl(const TKey<NL>& v, int src) {
-  TKey<NL> r;
-  r.k = key_shfl<NL>(v.k, src);
-  r.tag = __shfl(v.tag, src);
-  return r;
 }
 template <int CTRL, int NL>
 __device__ inline Key<NL> e_dpp(const Key<NL>& v) { return key_dpp<CTRL>(v); }
