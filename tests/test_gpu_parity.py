@@ -55,7 +55,7 @@ def _same(got, exp, what):
     assert np.array_equal(gb, eb), "%s: bucket offsets differ" % what
 
 
-@pytest.mark.parametrize("variant", [0, 1, 2, 3, 4, 5, 6])
+@pytest.mark.parametrize("variant", [0, 1, 2, 3, 4, 5, 6, 7])
 def test_long_segments_every_variant(gpu, oracle_mod, default_config, variant):
     # 1.5M words over few lengths: many merge levels and many tiles per workgroup
     wl = wordgen.single(1_500_000, 40_000, 1.1, 20, seed=5)
@@ -99,15 +99,18 @@ def test_config1_bit_exact(gpu, oracle_mod):
     _same(gpu.sort_wordlist(wl), _expect(oracle_mod, wl), "config1")
 
 
-@pytest.mark.parametrize("variant", [0, 1])
+@pytest.mark.parametrize("variant", [0, 1, 7])
 def test_config2_chunk1024_bit_exact(gpu, oracle_mod, default_config, variant):
     # 1024-word odd-even chunks in every class, as configured: variant 0 holds
     # 8 items per thread in classes 2-4 (a chunk spans two waves), variant 1
     # 8 in classes 0-2 and 16 in classes 3-4 (a chunk spans one wave); the
-    # short segments' tiles always hold 8 per thread
+    # short segments' tiles hold 8 per thread; the last variant of every
+    # class holds 2 per thread, also in the short segments' tiles (a chunk
+    # spans eight waves)
     wl = wordgen.config(2)
     _say("case config2 n=%d chunk=1024 variant=%d" % (wl.n, variant))
-    cfg = gpu.set_config(chunk=[1024] * gpu.NUM_CLASSES, variant=[variant] * gpu.NUM_CLASSES)
+    var = [min(variant, gpu.num_variants(c) - 1) for c in range(gpu.NUM_CLASSES)]
+    cfg = gpu.set_config(chunk=[1024] * gpu.NUM_CLASSES, variant=var)
     assert cfg["chunk"] == [1024] * gpu.NUM_CLASSES
     _same(gpu.sort_wordlist(wl), _expect(oracle_mod, wl, bubble=False), "config2")
 
@@ -122,7 +125,7 @@ CHUNK_WL = None
 
 
 @pytest.mark.parametrize("chunk", [2, 4, 8, 16, 32, 64, 128, 256, 512, 1024])
-@pytest.mark.parametrize("variant", [0, 1, 2, 3, 4, 5, 6])
+@pytest.mark.parametrize("variant", [0, 1, 2, 3, 4, 5, 6, 7])
 def test_chunk_step_bit_exact(gpu, oracle_mod, default_config, chunk, variant):
     # the chunk step alone (odd-even transposition on each chunk of C, no
     # merge) against the oracle's bubble sort of each chunk: every chunk size
@@ -145,7 +148,7 @@ def test_chunk_step_bit_exact(gpu, oracle_mod, default_config, chunk, variant):
 
 
 @pytest.mark.parametrize("chunk", [2, 4, 8, 16, 32, 64, 128, 256, 512, 1024])
-@pytest.mark.parametrize("variant", [0, 1, 2, 3, 4, 5, 6])
+@pytest.mark.parametrize("variant", [0, 1, 2, 3, 4, 5, 6, 7])
 def test_chunk_and_variant_sweep(gpu, oracle_mod, default_config, chunk, variant):
     # several tiles, merge levels and a ragged tail in every class
     wl = wordgen.single(41_000, 3000, 1.0, 32, seed=77)

@@ -171,7 +171,7 @@ def test_plan_alternates_sort_and_text(gpu, oracle_mod):
         plan.close()
 
 
-@pytest.mark.parametrize("variant", [0, 1, 2, 3, 4, 5, 6])
+@pytest.mark.parametrize("variant", [0, 1, 2, 3, 4, 5, 6, 7])
 def test_every_variant(gpu, oracle_mod, default_config, variant):
     wl = wordgen.single(400_000, 30_000, 1.1, 24, seed=7)
     _say("case text variant=%d n=%d" % (variant, wl.n))
