@@ -173,3 +173,44 @@ def test_native_server_budget_binds_on_device_memory(gpu, oracle_mod):
     for w, (perm, boff, _) in zip(reqs, out):
         ep, eb = oracle_mod.oracle_def(w.chars, w.offsets)
         assert np.array_equal(perm, ep) and np.array_equal(boff, eb)
+
+
+def test_native_server_stress_tight_budget(gpu, oracle_mod):
+    # many requests of mixed sizes through a pool of three times the largest
+    # request, three slots and four upload threads (uploads grouped where
+    # blocks lie back to back), from two client threads at once: the pool
+    # fills, fragments and drains many times; every result is exact
+    rng = np.random.default_rng(77)
+    sizes = np.clip(np.round(rng.lognormal(np.log(2000), 1.2, 300)), 0, 150_000).astype(int)
+    reqs = [wordgen.single(int(n), 3000, 1.0, 24, seed=900 + i) if n else wordgen.from_words([])
+            for i, n in enumerate(sizes)]
+    fp = [gpu.NativeServer.request_bytes(w.n, int(w.offsets[-1] - w.offsets[0])) for w in reqs]
+    budget = 3 * max(fp)
+    _say("case native server stress: %d requests, %d words, budget %d" % (len(reqs), int(sizes.sum()), budget))
+    srv = gpu.NativeServer(slots=3, max_batch_words=1 << 19, max_batch_docs=16, budget_bytes=budget,
+                           min_batch_words=20_000, max_wait_us=100, copy_threads=4)
+    got = {}
+    lock = threading.Lock()
+
+    def client(part):
+        mine = []
+        for i in range(part, len(reqs), 2):
+            mine.append((i, srv.submit(reqs[i].chars, reqs[i].offsets)))
+        for i, t in mine:
+            r = srv.wait(t)
+            with lock:
+                got[i] = r
+    try:
+        th = [threading.Thread(target=client, args=(p,)) for p in (0, 1)]
+        for t in th:
+            t.start()
+        for t in th:
+            t.join()
+        st = srv.stats()
+    finally:
+        srv.close()
+    assert len(got) == len(reqs) and st["failed"] == 0
+    assert st["max_bytes_in_use"] <= budget and st["bytes_in_use"] == 0
+    for i, w in enumerate(reqs):
+        ep, eb = oracle_mod.oracle_def(w.chars, w.offsets)
+        assert np.array_equal(got[i][0], ep) and np.array_equal(got[i][1], eb), i
