@@ -138,17 +138,24 @@ __device__ inline uint32_t lanes_below(uint64_t m) {
   return __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
 }
 
-// Lanes whose BITS-bit key equals this lane's (valid lanes only).
+// Lanes whose BITS-bit key equals this lane's (valid lanes only).  Per bit b,
+// `mine` is all ones where the lane's bit is set and the ballot holds the
+// lanes with it set, so (ballot ^ mine) are the lanes that differ from this
+// one on bit b; v_bitop3 (0xF6: a | (b ^ c)) gathers them over the bits, two
+// instructions a bit for the 64-lane mask.  The empty asm keeps `mine` the
+// value the ballot compares, rather than a second shift of the key.
 template <int BITS>
 __device__ inline uint64_t match_mask(uint32_t key, bool valid) {
-  uint64_t m = __ballot(valid);
+  uint32_t dlo = 0, dhi = 0;
 #pragma unroll
   for (int b = 0; b < BITS; ++b) {
-    const bool bit = (key >> b) & 1u;
-    const uint64_t bb = __ballot(bit);
-    m &= bit ? bb : ~bb;
+    uint32_t mine = (uint32_t)__builtin_amdgcn_sbfe((int)key, b, 1);
+    asm volatile("" : "+v"(mine));
+    const uint64_t bb = __ballot(mine != 0u);
+    dlo = __builtin_amdgcn_bitop3_b32(dlo, (uint32_t)bb, mine, 0xF6);
+    dhi = __builtin_amdgcn_bitop3_b32(dhi, (uint32_t)(bb >> 32), mine, 0xF6);
   }
-  return m;
+  return __ballot(valid) & ~(((uint64_t)dhi << 32) | dlo);
 }
 
 __device__ inline uint32_t wave_incl_scan(uint32_t v) {

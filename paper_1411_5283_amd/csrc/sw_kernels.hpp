@@ -402,51 +402,100 @@ __device__ inline void load_be_lanes(const uint8_t* p, uint32_t L, uint64_t (&la
   }
 }
 
-// Big-endian lanes of an L-byte word whose first byte is byte `pos` of a
-// dword array held in LDS (pos counts from the array's first byte).  The
-// 2*NQ+1 dwords from the word's first one are read whatever L is: the array
-// must extend that far (bytes past the word are masked off below).
-template <int NQ>
-__device__ inline void lds_be_lanes(const uint32_t* dw, uint32_t pos, uint32_t L, uint64_t (&lane)[NQ]) {
-  const uint32_t s = pos & 3;
-  const uint32_t* base = dw + (pos >> 2);
-  uint32_t wv[2 * NQ + 1];
+// Big-endian bytes of a word staged in LDS as dwords d[0], d[1], ... with its
+// first byte at byte s (0..3) of d[0].  Bytes 4t..4t+3 of the word are bytes
+// s..s+3 of the eight-byte pair (d[t+1]:d[t]); v_perm picks them most
+// significant first with the selector s*0x01010101 + 0x00010203, and a
+// selector byte of 0x0C yields a zero byte.
+__device__ inline uint32_t be_sel(uint32_t s) { return s * 0x01010101u + 0x00010203u; }
+__device__ inline uint32_t be_word(const uint32_t* d, int t, uint32_t sel) {
+  return __builtin_amdgcn_perm(d[t + 1], d[t], sel);
+}
+
+// Lanes of a class-C word of length L (C >= 1: 8(C-1) < L <= 8C) from LDS:
+// lanes 0..C-2 are full; the last keeps its first L - 8(C-1) bytes.
+template <int C>
+__device__ inline void lds_class_lanes(const uint32_t* d, uint32_t s, uint32_t L, uint64_t (&lane)[C]) {
+  const uint32_t sel = be_sel(s);
 #pragma unroll
-  for (int j = 0; j < 2 * NQ + 1; ++j) wv[j] = __builtin_bswap32(base[j]);
-#pragma unroll
-  for (int q = 0; q < NQ; ++q) {
-    const uint64_t hi = ((uint64_t)wv[2 * q] << 32) | wv[2 * q + 1];
-    uint64_t v = s ? (hi << (8 * s)) | (uint64_t)(wv[2 * q + 2] >> (32 - 8 * s)) : hi;
-    const int rem = (int)L - 8 * q;
-    v = rem >= 8 ? v : (rem <= 0 ? 0ull : (v & (~0ull << (64 - 8 * rem))));
-    lane[q] = v;
-  }
+  for (int q = 0; q < C; ++q) lane[q] = ((uint64_t)be_word(d, 2 * q, sel) << 32) | be_word(d, 2 * q + 1, sel);
+  lane[C - 1] &= ~0ull << (64 * C - 8 * L);
 }
 
 // ---------------------------------------------------------------- k_scatter_pack
 // Stable scatter of every word into its (document, length) segment, packed
 // into key lanes.  The block's offsets, and its characters when they fit
-// kScatterChars bytes, are first staged in LDS with coalesced loads.
+// kScatterChars bytes, are first staged in LDS with 16-byte loads from
+// 16-byte aligned addresses (the few words before the block's first offset or
+// character in its 16 bytes come along and are skipped).
 // Pass 1: the rank of a word among the words of the same length before it in
 // the block (per wave with ballots, a running count per wave carries ranks
 // across iterations) gives its slot in the block's length-sorted order; LDS
-// records which word holds each slot.  Pass 2 walks the slots in order, so
-// consecutive lanes write consecutive positions of one segment (coalesced
-// stores), reading the words from LDS.
+// records which word holds each slot.  Pass 2 walks the slots in order, class
+// by class (a class's slots are contiguous), so consecutive lanes write
+// consecutive positions of one segment (coalesced stores) and build the lanes
+// of one class, reading the words from LDS.
 constexpr uint32_t kScatterChars = 24576;   // three workgroups per CU; a block of 4096 words averages about 18 KB
+
+template <int NW>
+struct ScatterLds {
+  uint4 off4[(kWordsPerBlock + 1 + 3 + 3) / 4];   // the block's offsets after up to 3 dwords of lead
+  uint4 chr4[kScatterChars / 16 + 2];              // + the dwords a word's lanes may read past the end
+  uint16_t slot[kWordsPerBlock];
+  uint32_t run[NW][kNB];
+  uint32_t bstart[kNB + 1];
+  uint32_t dst[kNB];     // segment position of slot 0 of each length
+  uint32_t doc;
+};
+
+// Pass 2 for the slots [ps, pe) of class C.
+template <int NT, int C>
+__device__ inline void scatter_class(const Ws& w, const ScatterLds<NT / 64>& S, const uint32_t* s_off, uint32_t ps,
+                                     uint32_t pe, bool staged, uint32_t cpos, uint32_t ibase,
+                                     const uint8_t* chars) {
+  const uint32_t* s_chr = (const uint32_t*)S.chr4;
+  for (uint32_t p = ps + threadIdx.x; p < pe; p += NT) {
+    const uint32_t i = S.slot[p];
+    const uint32_t a = s_off[i];
+    const uint32_t L = min(s_off[i + 1] - a, (uint32_t)kMaxLen);
+    const uint32_t dest = S.dst[L] + p;
+    const uint32_t idx = ibase + i;
+    if constexpr (C == 0) {
+      uint64_t hi;
+      if (staged) {
+        const uint32_t pos = a + cpos;
+        // the word's L (0..4) bytes: selector bytes past them become 0x0C
+        const uint32_t keep = (uint32_t)(0xFFFFFFFF00000000ull >> (8 * L));
+        const uint32_t sel = (be_sel(pos & 3) & keep) | (0x0C0C0C0Cu & ~keep);
+        hi = (uint64_t)be_word(s_chr + (pos >> 2), 0, sel) << 32;
+      } else {
+        uint64_t ln[1];
+        load_be_lanes<1>(chars + a, L, ln);
+        hi = ln[0] & 0xFFFFFFFF00000000ull;
+      }
+      w.a.k[0][dest] = hi | idx;
+    } else {
+      uint64_t ln[C];
+      if (staged) {
+        const uint32_t pos = a + cpos;
+        lds_class_lanes<C>(s_chr + (pos >> 2), pos & 3, L, ln);
+      } else {
+        load_be_lanes<C>(chars + a, L, ln);
+      }
+#pragma unroll
+      for (int q = 0; q < C; ++q) w.a.k[q][dest] = ln[q];
+      w.a.idx[dest] = idx;
+    }
+  }
+}
+
 template <int NT>
 __global__ __launch_bounds__(NT) void k_scatter_pack(Ws w) {
   constexpr int NW = NT / 64;
   constexpr uint32_t PER_WAVE = kWordsPerBlock / NW;
   constexpr int IT = PER_WAVE / 64;
-  __shared__ uint32_t s_off[kWordsPerBlock + 1];
-  __shared__ uint32_t s_chr[kScatterChars / 4 + 9];   // + the dwords lds_be_lanes<4> may read past the end
-  __shared__ uint32_t s_run[NW][kNB];
-  __shared__ uint32_t s_bstart[kNB + 1];
-  __shared__ uint32_t s_gbase[kNB];
-  __shared__ uint16_t s_slot[kWordsPerBlock];
-  __shared__ uint32_t s_doc;
   static_assert(kWordsPerBlock <= 65536, "slot index is 16-bit");
+  __shared__ ScatterLds<NW> S;
   Header* h = w.h;
   if (h->abort) return;
   const uint32_t nblk = h->n_blocks, D = h->n_docs;
@@ -455,41 +504,45 @@ __global__ __launch_bounds__(NT) void k_scatter_pack(Ws w) {
   const uint32_t rs = w.Bmax + 1;
   const uint32_t lane = __lane_id(), wave = threadIdx.x >> 6;
   for (uint32_t b = blockIdx.x; b < nblk; b += gridDim.x) {
-    for (uint32_t k = threadIdx.x; k < (uint32_t)(NW * kNB); k += NT) (&s_run[0][0])[k] = 0;
-    const BlockRange r = block_range<NT>(w, b, D, &s_doc);   // has a barrier
+    for (uint32_t k = threadIdx.x; k < (uint32_t)(NW * kNB); k += NT) (&S.run[0][0])[k] = 0;
+    const BlockRange r = block_range<NT>(w, b, D, &S.doc);   // has a barrier
     const uint32_t nw = r.we - r.ws;
-    // the block's characters: whole aligned dwords covering [off[ws], off[we]),
-    // loaded together with the block's offsets
+    // offsets [ws, we] and characters [off[ws], off[we]) as whole aligned
+    // 16-byte pieces; olead dwords and lead bytes precede the block's own
+    const uintptr_t oaddr = (uintptr_t)(off + r.ws);
+    const uint4* osrc = (const uint4*)(oaddr & ~(uintptr_t)15);
+    const uint32_t olead = (uint32_t)(oaddr & 15) >> 2;
+    const uint32_t n_o4 = (olead + nw + 1 + 3) >> 2;
     const uint32_t c0 = off[r.ws], c1 = off[r.we];
-    const uintptr_t abase = ((uintptr_t)(chars + c0)) & ~(uintptr_t)3;
-    const uint32_t lead = (uint32_t)((uintptr_t)(chars + c0) - abase);
-    const uint32_t span_dw = c1 > c0 ? (lead + (c1 - c0) + 3) >> 2 : 0u;
-    const bool staged = span_dw <= kScatterChars / 4;
+    const uintptr_t caddr = (uintptr_t)(chars + c0);
+    const uint4* csrc = (const uint4*)(caddr & ~(uintptr_t)15);
+    const uint32_t lead = (uint32_t)(caddr & 15);
+    const uint32_t n_c4 = c1 > c0 ? (lead + (c1 - c0) + 15) >> 4 : 0u;
+    const bool staged = n_c4 <= kScatterChars / 16;
     {
-      // offsets then characters, UNR loads in flight per thread per step
-      constexpr int UNR = 8;
-      const uint32_t* src = (const uint32_t*)abase;
-      const uint32_t ntot = nw + 1 + (staged ? span_dw : 0u);
+      constexpr int UNR = 4;
+      const uint32_t ntot = n_o4 + (staged ? n_c4 : 0u);
       for (uint32_t k0 = 0; k0 < ntot; k0 += NT * UNR) {
-        uint32_t v[UNR];
+        uint4 v[UNR];
 #pragma unroll
         for (int u = 0; u < UNR; ++u) {
           const uint32_t k = k0 + threadIdx.x + u * NT;
-          v[u] = k < ntot ? (k <= nw ? off[r.ws + k] : src[k - nw - 1]) : 0u;
+          v[u] = k < ntot ? (k < n_o4 ? osrc[k] : csrc[k - n_o4]) : make_uint4(0, 0, 0, 0);
         }
 #pragma unroll
         for (int u = 0; u < UNR; ++u) {
           const uint32_t k = k0 + threadIdx.x + u * NT;
-          if (k <= nw)
-            s_off[k] = v[u];
+          if (k < n_o4)
+            S.off4[k] = v[u];
           else if (k < ntot)
-            s_chr[k - nw - 1] = v[u];
+            S.chr4[k - n_o4] = v[u];
         }
       }
     }
+    const uint32_t* s_off = (const uint32_t*)S.off4 + olead;
     if (threadIdx.x < (uint32_t)kNB) {
       const uint32_t L = threadIdx.x;
-      s_gbase[L] = w.seg_base[r.doc * kNB + L] + w.cnt[L * rs + b] - w.cnt[L * rs + w.doc_blk[r.doc]];
+      S.dst[L] = w.seg_base[r.doc * kNB + L] + w.cnt[L * rs + b] - w.cnt[L * rs + w.doc_blk[r.doc]];
     }
     __syncthreads();
     const uint32_t wofs = wave * PER_WAVE;
@@ -502,8 +555,8 @@ __global__ __launch_bounds__(NT) void k_scatter_pack(Ws w) {
       if (valid) L = min(s_off[i + 1] - s_off[i], (uint32_t)kMaxLen);
       const uint64_t mm = match_mask<6>(L, valid);
       const uint32_t rk = lanes_below(mm);
-      const uint32_t old = valid ? s_run[wave][L] : 0u;
-      if (valid && rk == 0) s_run[wave][L] = old + (uint32_t)__popcll(mm);
+      const uint32_t old = valid ? S.run[wave][L] : 0u;
+      if (valid && rk == 0) S.run[wave][L] = old + (uint32_t)__popcll(mm);
       pk[it] = L | ((old + rk) << 6);
     }
     __syncthreads();
@@ -512,13 +565,14 @@ __global__ __launch_bounds__(NT) void k_scatter_pack(Ws w) {
       uint32_t tot = 0;
       if (lane < (uint32_t)kNB) {
         for (int v = 0; v < NW; ++v) {
-          const uint32_t t = s_run[v][lane];
-          s_run[v][lane] = tot;
+          const uint32_t t = S.run[v][lane];
+          S.run[v][lane] = tot;
           tot += t;
         }
       }
       const uint32_t ex = wave_incl_scan(tot) - tot;
-      if (lane <= (uint32_t)kNB) s_bstart[lane] = ex;
+      if (lane <= (uint32_t)kNB) S.bstart[lane] = ex;
+      if (lane < (uint32_t)kNB) S.dst[lane] -= ex;
     }
     __syncthreads();
 #pragma unroll
@@ -526,63 +580,20 @@ __global__ __launch_bounds__(NT) void k_scatter_pack(Ws w) {
       const uint32_t i = wofs + it * 64 + lane;
       if (i < nw) {
         const uint32_t L = pk[it] & 63u;
-        s_slot[s_bstart[L] + s_run[wave][L] + (pk[it] >> 6)] = (uint16_t)i;
+        S.slot[S.bstart[L] + S.run[wave][L] + (pk[it] >> 6)] = (uint16_t)i;
       }
     }
     __syncthreads();
-    const uint32_t doc0 = w.doc_off[r.doc];
-#pragma unroll 4
-    for (uint32_t p = threadIdx.x; p < nw; p += NT) {
-      const uint32_t i = s_slot[p];
-      const uint32_t a = s_off[i];
-      const uint32_t L = min(s_off[i + 1] - a, (uint32_t)kMaxLen);
-      const uint32_t dest = s_gbase[L] + (p - s_bstart[L]);
-      const uint32_t idx = r.ws + i - doc0;
-      const uint32_t pos = lead + (a - c0);
-      // only the lanes of the word's class are built (a wave's slots mostly
-      // share one length, so the branch rarely diverges)
-      const int c = class_of_len(L);
-      if (c <= 1) {
-        uint64_t ln[1];
-        if (staged)
-          lds_be_lanes<1>(s_chr, pos, L, ln);
-        else
-          load_be_lanes<1>(chars + a, L, ln);
-        if (c == 0) {
-          w.a.k[0][dest] = (ln[0] & 0xFFFFFFFF00000000ull) | idx;
-        } else {
-          w.a.k[0][dest] = ln[0];
-          w.a.idx[dest] = idx;
-        }
-      } else if (c == 2) {
-        uint64_t ln[2];
-        if (staged)
-          lds_be_lanes<2>(s_chr, pos, L, ln);
-        else
-          load_be_lanes<2>(chars + a, L, ln);
-        w.a.k[0][dest] = ln[0];
-        w.a.k[1][dest] = ln[1];
-        w.a.idx[dest] = idx;
-      } else if (c == 3) {
-        uint64_t ln[3];
-        if (staged)
-          lds_be_lanes<3>(s_chr, pos, L, ln);
-        else
-          load_be_lanes<3>(chars + a, L, ln);
-#pragma unroll
-        for (int q = 0; q < 3; ++q) w.a.k[q][dest] = ln[q];
-        w.a.idx[dest] = idx;
-      } else {
-        uint64_t ln[4];
-        if (staged)
-          lds_be_lanes<4>(s_chr, pos, L, ln);
-        else
-          load_be_lanes<4>(chars + a, L, ln);
-#pragma unroll
-        for (int q = 0; q < 4; ++q) w.a.k[q][dest] = ln[q];
-        w.a.idx[dest] = idx;
-      }
-    }
+    // class c holds lengths (8(c-1), 8c] (class 0: 0..4); its slots start at
+    // the bucket start of its shortest length
+    const uint32_t cpos = lead - c0;                 // LDS byte of character position a is a + cpos
+    const uint32_t ibase = r.ws - w.doc_off[r.doc];  // document-relative index of the block's first word
+    const uint32_t q1 = S.bstart[5], q2 = S.bstart[9], q3 = S.bstart[17], q4 = S.bstart[25];
+    scatter_class<NT, 0>(w, S, s_off, 0, q1, staged, cpos, ibase, chars);
+    scatter_class<NT, 1>(w, S, s_off, q1, q2, staged, cpos, ibase, chars);
+    scatter_class<NT, 2>(w, S, s_off, q2, q3, staged, cpos, ibase, chars);
+    scatter_class<NT, 3>(w, S, s_off, q3, q4, staged, cpos, ibase, chars);
+    scatter_class<NT, 4>(w, S, s_off, q4, nw, staged, cpos, ibase, chars);
     __syncthreads();
   }
 }
