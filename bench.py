@@ -37,7 +37,7 @@ WORKLOADS = {
               "20k-word Zipf(1.0) vocabulary, lengths 1-20, 8 GiB HBM budget"),
 }
 CSRC = [os.path.join(ROOT, "paper_1411_5283_amd", "csrc", f)
-        for f in ("sw_device.hpp", "sw_keys.hpp", "sw_tiles.hpp", "sw_split.hpp", "sw_merge4.hpp", "sw_kernels.hpp", "sw_text.hpp",
+        for f in ("sw_device.hpp", "sw_keys.hpp", "sw_tiles.hpp", "sw_split.hpp", "sw_window.hpp", "sw_kernels.hpp", "sw_text.hpp",
                   "sw_bytes.hpp", "sw_gather.hpp", "sw_runtime.hip")]
 # VALU issue rate of the whole GPU: 256 CUs x 4 SIMDs x 16 lanes per clock
 # (a wave64 instruction occupies its SIMD for 4 clocks) x 2.4 GHz, in tera

@@ -9,7 +9,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 LIB = os.path.join(HERE, "libsortwords.so")
 SOURCES = [os.path.join(HERE, "csrc", "sw_runtime.hip")]
-DEPS = SOURCES + [os.path.join(HERE, "csrc", f) for f in ("sw_device.hpp", "sw_keys.hpp", "sw_tiles.hpp", "sw_split.hpp", "sw_merge4.hpp", "sw_kernels.hpp", "sw_text.hpp",
+DEPS = SOURCES + [os.path.join(HERE, "csrc", f) for f in ("sw_device.hpp", "sw_keys.hpp", "sw_tiles.hpp", "sw_split.hpp", "sw_window.hpp", "sw_kernels.hpp", "sw_text.hpp",
                                                       "sw_bytes.hpp", "sw_sched.hpp", "sw_gather.hpp")] + \
     [os.path.join(ROOT, "include", "sort_words.h")]
 

@@ -20,15 +20,16 @@
 //   k_merge        one two-way merge-path level over HBM (each workgroup
 //                  places its own tiles); the last level of a segment writes
 //                  the output permutation
-//   k_merge4       one four-way merge level over HBM (two doublings of the
-//                  run length per pass, streamed through LDS)
+//   k_merge4w      one four-way merge pass over HBM (two doublings of the
+//                  run length per pass, in steps of bounded windows)
 //   k_pack_full    the same words as one sequence of full keys (baseline
 //                  without length lists)
 // Every kernel after k_begin reads the run from the workspace, so the same
 // sequence runs eagerly or as one captured HIP graph.
 #pragma once
 #include "sw_device.hpp"
-#include "sw_merge4.hpp"
+#include "sw_split.hpp"
+#include "sw_window.hpp"
 
 namespace sw {
 
@@ -1249,16 +1250,22 @@ __global__ __launch_bounds__(NT) void k_merge(Ws w, int cls, int level, TileWork
   }
 }
 
-// ---------------------------------------------------------------- k_merge4
+// ---------------------------------------------------------------- four-way split
 // Co-ranks sp[] of rank d in the four runs (start st[r], len[r]) by the
 // bracket search of sw_split.hpp: each round every slot of every run is
 // sampled by one thread, every interior sample judged by one thread, and the
 // brackets narrowed with LDS atomics.  False if the search did not close
 // (never expected; the caller then stops its work and flags the run).
-template <class M, int NL, int NT>
-__device__ __attribute__((always_inline)) inline bool split4(typename M::Lds& L, const KeyBuf& src, const uint64_t (&st)[4],
-                              const uint32_t (&len)[4], uint32_t d, uint32_t (&sp)[4]) {
-  SplitScratch<Key<NL>>& S = L.u.sp;
+template <int NL>
+struct KeyLess {
+  __host__ __device__ __attribute__((always_inline)) bool operator()(const Key<NL>& a, const Key<NL>& b) const {
+    return key_less<NL>(a, b);
+  }
+};
+template <int NL, int NT>
+__device__ __attribute__((always_inline)) inline bool split4(SplitScratch<Key<NL>>& S, const KeyBuf& src,
+                                                             const uint64_t (&st)[4], const uint32_t (&len)[4],
+                                                             uint32_t d, uint32_t (&sp)[4]) {
   if (threadIdx.x == 0) {
     split_init(S, len, d);
 #pragma unroll
@@ -1278,7 +1285,7 @@ __device__ __attribute__((always_inline)) inline bool split4(typename M::Lds& L,
     for (uint32_t slot = threadIdx.x; slot < (uint32_t)(kSplitRuns * kSplitSlots); slot += NT) {
       const int i = (int)(slot / kSplitSlots), j = (int)(slot % kSplitSlots);
       if (j == 0 || j == kSplitSlots - 1 || S.pos[i][j] == kSplitNone) continue;
-      const int v = split_decide(S, i, j, typename M::Less());
+      const int v = split_decide(S, i, j, KeyLess<NL>());
       if (v < 0) atomicMax(&S.newlo[i], S.pos[i][j] + 1);
       if (v > 0) atomicMin(&S.newhi[i], S.pos[i][j]);
     }
@@ -1292,40 +1299,130 @@ __device__ __attribute__((always_inline)) inline bool split4(typename M::Lds& L,
     sp[i] = S.lo[i];
     sum += sp[i];
   }
-  __syncthreads();   // the scratch shares LDS with the X and Y rings
+  __syncthreads();   // the scratch may share LDS with the caller's buffers
   return sum == d;
 }
 
-// A thread's n outputs at position o: indices to the output permutation on
-// a segment's last level (and the keys too for the sorted text), keys to the
-// next buffer otherwise.
-template <int NL, int E>
-__device__ __attribute__((always_inline)) inline void merge4_store(const Key<NL> (&out)[E], uint32_t n, size_t o,
-                                                                   bool final, bool keep, uint32_t* out_perm,
-                                                                   const KeyBuf& dst) {
+// ---------------------------------------------------------------- k_merge4w
+// One four-way merge pass of class cls by bounded windows (sw_window.hpp):
+// groups of four runs of R = T * 4^level items merged into runs of 4R.  The
+// pass's output (the active segments of the class one after another, or the
+// one segment given directly) is cut into one contiguous range per
+// workgroup; a range entered inside a group starts from the co-ranks of the
+// split search.  A step of W = NT*E/4 items a window:
+//   A  the windows loaded during the last step go into LDS (run r from
+//      slot r*W);
+//   B  waves 0-3 find the bound and count their run's items below it (two
+//      rounds of 64 probes);
+//   C  the next step's windows are requested into registers;
+//   D  threads [0, NT/2) merge X = A and B, the others Y = C and D, E items
+//      each from a merge-path diagonal (reads bounded by the counts), into
+//      LDS, each followed by a sentinel;
+//   E  every thread merges E outputs of X and Y from its diagonal into LDS,
+//      and the step's outputs are stored in order (indices to the output
+//      permutation on a segment's last pass).
+// Four barriers a step; LDS holds the windows, X and Y, and the outputs:
+// 12W items.
+template <int NL, int NT, int E>
+struct W4 {
+  static_assert(NT >= 256 && NT % 64 == 0, "waves 0-3 search the four windows");
+  static constexpr int W = NT * E / 4;
+  static_assert(W % 64 == 0, "a wave's window load stays inside one run");
+  static_assert(W <= (int)(kWinLanes * kWinLanes), "two rounds of 64 probes cover a window");
+  static constexpr int WS = W;           // window slots of a run
+  static constexpr int XS = 2 * W + 1;   // X, Y: up to 2W items and a sentinel
+  static constexpr int XOFF = kWinRuns * WS, YOFF = XOFF + XS;
+  // E slots a serial merge may step past both sentinels (outputs never
+  // stored), then the outputs staged for in-order stores
+  static constexpr int SOFF = YOFF + XS + E;
+  static constexpr int CAP = SOFF + 4 * W;
+  struct Lds {
+    LdsTile<NL, CAP> t;
+    SplitScratch<Key<NL>> sp;
+    uint32_t c[kWinRuns];
+    uint32_t seg;
+  };
+};
+
+// E items merged from positions pa and pb of two runs in LDS that each end
+// with a sentinel (ties go to the first run; keys are distinct anyway).
+template <int E, class Tile>
+__device__ __attribute__((always_inline)) inline void lds_serial_merge(const Tile& t, int pa, int pb,
+                                                                       typename Tile::value_type (&out)[E]) {
+  using K = typename Tile::value_type;
+  K ha = t.get(pa), hb = t.get(pb);
 #pragma unroll
   for (int j = 0; j < E; ++j) {
-    if ((uint32_t)j < n) {
-      if (final) __builtin_nontemporal_store(key_index<NL>(out[j]), out_perm + o + j);
-      if (!final || keep) gstore_nt<NL>(dst, o + j, out[j]);
-    }
+    const bool takeB = e_less(hb, ha);
+    out[j] = e_select(takeB, hb, ha);
+    pa += takeB ? 0 : 1;
+    pb += takeB ? 1 : 0;
+    const K nv = t.get(takeB ? pb : pa);
+    ha = e_select(takeB, ha, nv);
+    hb = e_select(takeB, nv, hb);
   }
 }
 
-// One four-way merge level of class cls (runs of R = T * 4^level items
-// merged four at a time into runs of 4R).  The level's output -- the active
-// segments of the class one after another, or the one segment given directly
-// -- is cut into one contiguous range per workgroup; the range is walked
-// group by group: a group entered at rank d > 0 starts from the co-ranks of
-// the split search, one entered at its start from zero, and each streams
-// through LDS (sw_merge4.hpp).  A segment's last level writes the indices to
-// the output permutation (and, for the sorted text, its keys as well).
-template <int NL, int NT, int E, int PS, int RC>
-__global__ __launch_bounds__(NT) void k_merge4(Ws w, int cls, int level, TileWork tw) {
-  using M = M4<NL, NT, E, PS, RC>;
+// The same from positions pa < ea and pb < eb (either may start at its end):
+// a run read to its end reads as the sentinel.
+template <int E, class Tile>
+__device__ __attribute__((always_inline)) inline void lds_bounded_merge(const Tile& t, int pa, int ea, int pb, int eb,
+                                                                        typename Tile::value_type (&out)[E]) {
+  using K = typename Tile::value_type;
+  K ha, hb;
+  e_set_sentinel(ha);
+  e_set_sentinel(hb);
+  if (pa < ea) ha = t.get(pa);
+  if (pb < eb) hb = t.get(pb);
+#pragma unroll
+  for (int j = 0; j < E; ++j) {
+    const bool takeB = e_less(hb, ha);
+    out[j] = e_select(takeB, hb, ha);
+    pa += takeB ? 0 : 1;
+    pb += takeB ? 1 : 0;
+    const int np = takeB ? pb : pa;
+    K nv;
+    e_set_sentinel(nv);
+    if (np < (takeB ? eb : ea)) nv = t.get(np);
+    ha = e_select(takeB, ha, nv);
+    hb = e_select(takeB, nv, hb);
+  }
+}
+
+// Element r of four wave-uniform values without indexing by a runtime r
+// (which would put the array in scratch memory).
+template <class T>
+__device__ __attribute__((always_inline)) inline T pick4(const T (&a)[4], int r) {
+  return r == 0 ? a[0] : (r == 1 ? a[1] : (r == 2 ? a[2] : a[3]));
+}
+
+// Run of thread t's u-th window item, (t + u*NT) / W: a constant of the
+// unrolled loop when W is a multiple of NT, else the same across a wave.
+template <int NT, int W>
+__device__ __attribute__((always_inline)) inline int w4_run(int u) {
+  return W % NT == 0 ? (u * NT) / W : win_load_run(u, (int)threadIdx.x, NT, W);
+}
+
+// The next windows into registers: thread t's u-th item is item
+// (t + u*NT) % W of run (t + u*NT) / W's window.
+template <int NL, int NT, int E, int W>
+__device__ __attribute__((always_inline)) inline void w4_load(const KeyBuf& src, const uint64_t (&st)[4],
+                                                              const uint32_t (&len)[4], const uint32_t (&cons)[4],
+                                                              Key<NL> (&pf)[E]) {
+#pragma unroll
+  for (int u = 0; u < E; ++u) {
+    const int r = w4_run<NT, W>(u);
+    const uint32_t i = pick4(cons, r) + (uint32_t)win_load_pos(u, (int)threadIdx.x, NT, W);
+    if (i < pick4(len, r)) pf[u] = gload_nt<NL>(src, (size_t)(pick4(st, r) + i));
+  }
+}
+
+template <int NL, int NT, int E>
+__global__ __launch_bounds__(NT) void k_merge4w(Ws w, int cls, int level, TileWork tw) {
+  using G = W4<NL, NT, E>;
   using K = Key<NL>;
-  constexpr int FE = M::FE;
-  __shared__ typename M::Lds L;
+  constexpr int W = G::W, WS = G::WS;
+  __shared__ typename G::Lds L;
   Header* h = w.h;
   if (h->abort) return;
   const uint32_t Tc = w.T[cls];
@@ -1348,7 +1445,7 @@ __global__ __launch_bounds__(NT) void k_merge4(Ws w, int cls, int level, TileWor
   const KeyBuf dst = (level & 1) ? w.a : w.b;
   uint32_t* out_perm = h->d.out_perm;
   const bool keep = h->d.out_text != nullptr;
-  const uint32_t tid = threadIdx.x;
+  const uint32_t tid = threadIdx.x, lane = __lane_id(), wave = tid >> 6;
   uint32_t k = 0;
   if (!tw.direct) {
     if (tid < 64) {
@@ -1356,7 +1453,7 @@ __global__ __launch_bounds__(NT) void k_merge4(Ws w, int cls, int level, TileWor
       if (tid == 0) L.seg = kk;
     }
     __syncthreads();
-    k = L.seg;
+    k = __builtin_amdgcn_readfirstlane(L.seg);
   }
   for (uint64_t pos = r0; pos < r1;) {
     uint32_t base, n;
@@ -1379,77 +1476,119 @@ __global__ __launch_bounds__(NT) void k_merge4(Ws w, int cls, int level, TileWor
     uint64_t st[4];
 #pragma unroll
     for (int r = 0; r < 4; ++r) st[r] = (uint64_t)base + g.start + g.run_off[r];
-    uint32_t sp[4] = {0, 0, 0, 0};
-    if (g.d > 0 && !split4<M, NL, NT>(L, src, st, g.len, g.d, sp)) {
+    uint32_t cons[4] = {0, 0, 0, 0};
+    if (g.d > 0 && !split4<NL, NT>(L.sp, src, st, g.len, g.d, cons)) {
       if (tid == 0) {
         atomicOr(&h->status, ST_INVALID);
         atomicOr(&h->abort, 1u);
       }
       return;
     }
-    typename M::State s;
-    M::begin(s, st, g.len, sp);
-    // rings filled, X and Y topped up, rings refilled: all synchronously
-    M::fill_amounts(s, 4u * RC);
-    for (uint32_t q = tid; q < M::refill_total(s); q += NT) {
-      K v;
-      if (M::refill_load(s, src, q, v)) M::refill_put(L, s, q, v);
-    }
-    if (tid == 0) L.end[0][0] = L.end[0][1] = L.end[1][0] = L.end[1][1] = 0;
-    M::refill_done(s);
-    M::seal_runs(L, s, tid);
-    __syncthreads();
-    uint32_t wx = M::want(s, 0), wy = M::want(s, 1);
-    for (uint32_t wi = tid; wi < M::topup_items(s); wi += NT) M::topup(L, s, wi);
-    M::seal_xy(L, s, tid, wx, wy);
-    __syncthreads();
-    M::topup_done(s, L, wx, wy);
-    M::fill_amounts(s, 4u * RC);
-    for (uint32_t q = tid; q < M::refill_total(s); q += NT) {
-      K v;
-      if (M::refill_load(s, src, q, v)) M::refill_put(L, s, q, v);
-    }
-    M::refill_done(s);
-    M::seal_runs(L, s, tid);
-    __syncthreads();
-    K pf[FE];
-    // a step's outputs are stored in the next step, after that step has
-    // waited for its ring loads: the wait then never waits for them
-    K out[E];
-    uint32_t nout = 0;
-    size_t o = 0;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) cons[r] = __builtin_amdgcn_readfirstlane(cons[r]);
+    K pf[E];
+    w4_load<NL, NT, E, W>(src, st, g.len, cons, pf);
     for (uint32_t done = 0; done < count;) {
-      // A: last step's loads into the rings; last step's outputs stored;
-      // loads for the ring slots now free
+      // A: the windows into LDS
 #pragma unroll
-      for (int u = 0; u < FE; ++u) {
-        const uint32_t q = tid + (uint32_t)u * NT;
-        if (q < M::refill_total(s)) M::refill_put(L, s, q, pf[u]);
+      for (int u = 0; u < E; ++u) {
+        const int r = w4_run<NT, W>(u);
+        const int i = win_load_pos(u, (int)tid, NT, W);
+        if ((uint32_t)i < win_len(pick4(g.len, r), pick4(cons, r), W)) L.t.put(r * WS + i, pf[u]);
       }
-      M::refill_done(s);
-      M::seal_runs(L, s, tid);
-      merge4_store<NL, E>(out, nout, o, final, keep, out_perm, dst);
-      M::fill_amounts(s, (uint32_t)(FE * NT));
+      __syncthreads();
+      // B: the bound and each run's count (wave r searches run r)
+      if (wave < (uint32_t)kWinRuns) {
+        const int r = (int)wave;
+        K bk = key_sentinel<NL>();
+        const int br = win_bound(g.len, cons, (uint32_t)W, [&](int rr) { return L.t.get(rr * WS + W - 1); },
+                                 KeyLess<NL>(), bk);
+        const uint32_t wl = win_len(pick4(g.len, r), pick4(cons, r), W);
+        uint32_t cnt;
+        if (br < 0) {
+          cnt = wl;
+        } else if (br == r) {
+          cnt = (uint32_t)W;
+        } else {
+          const int p1 = win_probe1(wl, lane);
+          const bool b1 = p1 >= 0 && e_less(L.t.get(r * WS + p1), bk);
+          const uint32_t k1 = (uint32_t)__popcll(__ballot(b1));
+          const int p2 = win_probe2(wl, k1, lane);
+          const bool b2 = p2 >= 0 && e_less(L.t.get(r * WS + p2), bk);
+          cnt = k1 * win_slice(wl) + (uint32_t)__popcll(__ballot(b2));
+        }
+        // (no sentinel is written into the window here: other waves may still
+        // be reading its last item for the bound)
+        if (lane == 0) L.c[r] = cnt;
+      }
+      __syncthreads();
+      // the counts are the same in every lane: readfirstlane keeps them (and
+      // all the step's bookkeeping that follows) in scalar registers
+      uint32_t c[4];
 #pragma unroll
-      for (int u = 0; u < FE; ++u) M::refill_load(s, src, tid + (uint32_t)u * NT, pf[u]);
-      if (tid == 0) L.end[0][0] = L.end[0][1] = L.end[1][0] = L.end[1][1] = 0;
+      for (int r = 0; r < 4; ++r) c[r] = __builtin_amdgcn_readfirstlane(L.c[r]);
+      const uint32_t nx = c[0] + c[1], ny = c[2] + c[3], ns = nx + ny;
+      if (ns == 0) {   // never: the bounding window, or what is left, is taken
+        if (tid == 0) {
+          atomicOr(&h->status, ST_INVALID);
+          atomicOr(&h->abort, 1u);
+        }
+        return;
+      }
+      // C: the next step's windows, in flight while this one merges
+      uint32_t nc[4];
+#pragma unroll
+      for (int r = 0; r < 4; ++r) nc[r] = cons[r] + c[r];
+      if (done + ns < count) w4_load<NL, NT, E, W>(src, st, g.len, nc, pf);
+      // D: X = merge(A, B) and Y = merge(C, D)
+      K e[E];
+      {
+        const bool side = tid >= (uint32_t)(NT / 2);
+        const int diag = (int)(tid - (side ? NT / 2 : 0)) * E;
+        const int la = (int)(side ? c[2] : c[0]), lb = (int)(side ? c[3] : c[1]);
+        const int a0 = side ? 2 * WS : 0, b0 = a0 + WS;
+        const int o0 = side ? G::YOFF : G::XOFF;
+        if (diag < la + lb) {
+          const int sa = run_merge_path_steps(LinRun<decltype(L.t)>{L.t, a0}, la, LinRun<decltype(L.t)>{L.t, b0}, lb,
+                                              diag, bitlen((uint32_t)(la < lb ? la : lb)));
+          lds_bounded_merge<E>(L.t, a0 + sa, a0 + la, b0 + (diag - sa), b0 + lb, e);
+#pragma unroll
+          for (int j = 0; j < E; ++j)
+            if (diag + j < la + lb) L.t.put(o0 + diag + j, e[j]);
+        }
+        if (tid == 0) L.t.put(G::XOFF + (int)nx, key_sentinel<NL>());
+        if (tid == (uint32_t)(NT / 2)) L.t.put(G::YOFF + (int)ny, key_sentinel<NL>());
+      }
       __syncthreads();
-      // B: X and Y topped up
-      wx = M::want(s, 0);
-      wy = M::want(s, 1);
-      for (uint32_t wi = tid; wi < M::topup_items(s); wi += NT) M::topup(L, s, wi);
-      M::seal_xy(L, s, tid, wx, wy);
+      // E: the outputs, staged in LDS and stored in order
+      const uint32_t take = ns < count - done ? ns : count - done;
+      {
+        const int diag = (int)tid * E;
+        if ((uint32_t)diag < take) {
+          const int sx = run_merge_path_steps(LinRun<decltype(L.t)>{L.t, G::XOFF}, (int)nx,
+                                              LinRun<decltype(L.t)>{L.t, G::YOFF}, (int)ny, diag,
+                                              bitlen(nx < ny ? nx : ny));
+          lds_serial_merge<E>(L.t, G::XOFF + sx, G::YOFF + (diag - sx), e);
+#pragma unroll
+          for (int j = 0; j < E; ++j)
+            if ((uint32_t)(diag + j) < take) L.t.put(G::SOFF + diag + j, e[j]);
+        }
+      }
       __syncthreads();
-      M::topup_done(s, L, wx, wy);
-      // C: this step's outputs, into registers
-      const uint32_t cnt = count - done < (uint32_t)PS ? count - done : (uint32_t)PS;
-      nout = M::final_merge(L, s, tid, cnt, out);
-      o = ob + done + (size_t)tid * E;
-      __syncthreads();
-      M::final_done(s, L, cnt);
-      done += cnt;
+#pragma unroll
+      for (int r = 0; r < E; ++r) {
+        const uint32_t q = tid + (uint32_t)r * NT;
+        if (q < take) {
+          const K v = L.t.get(G::SOFF + (int)q);
+          const size_t o = ob + done + q;
+          if (final) __builtin_nontemporal_store(key_index<NL>(v), out_perm + o);
+          if (!final || keep) gstore_nt<NL>(dst, o, v);
+        }
+      }
+#pragma unroll
+      for (int r = 0; r < 4; ++r) cons[r] = nc[r];
+      done += ns;
     }
-    merge4_store<NL, E>(out, nout, o, final, keep, out_perm, dst);
     pos += count;
   }
 }

@@ -114,30 +114,30 @@ const Variant* variants(int c, int* count) {
   return all[c];
 }
 
-// Four-way merge configurations of a class: threads NT, outputs per thread E,
-// outputs per step PS, ring slots per run RC.
+// Four-way merge configurations of a class (k_merge4w, passes by bounded
+// windows): NT threads, E outputs a thread, windows of NT*E/4 items.
 struct Merge4 {
   void (*merge)(const Ws&, int, int, TileWork, unsigned, hipStream_t);
   const void* fn;
   int nt;
-  uint32_t ps;
+  uint32_t ps;   // outputs per step at most: four windows
 };
-template <int NL, int NT, int E, int PS, int RC>
-struct V4 {
+template <int NL, int NT, int E>
+struct V4W {
   static void merge(const Ws& w, int c, int l, TileWork tw, unsigned grid, hipStream_t s) {
-    sw::k_merge4<NL, NT, E, PS, RC><<<grid, NT, 0, s>>>(w, c, l, tw);
+    sw::k_merge4w<NL, NT, E><<<grid, NT, 0, s>>>(w, c, l, tw);
   }
-  static Merge4 get() { return Merge4{merge, (const void*)sw::k_merge4<NL, NT, E, PS, RC>, NT, (uint32_t)PS}; }
+  static Merge4 get() { return Merge4{merge, (const void*)sw::k_merge4w<NL, NT, E>, NT, (uint32_t)(NT * E)}; }
 };
 constexpr int kMaxMerge4 = 2;
 const Merge4* merges4(int c, int* count) {
-  static const Merge4 m0[] = {V4<0, 128, 2, 256, 512>::get(), V4<0, 128, 4, 512, 1024>::get()};
-  static const Merge4 m1[] = {V4<1, 128, 2, 256, 512>::get()};
-  static const Merge4 m2[] = {V4<2, 256, 1, 256, 512>::get()};
-  static const Merge4 m3[] = {V4<3, 128, 1, 128, 256>::get()};
-  static const Merge4 m4[] = {V4<4, 128, 1, 128, 256>::get()};
+  static const Merge4 m0[] = {V4W<0, 256, 4>::get(), V4W<0, 256, 2>::get()};
+  static const Merge4 m1[] = {V4W<1, 256, 4>::get(), V4W<1, 256, 2>::get()};
+  static const Merge4 m2[] = {V4W<2, 256, 4>::get(), V4W<2, 256, 2>::get()};
+  static const Merge4 m3[] = {V4W<3, 256, 2>::get()};
+  static const Merge4 m4[] = {V4W<4, 256, 2>::get()};
   static const Merge4* all[] = {m0, m1, m2, m3, m4};
-  static const int counts[] = {2, 1, 1, 1, 1};
+  static const int counts[] = {2, 2, 2, 1, 1};
   *count = counts[c];
   return all[c];
 }

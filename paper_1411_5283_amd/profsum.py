@@ -78,9 +78,9 @@ def _family(kernel: str) -> str | None:
     if not m:
         return None
     name = m.group(1)
-    if name in ("sort_tiles", "sort_packed", "merge", "merge4"):
+    if name in ("sort_tiles", "sort_packed", "merge", "merge4w"):
         nl = int(m.group(2)) if m.group(2) else -1
-        return "%s_c%d" % ("merge" if name == "merge4" else name, nl) if 0 <= nl <= 4 else None
+        return "%s_c%d" % ("merge" if name == "merge4w" else name, nl) if 0 <= nl <= 4 else None
     return name
 
 

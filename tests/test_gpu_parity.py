@@ -69,7 +69,7 @@ def test_long_segments_every_variant(gpu, oracle_mod, default_config, variant):
 def test_long_segments_every_merge(gpu, oracle_mod, default_config, merge):
     # the two-way levels (0) and each four-way configuration (1..) of every
     # class, on 1.5M words: many groups, workgroup ranges starting inside
-    # groups at every level, short last groups
+    # groups at every level, short last groups, windows bounded by every run
     wl = wordgen.single(1_500_000, 40_000, 1.1, 20, seed=9)
     m = [min(merge, gpu.num_merges(c) - 1) for c in range(gpu.NUM_CLASSES)]
     _say("case long segments merge=%s n=%d" % (m, wl.n))
@@ -77,12 +77,12 @@ def test_long_segments_every_merge(gpu, oracle_mod, default_config, merge):
     _same(gpu.sort_wordlist(wl), _expect(oracle_mod, wl, bubble=False), "long merge %s" % m)
 
 
-@pytest.mark.parametrize("merge", [0, 1])
+@pytest.mark.parametrize("merge", [0, 1, 2])
 def test_per_bucket_launch_every_merge(gpu, oracle_mod, default_config, merge):
     # the per-bucket-launch form launches each segment's merge passes directly
     import torch
     wl = wordgen.config(3, 0.01)
-    gpu.set_config(merge=[merge] * gpu.NUM_CLASSES)
+    gpu.set_config(merge=[min(merge, gpu.num_merges(c) - 1) for c in range(gpu.NUM_CLASSES)])
     _say("case per-bucket launch merge=%d docs=%d n=%d" % (merge, wl.n_docs, wl.n))
     chars, offs, docs = gpu.device_words(wl)
     ws = torch.empty(gpu.sort_words_workspace_size(wl.n, wl.n_docs), dtype=torch.uint8, device="cuda")

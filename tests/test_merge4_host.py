@@ -1,10 +1,10 @@
-"""The four-way merge level on the CPU (host builds of csrc/sw_split.hpp and
-csrc/sw_merge4.hpp, the code the merge kernel runs): the co-rank search
+"""The four-way merge pass on the CPU (host builds of csrc/sw_split.hpp and
+csrc/sw_window.hpp, the code the merge kernel runs): the co-rank search
 against a plain merge on every rank of small runs and on random ranks of
-large ones, and a whole level -- workgroup ranges, segments, groups, split
-search, rings, top-ups and final merges, thread by thread -- against a plain
-sort of each group, with the rings' invariants asserted at every step.  Both
-under the address and undefined-behaviour sanitizers."""
+large ones, and the pass by bounded windows -- bound, counts by the two probe
+rounds, the merges of every step, the window loads -- walked from random
+start ranks over groups of many shapes against a plain sort.  Both under the
+address and undefined-behaviour sanitizers."""
 import os
 import subprocess
 
@@ -13,7 +13,7 @@ import pytest
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 
 
-@pytest.mark.parametrize("name", ["split_test", "merge4_test"])
+@pytest.mark.parametrize("name", ["split_test", "window_test"])
 def test_four_way_merge_host(tmp_path, name):
     exe = str(tmp_path / name)
     subprocess.check_call(["g++", "-std=c++17", "-O1", "-Wall", "-Wno-unknown-pragmas",
