@@ -4,6 +4,7 @@ Every case sorts through the C ABI (sort_words, sort_words_ex,
 sort_words_batch, sort_words_plain, sw_plan_*) and compares the permutation
 and the bucket offsets with the oracle on the same seeded input.
 """
+import functools
 import sys
 
 import numpy as np
@@ -191,6 +192,38 @@ def test_edge_cases(gpu, oracle_mod, name):
     wl = wordgen.from_words(EDGES[name])
     _say("case edge %s n=%d" % (name, wl.n))
     _same(gpu.sort_wordlist(wl), _expect(oracle_mod, wl, bubble=False), name)
+
+
+SKEWED = ("equal", "reversed", "sawtooth", "sorted", "sorted_every_class")
+
+
+@functools.lru_cache(maxsize=1)
+def _skewed_lists():
+    # runs whose key ranges are disjoint or nested after the chunk sort, so
+    # that a four-way step is bounded by one run and takes only its window
+    # (built when first used: a CPU-only run collects this module too)
+    rng = np.random.default_rng(13)
+    six = sorted({bytes(rng.integers(97, 123, 6, dtype=np.uint8)) for _ in range(150_000)})
+    saw = [b"%07d" % (k % 20_000) for k in range(160_000)]
+    by_len = [w for L in (3, 7, 12, 20, 30)
+              for w in sorted(bytes(rng.integers(97, 123, L, dtype=np.uint8)) for _ in range(40_000))]
+    return {
+        "sorted": six,
+        "reversed": six[::-1],
+        "equal": [b"word"] * 120_000,
+        "sawtooth": saw,
+        "sorted_every_class": by_len,
+    }
+
+
+@pytest.mark.parametrize("name", SKEWED)
+def test_four_way_skewed_runs(gpu, oracle_mod, default_config, name):
+    # the four-way passes (every class) against the oracle where the bound of
+    # a step comes from one run again and again
+    wl = wordgen.from_words(_skewed_lists()[name])
+    _say("case four-way skewed %s n=%d" % (name, wl.n))
+    gpu.set_config(merge=[1] * gpu.NUM_CLASSES)
+    _same(gpu.sort_wordlist(wl), _expect(oracle_mod, wl, bubble=False), "four-way " + name)
 
 
 def _three_lane_words(n, seed):
