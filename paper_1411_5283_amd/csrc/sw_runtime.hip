@@ -1290,13 +1290,19 @@ class CopyPool {
 class Uploader {
  public:
   static constexpr uint64_t kStage = 4u << 20;
+  // host-to-device copies go out on this many streams (worker i on stream
+  // i % kStreams), so that several copy engines can carry them
+  static constexpr int kStreams = 4;
 
   int init(unsigned workers, uint8_t* base, std::function<void()> notify) {
     base_ = base;
     notify_ = std::move(notify);
-    if (hipStreamCreateWithFlags(&s_, hipStreamNonBlocking) != hipSuccess) return SW_ERR_HIP;
+    for (int k = 0; k < kStreams; ++k)
+      if (hipStreamCreateWithFlags(&s_[k], hipStreamNonBlocking) != hipSuccess) return SW_ERR_HIP;
     stage_.resize(std::max(1u, workers));
-    for (Stage& st : stage_) {
+    for (size_t i = 0; i < stage_.size(); ++i) {
+      Stage& st = stage_[i];
+      st.stream = (int)(i % kStreams);
       for (int b = 0; b < 2; ++b) {
         if (hipHostMalloc(&st.buf[b], kStage, 0) != hipSuccess) return SW_ERR_OOM;
         if (hipEventCreateWithFlags(&st.ev[b], hipEventDisableTiming) != hipSuccess) return SW_ERR_HIP;
@@ -1313,7 +1319,8 @@ class Uploader {
     cv_.notify_all();
     for (auto& t : th_) t.join();
     th_.clear();
-    if (s_) (void)hipStreamSynchronize(s_);
+    for (int k = 0; k < kStreams; ++k)
+      if (s_[k]) (void)hipStreamSynchronize(s_[k]);
   }
   void free_all() {
     for (Stage& st : stage_)
@@ -1322,8 +1329,10 @@ class Uploader {
         if (st.ev[b]) (void)hipEventDestroy(st.ev[b]);
       }
     stage_.clear();
-    if (s_) (void)hipStreamDestroy(s_);
-    s_ = nullptr;
+    for (int k = 0; k < kStreams; ++k) {
+      if (s_[k]) (void)hipStreamDestroy(s_[k]);
+      s_[k] = nullptr;
+    }
   }
   void push(swsrv::Request* r) {
     {
@@ -1338,6 +1347,7 @@ class Uploader {
     uint8_t* buf[2] = {nullptr, nullptr};
     hipEvent_t ev[2] = {nullptr, nullptr};
     int next = 0;
+    int stream = 0;
   };
 
   void loop(Stage& st) {
@@ -1396,14 +1406,15 @@ class Uploader {
       for (int part = 0; part < 2; ++part)
         if (len[part]) memcpy(st.buf[b] + (r->dev_off - start) + at[part], src[part], len[part]);
     }
-    std::lock_guard<std::mutex> lk(issue_mu_);
-    if (hipMemcpyAsync(base_ + start, st.buf[b], total, hipMemcpyHostToDevice, s_) != hipSuccess ||
-        hipEventRecord(st.ev[b], s_) != hipSuccess)
+    std::lock_guard<std::mutex> lk(issue_mu_[st.stream]);
+    if (hipMemcpyAsync(base_ + start, st.buf[b], total, hipMemcpyHostToDevice, s_[st.stream]) != hipSuccess ||
+        hipEventRecord(st.ev[b], s_[st.stream]) != hipSuccess)
       return SW_ERR_HIP;
-    ++seq_;
+    const uint64_t q = ++seq_[st.stream];
     for (swsrv::Request* r : group) {
       r->upload_event = st.ev[b];
-      r->upload_seq = seq_;
+      r->upload_seq = q;
+      r->upload_stream = st.stream;
     }
     return SW_OK;
   }
@@ -1419,26 +1430,27 @@ class Uploader {
         int b;
         if (next_buffer(st, &b)) return SW_ERR_HIP;
         memcpy(st.buf[b], src[part] + pos, n);
-        std::lock_guard<std::mutex> lk(issue_mu_);
-        if (hipMemcpyAsync(dst + at[part] + pos, st.buf[b], n, hipMemcpyHostToDevice, s_) != hipSuccess ||
-            hipEventRecord(st.ev[b], s_) != hipSuccess)
+        std::lock_guard<std::mutex> lk(issue_mu_[st.stream]);
+        if (hipMemcpyAsync(dst + at[part] + pos, st.buf[b], n, hipMemcpyHostToDevice, s_[st.stream]) != hipSuccess ||
+            hipEventRecord(st.ev[b], s_[st.stream]) != hipSuccess)
           return SW_ERR_HIP;
         r->upload_event = st.ev[b];
-        r->upload_seq = ++seq_;
+        r->upload_seq = ++seq_[st.stream];
+        r->upload_stream = st.stream;
       }
     }
     return SW_OK;
   }
 
-  hipStream_t s_ = nullptr;
+  hipStream_t s_[kStreams] = {};
   uint8_t* base_ = nullptr;
   std::function<void()> notify_;
   std::vector<Stage> stage_;
   std::vector<std::thread> th_;
-  std::mutex mu_, issue_mu_;
+  std::mutex mu_, issue_mu_[kStreams];
   std::condition_variable cv_;
   std::deque<swsrv::Request*> q_;
-  uint64_t seq_ = 0;
+  uint64_t seq_[kStreams] = {};   // uploads issued on each stream
   bool stop_ = false;
 };
 
@@ -1492,12 +1504,14 @@ class HipExec {
     sl.cpos.resize(nr + 1);
     sl.wpos[0] = sl.cpos[0] = 0;
     sl.h_docs[0] = 0;
-    const swsrv::Request* latest = b.reqs[0];
+    // per upload stream, the batch's request uploaded last on it
+    const swsrv::Request* latest[Uploader::kStreams] = {};
     uint32_t np = 0;
     for (size_t i = 0; i < nr; ++i) {
       const swsrv::Request* r = b.reqs[i];
       if (r->upload_error) return r->upload_error;
-      if (r->upload_seq > latest->upload_seq) latest = r;
+      const swsrv::Request*& l = latest[r->upload_stream];
+      if (!l || r->upload_seq > l->upload_seq) l = r;
       sl.wpos[i + 1] = sl.wpos[i] + r->n;
       sl.cpos[i + 1] = sl.cpos[i] + r->nchars;
       sl.h_docs[i + 1] = (uint32_t)sl.wpos[i + 1];
@@ -1512,8 +1526,10 @@ class HipExec {
     const uint64_t W = sl.wpos[nr];
     HIP_TRY(hipMemcpyAsync(sl.d_pieces, sl.h_pieces, sizeof(sw::GatherPiece) * np, hipMemcpyHostToDevice, sl.s));
     HIP_TRY(hipMemcpyAsync(sl.d_docs, sl.h_docs, 4 * (nr + 1), hipMemcpyHostToDevice, sl.s));
-    // the uploads are issued in one order on one stream: the batch's latest covers all
-    HIP_TRY(hipStreamWaitEvent(sl.s, (hipEvent_t)latest->upload_event, 0));
+    // each upload stream carries its copies in issue order: the batch's latest
+    // on a stream covers its other requests there
+    for (const swsrv::Request* l : latest)
+      if (l) HIP_TRY(hipStreamWaitEvent(sl.s, (hipEvent_t)l->upload_event, 0));
     sw::k_gather<256><<<np, 256, 0, sl.s>>>(sl.d_pieces, sl.d_chars, sl.d_offsets);
     HIP_TRY(hipGetLastError());
     int rc = sw_plan_run(sl.plan, sl.d_chars, sl.d_offsets, sl.d_docs, (uint32_t)nr, (uint32_t)W, sl.d_perm,

@@ -52,7 +52,8 @@ struct Request {
   // the executor's: where the request lies in device memory, and its upload
   uint64_t dev_off = 0;
   std::atomic<bool> uploaded{false};
-  uint64_t upload_seq = 0;          // issue order of the upload (valid once uploaded)
+  uint64_t upload_seq = 0;          // issue order of the upload on its stream (valid once uploaded)
+  int upload_stream = 0;            // which upload stream carried it
   int upload_error = 0;
   void* upload_event = nullptr;
 };
