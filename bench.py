@@ -711,6 +711,8 @@ def main():
         print("bench.py: the library runs on one GPU; --gpus %d is not supported (sharding across "
               "GPUs is a design, not code)" % args.gpus, file=sys.stderr)
         sys.exit(2)
+    if args.steps < 1 or args.profile_steps < 1 or args.warmup < 0:
+        ap.error("--steps and --profile-steps must be at least 1, --warmup at least 0")
 
     import torch
     if args.copy_calibration:
