@@ -7,7 +7,9 @@
         [--outdir <dir>]
 
 --outdir names the folder the counter runs wrote to (it appears in the
-commands each summary records).
+commands each summary records); --extra "<args>" adds bench arguments to
+those commands (e.g. a merge choice), and --tag names the runs' folders when
+it is not the workload.
 
 ``traffic`` averages FETCH_SIZE and WRITE_SIZE (KiB per dispatch) per kernel
 family and scales them by what the same counters read for a plain 1 GiB
@@ -40,22 +42,29 @@ SQ_COUNTERS = ("SQ_INSTS_VALU SQ_ACTIVE_INST_VALU SQ_INSTS_LDS SQ_ACTIVE_INST_LD
                "GRBM_GUI_ACTIVE")
 
 
-def traffic_commands(w: str, d: str) -> list:
+def _bench_cmd(w: str, extra: str) -> str:
+    return BENCH.format(w=w) + (" " + extra if extra else "")
+
+
+def traffic_commands(w: str, d: str, extra: str = "", tag: str = "", text: bool = True) -> list:
     """The runs a traffic summary is made from; d: the folder they wrote to."""
-    b = BENCH.format(w=w)
-    return [
-        "rocprofv3 --pmc FETCH_SIZE --output-format csv -d %s/f_%s -o f -- %s --no-text" % (d, w, b),
-        "rocprofv3 --pmc WRITE_SIZE --output-format csv -d %s/w_%s -o w -- %s --no-text" % (d, w, b),
-        "rocprofv3 --pmc FETCH_SIZE --output-format csv -d %s/ft_%s -o f -- %s" % (d, w, b),
-        "rocprofv3 --pmc WRITE_SIZE --output-format csv -d %s/wt_%s -o w -- %s" % (d, w, b),
+    b, t = _bench_cmd(w, extra), tag or w
+    cmds = [
+        "rocprofv3 --pmc FETCH_SIZE --output-format csv -d %s/f_%s -o f -- %s --no-text" % (d, t, b),
+        "rocprofv3 --pmc WRITE_SIZE --output-format csv -d %s/w_%s -o w -- %s --no-text" % (d, t, b),
+    ]
+    if text:
+        cmds += ["rocprofv3 --pmc FETCH_SIZE --output-format csv -d %s/ft_%s -o f -- %s" % (d, t, b),
+                 "rocprofv3 --pmc WRITE_SIZE --output-format csv -d %s/wt_%s -o w -- %s" % (d, t, b)]
+    return cmds + [
         "rocprofv3 --pmc FETCH_SIZE --output-format csv -d %s/cf -o cf -- python3 bench.py --copy-calibration" % d,
         "rocprofv3 --pmc WRITE_SIZE --output-format csv -d %s/cw -o cw -- python3 bench.py --copy-calibration" % d,
     ]
 
 
-def valu_commands(w: str, d: str) -> list:
+def valu_commands(w: str, d: str, extra: str = "", tag: str = "") -> list:
     return ["rocprofv3 --pmc %s --output-format csv -d %s/sq%d_%s -o s -- %s --no-text" % (
-        c, d, i, w, BENCH.format(w=w)) for i, c in enumerate(SQ_COUNTERS)]
+        c, d, i, tag or w, _bench_cmd(w, extra)) for i, c in enumerate(SQ_COUNTERS)]
 
 
 def stats(src: str, cmd: str, out: str) -> None:
@@ -103,7 +112,8 @@ def _tiles(b: dict) -> dict:
 
 
 def traffic(workload: str, fetch: str, write: str, cfetch: str, cwrite: str, bench_json: str, out: str,
-            text_fetch: str | None = None, text_write: str | None = None, outdir: str = "out") -> None:
+            text_fetch: str | None = None, text_write: str | None = None, outdir: str = "out",
+            extra: str = "", tag: str = "") -> None:
     f = _per_dispatch(fetch, "FETCH_SIZE")
     w = _per_dispatch(write, "WRITE_SIZE")
     if text_fetch and text_write:
@@ -130,12 +140,14 @@ def traffic(workload: str, fetch: str, write: str, cfetch: str, cwrite: str, ben
            "tiles": _tiles(b), "fetch_scale": fs, "write_scale": wsc,
            "calibration": "plain device copy of 1 GiB (__amd_rocclr_copyBuffer): FETCH_SIZE %.0f KiB, "
                           "WRITE_SIZE %.0f KiB per dispatch" % (cf, cw),
-           "commands": traffic_commands(workload, outdir), "kernels": kern}
+           "commands": traffic_commands(workload, outdir, extra, tag, bool(text_fetch and text_write)),
+           "kernels": kern}
     with open(out, "w") as fh:
         json.dump(res, fh, indent=1, sort_keys=True)
 
 
-def valu(workload: str, pmcs: str, bench_json: str, out: str, outdir: str = "out") -> None:
+def valu(workload: str, pmcs: str, bench_json: str, out: str, outdir: str = "out", extra: str = "",
+         tag: str = "") -> None:
     agg = collections.defaultdict(lambda: collections.defaultdict(list))
     for pmc in pmcs.split(","):
         for r in csv.DictReader(open(pmc)):
@@ -152,7 +164,7 @@ def valu(workload: str, pmcs: str, bench_json: str, out: str, outdir: str = "out
             row[name + "_per_dispatch"] = sum(vals) / len(vals)
         kern[fam] = row
     res = {"source_hash": b["kernel_source"], "workload": b["config"]["workload"] + " (bench.py --serial)",
-           "tiles": _tiles(b), "commands": valu_commands(workload, outdir), "kernels": kern,
+           "tiles": _tiles(b), "commands": valu_commands(workload, outdir, extra, tag), "kernels": kern,
            "note": "SQ_INSTS_VALU counts wave instructions (each up to 64 lanes); SQ_ACTIVE_INST_VALU and "
                    "SQ_ACTIVE_INST_LDS are quad-cycles summed over waves; every value is summed over the "
                    "shader engines and the 8 XCDs (GRBM_GUI_ACTIVE / 8 = the dispatch's clocks)"}
@@ -162,16 +174,18 @@ def valu(workload: str, pmcs: str, bench_json: str, out: str, outdir: str = "out
 
 if __name__ == "__main__":
     argv = list(sys.argv[1:])
-    outdir = "out"
-    if "--outdir" in argv:   # the folder the counter runs wrote to, for the recorded commands
-        k = argv.index("--outdir")
-        outdir = argv[k + 1]
-        del argv[k:k + 2]
+    opts = {"--outdir": "out", "--extra": "", "--tag": ""}
+    for name in opts:   # the recorded commands: runs' folder, extra bench arguments, folder tag
+        if name in argv:
+            k = argv.index(name)
+            opts[name] = argv[k + 1]
+            del argv[k:k + 2]
+    kw = {"outdir": opts["--outdir"], "extra": opts["--extra"], "tag": opts["--tag"]}
     if argv[0] == "stats":
         stats(*argv[1:4])
     elif argv[0] == "traffic":
-        traffic(*argv[1:10], outdir=outdir)
+        traffic(*argv[1:10], **kw)
     elif argv[0] == "valu":
-        valu(*argv[1:5], outdir=outdir)
+        valu(*argv[1:5], **kw)
     else:
         raise SystemExit(__doc__)
