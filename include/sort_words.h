@@ -32,7 +32,9 @@
  *     L = 0..SW_MAX_LEN+1 (SW_NUM_OFFSETS entries; the last one is n).  The
  *     words of length L are out_perm[out_bucket_offsets[L] ..
  *     out_bucket_offsets[L+1]).
- *   - Pointers named chars/offsets/doc_offsets/out_* are DEVICE pointers.  The
+ *   - Pointers named chars/offsets/doc_offsets/out_* are DEVICE pointers;
+ *     the device offsets and doc_offsets must be 4-byte aligned (as a
+ *     uint32_t array is), else SW_ERR_INVALID_ARG.  The
  *     caller owns every buffer; the library keeps no reference to one after
  *     the work on the stream has completed.  Inputs and outputs must not
  *     alias.  Outputs are fully overwritten.
@@ -56,7 +58,7 @@ extern "C" {
 
 typedef enum {
     SW_OK = 0,
-    SW_ERR_INVALID_ARG = -1,   /* null pointer, bad size, offsets that decrease */
+    SW_ERR_INVALID_ARG = -1,   /* null or misaligned pointer, bad size, offsets that decrease */
     SW_ERR_WORD_TOO_LONG = -2, /* a word longer than SW_MAX_LEN bytes */
     SW_ERR_WORKSPACE = -3,     /* workspace too small for the request */
     SW_ERR_OOM = -4,           /* device allocation failed */

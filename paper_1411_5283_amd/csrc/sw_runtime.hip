@@ -681,10 +681,17 @@ size_t sort_words_workspace_size(uint32_t max_words, uint32_t max_docs) {
   return L.total;
 }
 
+// Device offset arrays are read with 16-byte loads from the 16-byte aligned
+// address below them, which assumes a 4-byte aligned start (as any uint32_t
+// array has); a misaligned one is rejected rather than read shifted.
+bool misaligned(const void* p) { return ((uintptr_t)p & 3) != 0; }
+
 int sort_words_noalloc(const uint8_t* chars, const uint32_t* offsets, uint32_t n, uint32_t* out_perm,
                        uint32_t* out_bucket_offsets, uint32_t* out_status, void* stream) {
   if (!offsets || !out_bucket_offsets || !out_status || (n && !out_perm))
     return fail(SW_ERR_INVALID_ARG, "sort_words_noalloc: null pointer argument");
+  if (misaligned(offsets))
+    return fail(SW_ERR_INVALID_ARG, "sort_words_noalloc: offsets not 4-byte aligned");
   Layout L;
   if (!make_layout(n, 1, L)) return fail(SW_ERR_INVALID_ARG, "sort_words_noalloc: n out of range");
   if (L.total > SW_NOALLOC_SCRATCH_BYTES)
@@ -713,6 +720,8 @@ int sort_words_ex(const uint8_t* chars, const uint32_t* offsets, uint32_t n, uin
                   uint32_t* out_bucket_offsets, void* workspace, size_t workspace_bytes, void* stream) {
   if (!offsets || !out_bucket_offsets || (n && !out_perm) || !workspace)
     return fail(SW_ERR_INVALID_ARG, "sort_words_ex: null pointer argument");
+  if (misaligned(offsets))
+    return fail(SW_ERR_INVALID_ARG, "sort_words_ex: offsets not 4-byte aligned");
   Layout L;
   if (!make_layout(n, 1, L)) return fail(SW_ERR_INVALID_ARG, "sort_words_ex: n out of range");
   if (L.total > workspace_bytes)
@@ -724,6 +733,8 @@ int sort_words(const uint8_t* chars, const uint32_t* offsets, uint32_t n, uint32
                uint32_t* out_bucket_offsets) {
   if (!offsets || !out_bucket_offsets || (n && !out_perm))
     return fail(SW_ERR_INVALID_ARG, "sort_words: null pointer argument");
+  if (misaligned(offsets))
+    return fail(SW_ERR_INVALID_ARG, "sort_words: offsets not 4-byte aligned");
   Layout L;
   if (!make_layout(n, 1, L)) return fail(SW_ERR_INVALID_ARG, "sort_words: n out of range");
   int dev = 0;
@@ -755,6 +766,8 @@ int sort_words_batch(const uint8_t* chars, const uint32_t* offsets, const uint32
                      void* stream) {
   if (!offsets || !doc_offsets || !out_bucket_offsets || !out_perm || !workspace)
     return fail(SW_ERR_INVALID_ARG, "sort_words_batch: null pointer argument");
+  if (misaligned(offsets) || misaligned(doc_offsets))
+    return fail(SW_ERR_INVALID_ARG, "sort_words_batch: offsets not 4-byte aligned");
   const uint64_t cap = capacity_for(workspace_bytes, n_docs);
   Layout L;
   if (!make_layout(cap, n_docs, L) || L.total > workspace_bytes)
@@ -783,6 +796,8 @@ int sort_words_plain(const uint8_t* chars, const uint32_t* offsets, const uint32
                      void* stream) {
   if (!offsets || !doc_offsets || !out_bucket_offsets || !out_perm || !workspace)
     return fail(SW_ERR_INVALID_ARG, "sort_words_plain: null pointer argument");
+  if (misaligned(offsets) || misaligned(doc_offsets))
+    return fail(SW_ERR_INVALID_ARG, "sort_words_plain: offsets not 4-byte aligned");
   const uint64_t cap = capacity_for(workspace_bytes, n_docs);
   Layout L;
   if (!make_layout(cap, n_docs, L) || L.total > workspace_bytes)
@@ -832,6 +847,8 @@ int sort_words_chunks(const uint8_t* chars, const uint32_t* offsets, uint32_t n,
                       void* stream) {
   if (!offsets || !out_bucket_offsets || !workspace || (n && !out_perm))
     return fail(SW_ERR_INVALID_ARG, "sort_words_chunks: null pointer argument");
+  if (misaligned(offsets))
+    return fail(SW_ERR_INVALID_ARG, "sort_words_chunks: offsets not 4-byte aligned");
   if (chunk < 2 || chunk > 1024 || (chunk & (chunk - 1)))
     return fail(SW_ERR_INVALID_ARG, "sort_words_chunks: chunk %u is not a power of two in [2,1024]", chunk);
   Layout L;
@@ -868,6 +885,8 @@ int sort_words_unbucketed(const uint8_t* chars, const uint32_t* offsets, uint32_
                           uint32_t* out_bucket_offsets, void* workspace, size_t workspace_bytes, void* stream) {
   if (!offsets || !out_bucket_offsets || !workspace || (n && !out_perm))
     return fail(SW_ERR_INVALID_ARG, "sort_words_unbucketed: null pointer argument");
+  if (misaligned(offsets))
+    return fail(SW_ERR_INVALID_ARG, "sort_words_unbucketed: offsets not 4-byte aligned");
   Layout L;
   if (!make_layout(capacity_for(workspace_bytes, 1), 1, L) || L.total > workspace_bytes || n > L.Nmax)
     return fail(SW_ERR_WORKSPACE, "sort_words_unbucketed: workspace too small for %u words", n);
@@ -998,6 +1017,8 @@ static int plan_check(const sw_plan* p, const char* what, const uint32_t* offset
                       uint32_t n_docs, uint32_t n_words, const uint32_t* out_perm,
                       const uint32_t* out_bucket_offsets) {
   if (!p || !offsets || !out_bucket_offsets) return fail(SW_ERR_INVALID_ARG, "%s: null argument", what);
+  if (misaligned(offsets) || misaligned(doc_offsets))
+    return fail(SW_ERR_INVALID_ARG, "%s: offsets not 4-byte aligned", what);
   if (doc_offsets) {
     if (n_docs > p->L.Dmax)
       return fail(SW_ERR_WORKSPACE, "%s: %u documents, plan holds %llu", what, n_docs, (unsigned long long)p->L.Dmax);
@@ -1183,6 +1204,8 @@ int sort_words_materialize(const uint8_t* chars, const uint32_t* offsets, const 
                            int sep, uint8_t* out_text, uint32_t* out_status, void* stream) {
   if (!offsets || !bucket_offsets || !out_status || (n_words && (!chars || !perm || !out_text)))
     return fail(SW_ERR_INVALID_ARG, "sort_words_materialize: null pointer argument");
+  if (misaligned(offsets) || misaligned(doc_offsets))
+    return fail(SW_ERR_INVALID_ARG, "sort_words_materialize: offsets not 4-byte aligned");
   if (sep > 255) return fail(SW_ERR_INVALID_ARG, "sort_words_materialize: separator %d is not a byte", sep);
   if (doc_offsets ? n_docs == 0 : n_docs != 1)
     return fail(SW_ERR_INVALID_ARG, "sort_words_materialize: n_docs must be 1 without doc_offsets, >= 1 with");

@@ -104,9 +104,10 @@ def test_text_entry_points_validate_on_host():
     assert L.sort_words_materialize(None, None, None, 1, 0, None, None, 10, None, None, None) == sw.ERR_INVALID_ARG
     # sort + text: a null plan
     assert L.sw_plan_run_text(None, None, None, None, 1, 0, None, None, 10, None) == sw.ERR_INVALID_ARG
-    assert L.sort_words_materialize(1, 1, None, 1, 5, 1, 1, 256, 1, 1, None) == sw.ERR_INVALID_ARG
-    assert L.sort_words_materialize(1, 1, None, 2, 5, 1, 1, 10, 1, 1, None) == sw.ERR_INVALID_ARG
-    assert L.sort_words_materialize(1, 1, 1, 0, 5, 1, 1, 10, 1, 1, None) == sw.ERR_INVALID_ARG
+    assert L.sort_words_materialize(16, 16, None, 1, 5, 16, 16, 256, 16, 16, None) == sw.ERR_INVALID_ARG
+    assert b"separator" in L.sort_words_last_error()
+    assert L.sort_words_materialize(16, 16, None, 2, 5, 16, 16, 10, 16, 16, None) == sw.ERR_INVALID_ARG
+    assert L.sort_words_materialize(16, 16, 16, 0, 5, 16, 16, 10, 16, 16, None) == sw.ERR_INVALID_ARG
 
 
 def test_unbucketed_validates_on_host():
@@ -114,7 +115,7 @@ def test_unbucketed_validates_on_host():
     L = sw.lib()
     assert L.sort_words_unbucketed(None, None, 0, None, None, None, 0, None) == sw.ERR_INVALID_ARG
     assert L.sort_words_unbucketed(1, 1, 5, None, 1, 1, 1 << 20, None) == sw.ERR_INVALID_ARG
-    assert L.sort_words_unbucketed(1, 1, 5, 1, 1, 1, 16, None) == sw.ERR_WORKSPACE
+    assert L.sort_words_unbucketed(16, 16, 5, 16, 16, 16, 16, None) == sw.ERR_WORKSPACE
 
 
 def test_server_validates_on_host():
@@ -134,3 +135,30 @@ def test_server_validates_on_host():
     assert L.sw_server_submit(None, None, None, 0, None, None, ctypes.byref(t)) == sw.ERR_INVALID_ARG
     assert L.sw_server_wait(None, 1, None) == sw.ERR_INVALID_ARG
     assert L.sw_server_fixed_bytes(None) == 0
+
+def test_misaligned_offsets_rejected_on_host():
+    # device offsets are read with 16-byte loads from the aligned address
+    # below them: an array that does not start on 4 bytes is refused before
+    # any device call, by every entry point that takes one
+    import paper_1411_5283_amd as sw
+    if not os.path.exists(sw.LIB_PATH):
+        pytest.skip("library not built")
+    L = sw.lib()
+    buf = ctypes.create_string_buffer(256)
+    p = (ctypes.addressof(buf) + 15) & ~15
+    m = p + 2                                   # misaligned
+    big = 1 << 30
+    calls = {
+        "sort_words": lambda o: L.sort_words(p, o, 3, p, p),
+        "sort_words_ex": lambda o: L.sort_words_ex(p, o, 3, p, p, p, big, None),
+        "sort_words_noalloc": lambda o: L.sort_words_noalloc(p, o, 3, p, p, p, None),
+        "sort_words_batch": lambda o: L.sort_words_batch(p, o, p, 1, p, p, p, big, None),
+        "sort_words_batch docs": lambda o: L.sort_words_batch(p, p, o, 1, p, p, p, big, None),
+        "sort_words_plain": lambda o: L.sort_words_plain(p, o, p, 1, p, p, p, big, None),
+        "sort_words_chunks": lambda o: L.sort_words_chunks(p, o, 3, 16, p, p, p, big, None),
+        "sort_words_unbucketed": lambda o: L.sort_words_unbucketed(p, o, 3, p, p, p, big, None),
+        "sort_words_materialize": lambda o: L.sort_words_materialize(p, o, None, 1, 3, p, p, 10, p, p, None),
+    }
+    for name, call in calls.items():
+        assert call(m) == sw.ERR_INVALID_ARG, name
+        assert b"aligned" in L.sort_words_last_error(), name
