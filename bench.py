@@ -689,6 +689,8 @@ def main():
     ap.add_argument("--merge", default=None,
                     help="merge choice per class, e.g. 0,0,0,0 (two-way levels) or 1,1,1,1 (four-way); "
                          "default: the tuned or built-in choice")
+    ap.add_argument("--chunk", default=None,
+                    help="chunk size per class, e.g. 16,16,16,32,32; default: the tuned or built-in choice")
     ap.add_argument("--variant", default=None,
                     help="tile configuration per class, e.g. 3,3,1,0,0; default: the tuned or built-in choice")
     ap.add_argument("--serve-warmup", type=int, default=200)
@@ -745,6 +747,8 @@ def main():
         sw.set_config(merge=[int(x) for x in args.merge.split(",")])
     if args.variant:
         sw.set_config(variant=[int(x) for x in args.variant.split(",")])
+    if args.chunk:
+        sw.set_config(chunk=[int(x) for x in args.chunk.split(",")])
     cfg = sw.get_config()
     tiles = [sw.variant_tiles(c, cfg["variant"][c])[0] for c in range(sw.NUM_CLASSES)]
     tile_cfg = {"chunk": list(cfg["chunk"]), "variant": list(cfg["variant"]), "merge": list(cfg["merge"])}

@@ -29,7 +29,7 @@ from . import NUM_CLASSES
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 CACHE = os.environ.get("SW_TUNE_CACHE", os.path.join(HERE, "tuned.json"))
-CHUNKS = (16, 32, 64, 128, 256)
+CHUNKS = (8, 16, 32, 64, 128, 256)
 
 
 def device_key() -> str:
