@@ -276,7 +276,10 @@ struct LdsTile {
   uint64_t k[kLanes][kPadded];
   uint32_t idx[NL ? kPadded : 1];
 
-  __device__ static int pos(int i) { return i + (i >> PADSH); }
+  __device__ static int pos(int i) {
+    const uint32_t u = (uint32_t)i;   // i >= 0: a logical shift
+    return (int)(u + (u >> PADSH));
+  }
   __device__ Key<NL> get(int i) const {
     const int p = pos(i);
     Key<NL> v;
@@ -297,13 +300,22 @@ struct LdsTile<0, CAP, PADSH> {
   using value_type = Key<0>;
   static constexpr int kPadded = CAP + (CAP >> PADSH);
   uint64_t k[kPadded];
-  __device__ static int pos(int i) { return i + (i >> PADSH); }
+  __device__ static int pos(int i) {
+    const uint32_t u = (uint32_t)i;
+    return (int)(u + (u >> PADSH));
+  }
+  // Byte offset of item i, (i + i/2^PADSH) * 8: one shift and one
+  // add-and-scale (i >= 0).
+  __device__ static uint32_t boff(int i) {
+    const uint32_t u = (uint32_t)i;
+    return (u + (u >> PADSH)) << 3;
+  }
   __device__ Key<0> get(int i) const {
     Key<0> v;
-    v.k = k[pos(i)];
+    v.k = *(const uint64_t*)((const char*)k + boff(i));
     return v;
   }
-  __device__ void put(int i, const Key<0>& v) { k[pos(i)] = v.k; }
+  __device__ void put(int i, const Key<0>& v) { *(uint64_t*)((char*)k + boff(i)) = v.k; }
 };
 
 // ---------------------------------------------------------------- tagged keys
@@ -338,7 +350,7 @@ template <int NL>
 __device__ inline bool e_less(const Key<NL>& a, const Key<NL>& b) { return key_less<NL>(a, b); }
 template <int NL>
 __device__ inline bool e_less(const TKey<NL>& a, const TKey<NL>& b) {
-  return a.tag != b.tag ? a.tag < b.tag : key_less<NL>(a.k, b.k);
+  return (a.tag < b.tag) | ((a.tag == b.tag) & key_less<NL>(a.k, b.k));
 }
 template <int NL>
 __device__ inline Key<NL> e_select(bool c, const Key<NL>& x, const Key<NL>& y) { return key_select<NL>(c, x, y); }
@@ -354,6 +366,13 @@ __device__ inline void e_set_sentinel(Key<NL>& v) { v = key_sentinel<NL>(); }
 template <int NL>
 __device__ inline void e_set_sentinel(TKey<NL>& v) {
   v.k = key_sentinel<NL>();
+  v.tag = ~0u;
+}
+template <int NL>
+__device__ inline void e_set_fill(Key<NL>& v) { v = key_fill<NL>(); }
+template <int NL>
+__device__ inline void e_set_fill(TKey<NL>& v) {
+  v.k = key_fill<NL>();
   v.tag = ~0u;
 }
 template <class K>

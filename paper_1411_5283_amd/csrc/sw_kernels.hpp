@@ -819,11 +819,12 @@ __device__ inline void padded_register_merge(const Tile& t, int la, int lb, int 
 // chunks of C, then (unless only the chunks are wanted) the merge of the
 // sorted chunks -- inside a thread's registers while runs are shorter than E,
 // then merge-path rounds through LDS until one run covers the tile's cnt real
-// items (the rest of the tile is sentinels, already in place).
+// items (the rest of the tile is the fill, key_fill, already in place: above
+// every real key, below the sentinel).
 // In the round that merges runs of R, item i sits in slot i + i/R: every run
 // is followed by a sentinel slot, so the serial merge reads one slot per
-// output without a bounds test (its positions only stop at the run's
-// sentinel).  The tile must hold T + T/E slots.
+// output without a bounds test (its positions only reach a run's sentinel
+// once the run is used up).  The tile must hold T + T/E slots.
 template <int NT, int E, int MM, class Tile>
 __device__ inline void sort_tile_core(Tile& tile, typename Tile::value_type (&e)[E], uint32_t C, uint32_t cnt,
                                       bool merge = true) {
@@ -848,17 +849,20 @@ __device__ inline void sort_tile_core(Tile& tile, typename Tile::value_type (&e)
     const int sa = p0 + (p0 >> lr), sb = sa + (int)R + 1;
     const int a = lds_merge_path(tile, sa, (int)R, sb, (int)R, d);
     if (MM == 0) {
-      // after a run's last item its position stays on the run's sentinel
+      // Every item of a run (the fill included) lies strictly below the
+      // sentinel slot that ends it, so a run at its sentinel is taken only
+      // when the other is at its own, i.e. after all 2R outputs: a position
+      // advances only from a run's item and never passes the sentinel slot.
       int pa = sa + a, pb = sb + (d - a);
-      const int ea = sa + (int)R, eb = sb + (int)R;
       K ha = tile.get(pa), hb = tile.get(pb);
 #pragma unroll
       for (int j = 0; j < E; ++j) {
         const bool takeB = e_less(hb, ha);
         e[j] = e_select(takeB, hb, ha);
-        pa = takeB ? pa : min(pa + 1, ea);
-        pb = takeB ? min(pb + 1, eb) : pb;
-        const K nv = tile.get(takeB ? pb : pa);
+        const int nxt = (takeB ? pb : pa) + 1;   // the taken run's next slot
+        pa = takeB ? pa : nxt;
+        pb = takeB ? nxt : pb;
+        const K nv = tile.get(nxt);
         ha = e_select(takeB, ha, nv);
         hb = e_select(takeB, nv, hb);
       }
@@ -964,7 +968,7 @@ __global__ __launch_bounds__(NT) void k_sort_tiles(Ws w, int cls, TileWork tw) {
 #pragma unroll
     for (int r = 0; r < E; ++r) {
       const uint32_t i = threadIdx.x + r * NT;
-      tile.put(i, i < cnt ? gload<NL>(w.a, gb + i) : key_sentinel<NL>());
+      tile.put(i, i < cnt ? gload<NL>(w.a, gb + i) : key_fill<NL>());
     }
     __syncthreads();
     Key<NL> e[E];
@@ -1060,7 +1064,7 @@ __global__ __launch_bounds__(kPackTile / E) void k_sort_packed(Ws w, int cls) {
           e[r].k = gload<NL>(w.a, (size_t)s_base[tg] + (p - s_start[tg]));
           e[r].tag = tg;
         } else {
-          e_set_sentinel(e[r]);
+          e_set_fill(e[r]);
         }
       }
       sort_tile_core<NT, E, MM>(tile, e, C, cnt);

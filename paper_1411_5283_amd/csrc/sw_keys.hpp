@@ -30,11 +30,14 @@ struct Key<0> {
   uint64_t k;
 };
 
+// Lexicographic: lane 0 first, then the index.  Written with bitwise
+// and/or of the comparisons so that on the GPU they combine as wave masks
+// (scalar instructions), not as selects of 0/1 values.
 template <int NL>
 __host__ __device__ inline bool key_less(const Key<NL>& a, const Key<NL>& b) {
   bool lt = a.idx < b.idx;
 #pragma unroll
-  for (int q = NL - 1; q >= 0; --q) lt = (a.k[q] == b.k[q]) ? lt : (a.k[q] < b.k[q]);
+  for (int q = NL - 1; q >= 0; --q) lt = (a.k[q] < b.k[q]) | ((a.k[q] == b.k[q]) & lt);
   return lt;
 }
 template <>
@@ -54,6 +57,24 @@ template <>
 __host__ __device__ inline Key<0> key_sentinel<0>() {
   Key<0> s;
   s.k = ~0ull;
+  return s;
+}
+
+// The fill of a tile's slots past its last real item: one below the
+// sentinel, so above every real key (a real index is below 2^32 - 1) or, at
+// most, equal to one, which the stable chunk sort and merges then keep ahead
+// of the fill.  The LDS merge rounds rely on every item of a run lying
+// strictly below the sentinel slot that ends it.
+template <int NL>
+__host__ __device__ inline Key<NL> key_fill() {
+  Key<NL> s = key_sentinel<NL>();
+  s.idx = ~0u - 1u;
+  return s;
+}
+template <>
+__host__ __device__ inline Key<0> key_fill<0>() {
+  Key<0> s;
+  s.k = ~0ull - 1ull;
   return s;
 }
 

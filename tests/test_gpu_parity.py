@@ -172,6 +172,10 @@ def _edge_lists():
         "already_sorted": sorted([bytes(rng.integers(97, 123, 6, dtype=np.uint8)) for _ in range(9000)]),
         "all_lengths": [bytes(rng.integers(0, 256, L, dtype=np.uint8)) for L in rng.integers(0, 33, 20000)],
         "unsigned_bytes": [bytes([b]) * L for b in (0, 1, 127, 128, 254, 255) for L in (1, 4, 5, 8, 9, 16, 17, 32)] * 50,
+        # words of 0xFF bytes only: the largest keys of every class, in
+        # ragged tiles whose slots past the last word hold the fill key just
+        # below the sentinel
+        "all_ones_ragged": [b"\xff" * L for L in range(33) for _ in range(777)],
         "lane_edges": [bytes(rng.integers(97, 100, L, dtype=np.uint8)) for L in (8, 9, 16, 17, 24, 25, 32) for _ in range(1500)],
         # every word of a length shares all bytes but the last: the order is
         # decided in the class's last lane (lengths 16/17 and 24/25 sit on the
