@@ -241,9 +241,14 @@ __device__ inline void gstore_nt<0>(const KeyBuf& b, size_t p, const Key<0>& v) 
 // such neighbour (63, resp. 0) keeps its own value.
 constexpr int kDppNext = 0x130;   // wavefront shift left by one lane
 constexpr int kDppPrev = 0x138;   // wavefront shift right by one lane
+// Quad permutes (controls below 0x100) write every lane, so they need no
+// old value kept (no copy before the move).
 template <int CTRL>
 __device__ inline uint32_t dpp32(uint32_t v) {
-  return (uint32_t)__builtin_amdgcn_update_dpp((int)v, (int)v, CTRL, 0xF, 0xF, false);
+  if constexpr (CTRL < 0x100)
+    return (uint32_t)__builtin_amdgcn_mov_dpp((int)v, CTRL, 0xF, 0xF, false);
+  else
+    return (uint32_t)__builtin_amdgcn_update_dpp((int)v, (int)v, CTRL, 0xF, 0xF, false);
 }
 template <int CTRL>
 __device__ inline uint64_t dpp64(uint64_t v) {

@@ -814,6 +814,49 @@ __device__ inline void padded_register_merge(const Tile& t, int la, int lb, int 
     run_bitonic_merge(LinRun<Tile>{t, 0}, la, LinRun<Tile>{t, la + 1}, lb, ai, bi, out);
 }
 
+// One merge round in registers for runs of M*E items held by M neighbouring
+// lanes each (blocked: lane l holds items l*E .. l*E+E-1 of the pair), the
+// pair of runs in 2M aligned lanes: Batcher's bitonic merge.  Item i of the
+// first run meets item 2ME-1-i of the second (the mirror lane, the item
+// reversed), the lower half keeping the smaller; then half-cleaners at lane
+// distance M/2 .. 1 (same item index, the lower lane keeping the smaller)
+// and at item distance E/2 .. 1 inside each lane.  Afterwards the 2M lanes
+// hold the merged run in blocked order.  M is 1 or 2 (quad permutes); every
+// lane of the wave takes part.
+template <int M, class K, int E>
+__device__ inline void lane_merge_round(K (&e)[E]) {
+  static_assert(M == 1 || M == 2, "pairs of runs inside a quad");
+  constexpr int kMirror = M == 1 ? 0xB1 : 0x1B;   // quad_perm: lane ^ 1, lane ^ 3
+  constexpr int kSwap1 = 0xB1;
+  const uint32_t lane = __lane_id();
+  {
+    // items r and E-1-r together: both partner values are read before
+    // either is replaced (the partner lane runs the same instructions)
+    const bool upper = (lane & M) != 0;
+#pragma unroll
+    for (int r = 0; r < E / 2; ++r) {
+      const K a = e_dpp<kMirror>(e[E - 1 - r]);
+      const K b = e_dpp<kMirror>(e[r]);
+      e[r] = e_select(e_less(a, e[r]) != upper, a, e[r]);
+      e[E - 1 - r] = e_select(e_less(b, e[E - 1 - r]) != upper, b, e[E - 1 - r]);
+    }
+  }
+  if (M == 2) {
+    const bool upper = (lane & 1) != 0;
+#pragma unroll
+    for (int r = 0; r < E; ++r) {
+      const K q = e_dpp<kSwap1>(e[r]);
+      e[r] = e_select(e_less(q, e[r]) != upper, q, e[r]);
+    }
+  }
+#pragma unroll
+  for (int st = E / 2; st >= 1; st >>= 1) {
+#pragma unroll
+    for (int i = 0; i < E; ++i)
+      if ((i & st) == 0) e_cmp_xchg(e[i], e[i + st]);
+  }
+}
+
 // Sorting core of a tile held as E items per thread in registers (blocked:
 // thread t holds items t*E..t*E+E-1 of the tile): odd-even transposition on
 // chunks of C, then (unless only the chunks are wanted) the merge of the
@@ -835,7 +878,20 @@ __device__ inline void sort_tile_core(Tile& tile, typename Tile::value_type (&e)
   // runs of C inside a thread are merged there by the same transposition on
   // all E items (the merge strategy is free: the result is unique)
   if (C < (uint32_t)E) oddeven_chunks<NT>(e, (uint32_t)E);
-  for (uint32_t R = C < (uint32_t)E ? (uint32_t)E : C; R < (uint32_t)T && R < cnt; R <<= 1) {
+  uint32_t R0 = C < (uint32_t)E ? (uint32_t)E : C;
+  // with at most 8 items a thread, the first two rounds, whose pairs of runs
+  // lie in two and four neighbouring lanes, in registers (no LDS round trip,
+  // no barrier); with 16, a register round costs about what an LDS round
+  // does
+  if (E <= 8 && R0 == (uint32_t)E && R0 < (uint32_t)T && R0 < cnt) {
+    lane_merge_round<1>(e);
+    R0 <<= 1;
+    if (R0 < (uint32_t)T && R0 < cnt) {
+      lane_merge_round<2>(e);
+      R0 <<= 1;
+    }
+  }
+  for (uint32_t R = R0; R < (uint32_t)T && R < cnt; R <<= 1) {
     const int lr = __ffs((int)R) - 1;   // R is a power of two, at least E
     const int o = threadIdx.x * E;
     const int g = o + (o >> lr);        // a thread's E items lie inside one run
