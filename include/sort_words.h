@@ -23,7 +23,8 @@
  * Conventions shared by every entry point
  *   - Word i is chars[offsets[i] .. offsets[i+1]).  `offsets` has n+1 entries,
  *     must not decrease, and offsets[0] need not be 0.  Total characters must
- *     be below 2^32.  Any byte value is allowed.
+ *     be below 2^32, and n at most 2^32 - 2 (a workspace for more words is
+ *     refused).  Any byte value is allowed.
  *   - Lengths 0..SW_MAX_LEN are accepted.  A longer word is an error
  *     (SW_ERR_WORD_TOO_LONG); offsets that decrease are SW_ERR_INVALID_ARG,
  *     which takes precedence.  On any error the outputs are unspecified.

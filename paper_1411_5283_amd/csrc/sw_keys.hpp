@@ -61,10 +61,9 @@ __host__ __device__ inline Key<0> key_sentinel<0>() {
 }
 
 // The fill of a tile's slots past its last real item: one below the
-// sentinel, so above every real key (a real index is below 2^32 - 1) or, at
-// most, equal to one, which the stable chunk sort and merges then keep ahead
-// of the fill.  The LDS merge rounds rely on every item of a run lying
-// strictly below the sentinel slot that ends it.
+// sentinel, so above every real key (a workspace holds at most 2^32 - 2
+// words, so a real index is at most 2^32 - 3).  The LDS merge rounds rely on
+// every item of a run lying strictly below the sentinel slot that ends it.
 template <int NL>
 __host__ __device__ inline Key<NL> key_fill() {
   Key<NL> s = key_sentinel<NL>();

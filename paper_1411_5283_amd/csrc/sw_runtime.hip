@@ -214,7 +214,9 @@ struct Layout {
 
 bool make_layout(uint64_t Nmax, uint64_t Dmax, Layout& L) {
   if (Dmax == 0) Dmax = 1;
-  if (Nmax > 0xFFFFFFFFull || Dmax > 0xFFFFFFFFull / sw::kNB) return false;
+  // at most 2^32 - 2 words: every index then lies below the chunk sort's fill
+  // key (index 2^32 - 2) and its sentinel (2^32 - 1)
+  if (Nmax > 0xFFFFFFFEull || Dmax > 0xFFFFFFFFull / sw::kNB) return false;
   L.Nmax = Nmax;
   L.Dmax = Dmax;
   L.Bmax = (Nmax + sw::kWordsPerBlock - 1) / sw::kWordsPerBlock + Dmax;

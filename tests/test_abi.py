@@ -46,6 +46,8 @@ def test_host_side_calls_without_gpu():
     c = sw.sort_words_workspace_size(100000, 4096)
     assert 0 < a < b < c
     assert sw.sort_words_workspace_size(1000, 0xFFFFFFFF) == 0
+    # at most 2^32 - 2 words (every index below the chunk sort's fill key)
+    assert sw.sort_words_workspace_size(0xFFFFFFFF, 1) == 0
     # argument validation happens on the host before any device call
     assert L.sort_words(None, None, 5, None, None) == sw.ERR_INVALID_ARG
     assert L.sort_words_ex(None, None, 0, None, None, None, 0, None) == sw.ERR_INVALID_ARG
