@@ -21,8 +21,8 @@
  *     and the sorted chunks are merged.
  *
  * Readings where the paper is silent (each is listed in the design notes):
- *   - "alphabetic" is unsigned byte order (memcmp);
- *   - the exchange condition is strictly "greater than", so equal words are
+ *   - alphabetic order is unsigned byte order (memcmp);
+ *   - the exchange condition is strictly greater-than, so equal words are
  *     never exchanged and keep their input order (bubble sort is stable);
  *   - word length is the byte count offsets[i+1]-offsets[i]; lengths 0..32 are
  *     accepted, a longer word is an error;
@@ -124,7 +124,7 @@ static void bubble_sort_words(const uint8_t *chars, const uint32_t *offsets,
 }
 
 /* The sequential method: phase 2 then phase 3, then the lists concatenated in
- * length order ("all shorter words come before longer words"). */
+ * length order (every shorter word ahead of every longer one, §3). */
 int oracle_bubble(const uint8_t *chars, const uint32_t *offsets, uint32_t n,
                   uint32_t *perm, uint32_t *bucket_offsets)
 {
