@@ -1,8 +1,9 @@
 """Full-size parity in the launch configuration the benchmark times
 (graph-captured plan, autotuned config).
 
-* 64M words: the oracle cannot sort this, so the whole output is checked
-  against invariants that hold at any size (permutation, strict key order,
+* 64M words: the whole permutation against the oracle's definition applied
+  to every length list (the lists on host threads, a few seconds), besides
+  the invariants that hold at any size (permutation, strict key order,
   bucket sizes equal the length histogram) and sampled positions against
   the oracle's definitional rank of a word (perm[rank(i)] == i).
 * 4096 documents (about 31M words): every document against the oracle.
@@ -71,7 +72,7 @@ def gpu():
 
 
 @pytest.mark.timeout(1200)
-def test_config4_full_invariants_and_sampled_ranks(gpu, oracle_mod):
+def test_config4_full_against_oracle(gpu, oracle_mod):
     print("case config4 full 64M words", flush=True)
     wl = wordgen.config(4)
     perm, boff, (text, ref) = _plan_sort(gpu, wl, "c4", text=True)
@@ -79,6 +80,12 @@ def test_config4_full_invariants_and_sampled_ranks(gpu, oracle_mod):
     counts = oracle_mod.oracle_length_counts(wl.offsets)
     assert np.array_equal(np.diff(boff.astype(np.int64)), counts.astype(np.int64))
     check_invariants(wl.chars, wl.offsets, perm, boff)
+    # the whole permutation against the oracle (its definition on every
+    # length list, the lists on host threads): element by element
+    eperm, eboff = oracle_mod.oracle_def_parallel(wl.chars, wl.offsets)
+    assert np.array_equal(boff, eboff)
+    bad = np.nonzero(perm != eperm)[0]
+    assert bad.size == 0, "differs from the oracle at %d of %d positions" % (bad.size, wl.n)
     assert np.array_equal(text, ref), "text from the keys differs from the text from the permutation"
     # the invariants make perm the one sorted order; the oracle's writer lays
     # its words out on the host: the whole text, byte for byte
