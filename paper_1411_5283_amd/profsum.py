@@ -5,6 +5,7 @@
         <copy_write.csv> <bench.json> <out.json> [<text_fetch.csv> <text_write.csv>] [--outdir <dir>]
     python -m paper_1411_5283_amd.profsum valu <workload> <pmc_a.csv>,<pmc_b.csv> <bench.json> <out.json> \
         [--outdir <dir>]
+    python -m paper_1411_5283_amd.profsum timeline <kernel_trace.csv> "<command>" <out.txt> [<step>]
 
 --outdir names the folder the counter runs wrote to (it appears in the
 commands each summary records); --extra "<args>" adds bench arguments to
@@ -18,6 +19,13 @@ bytes per launch.  The sort's kernels come from a run without the text steps
 (a run that writes text also keeps the sorted keys in the last merge level,
 which changes that level's traffic); the text kernels, found only in the
 second pair, from a run with them.
+
+``timeline`` splits a ``rocprofv3 --kernel-trace`` record into passes (each
+begins with ``k_begin``) and lists, for one pass (``<step>``, an index into
+the passes, default -5: a timed plan replay before the eager profiling step
+and the checks of a ``--steps 3 --profile-steps 1`` run), each kernel
+family's first start, last end, busy time, launches and hardware queues,
+relative to the pass's start.
 
 ``valu`` averages the SQ counters of two runs (VALU and LDS instructions
 issued, the cycles waves spent in them, lane-cycles, LDS bank conflicts,
@@ -77,6 +85,38 @@ def stats(src: str, cmd: str, out: str) -> None:
                                                        float(r["AverageNs"]), float(r["Percentage"])))
     with open(out, "w") as f:
         f.write("\n".join(lines) + "\n")
+
+
+def timeline(src: str, cmd: str, out: str, step: int = -5) -> None:
+    rows = sorted(csv.DictReader(open(src)), key=lambda r: int(r["Start_Timestamp"]))
+    passes, cur = [], None
+    for r in rows:
+        if re.match(r"(?:void )?sw::k_begin\b", r["Kernel_Name"]):
+            cur = []
+            passes.append(cur)
+        if cur is not None:
+            cur.append(r)
+    ps = passes[step]
+    t0 = int(ps[0]["Start_Timestamp"])
+    fams = collections.OrderedDict()
+    for r in ps:
+        f = _family(r["Kernel_Name"].split("(")[0]) or r["Kernel_Name"][:24]
+        a, b = (int(r["Start_Timestamp"]) - t0) / 1e3, (int(r["End_Timestamp"]) - t0) / 1e3
+        g = fams.setdefault(f, [a, b, 0.0, 0, set()])
+        g[0], g[1] = min(g[0], a), max(g[1], b)
+        g[2] += b - a
+        g[3] += 1
+        g[4].add(r["Queue_Id"])
+    span = (max(int(r["End_Timestamp"]) for r in ps) - t0) / 1e3
+    lines = ["# rocprofv3 kernel trace: one pass of the plan, kernel families in order of first start", "#",
+             "# command (run from the repository root on one MI355X):", "#   " + cmd, "#",
+             "# pass %d of %d (%d kernels, %.1f us from the first start to the last end, under the profiler)"
+             % (step % len(passes), len(passes), len(ps), span), "#",
+             "# %-18s %10s %10s %10s %6s  %s" % ("family", "first_us", "last_us", "busy_us", "calls", "queues")]
+    for f, g in fams.items():
+        lines.append("  %-18s %10.1f %10.1f %10.1f %6d  %s" % (f, g[0], g[1], g[2], g[3], ",".join(sorted(g[4]))))
+    with open(out, "w") as fh:
+        fh.write("\n".join(lines) + "\n")
 
 
 def _family(kernel: str) -> str | None:
@@ -187,5 +227,7 @@ if __name__ == "__main__":
         traffic(*argv[1:10], **kw)
     elif argv[0] == "valu":
         valu(*argv[1:5], **kw)
+    elif argv[0] == "timeline":
+        timeline(argv[1], argv[2], argv[3], *([int(argv[4])] if len(argv) > 4 else []))
     else:
         raise SystemExit(__doc__)
