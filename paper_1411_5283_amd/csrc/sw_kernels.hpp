@@ -879,10 +879,11 @@ __device__ inline void sort_tile_core(Tile& tile, typename Tile::value_type (&e)
   // all E items (the merge strategy is free: the result is unique)
   if (C < (uint32_t)E) oddeven_chunks<NT>(e, (uint32_t)E);
   uint32_t R0 = C < (uint32_t)E ? (uint32_t)E : C;
-  // with at most 8 items a thread, the rounds whose pairs of runs lie in two
-  // and four neighbouring lanes in registers (no LDS round trip, no
-  // barrier); with 16, a register round costs about what an LDS round does
-  if (E <= 8 && R0 == (uint32_t)E && R0 < (uint32_t)T && R0 < cnt) {
+  // the rounds whose pairs of runs lie in two neighbouring lanes (up to 16
+  // items a thread) and in four (up to 8) in registers: no LDS round trip,
+  // no barrier; with 16 items the four-lane round costs about what an LDS
+  // round does
+  if (E <= 16 && R0 == (uint32_t)E && R0 < (uint32_t)T && R0 < cnt) {
     lane_merge_round<1>(e);
     R0 <<= 1;
   }
